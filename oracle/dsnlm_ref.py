@@ -1,0 +1,297 @@
+"""FP64 oracle for the doubly stochastic NLM denoiser (DSG-NLM).
+
+TEST INFRASTRUCTURE ONLY -- imported by tests/, the smoke check and the bench's
+CPU-baseline leg; never by the HIP library.
+
+What is computed (Section 3 of the paper):
+
+* patches P_s of side N_p = 2P+1 centred at each pixel s (eq. NLM); pixels of
+  a patch that fall outside the image take the half-sample symmetric mirror of
+  the guide (index -1 -> 0, n -> n-1; the paper is silent, reading R4);
+* kernel k_{s,r} = exp(-||P_s - P_r||^2 / (2 N_p^2 h^2)) for r in the search
+  window Omega_s = {r in the image : ||r - s||_inf <= S}; the window is cut at
+  the image border and includes r = s (eq. NLM; readings R1, R3, R6);
+* step S1: w = Lambda_{s,r} k_{s,r}, Lambda the separable hat with argument
+  (s - r)/(S + 1);
+* step S2: w <- w (row sum_s)^(-1/2) (column sum_r)^(-1/2);
+* step S3: with m the largest row sum after S2, w <- w/m and then the diagonal
+  w_ss <- 1 + w_ss - sum_r w_sr (the sum includes the diagonal, reading R9);
+* output W x.  Algorithm 2 computes the same product with three aggregation
+  loops over (pixel, window) pairs without storing W.
+
+Three independent routes are provided:
+
+dense_weights / dsnlm_dense -- build the n x n matrices of eqs. S1-S3 literally
+                               (tiny images only);
+dsnlm_alg2                  -- Algorithm 2's three loops in plain Python (tiny);
+dsnlm_shifts                -- Algorithm 2's three loops with the pixel loop
+                               vectorised (torch CPU float64, differentiable),
+                               the window loop kept as a Python loop over the
+                               (2S+1)^2 shifts, patch distances summed directly
+                               over the N_p^2 patch offsets (brute force, no
+                               box-sum trick).  This is the route used for GPU
+                               parity and for the CPU baseline.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+__all__ = [
+    "sym_index",
+    "pad_symmetric",
+    "hat",
+    "dense_weights",
+    "dsnlm_dense",
+    "dsnlm_alg2",
+    "dsnlm_shifts",
+    "check_args",
+]
+
+
+def check_args(n1: int, n2: int, S: int, P: int, h: float) -> None:
+    """Input domain: S >= 0, P >= 0, P < min(n1, n2) (one mirror reflection
+    suffices), h finite and > 0."""
+    if n1 < 1 or n2 < 1:
+        raise ValueError("empty image")
+    if S < 0 or P < 0:
+        raise ValueError("S and P must be >= 0")
+    if P >= min(n1, n2):
+        raise ValueError("P must be < min(n1, n2)")
+    if not (math.isfinite(float(h)) and float(h) > 0):
+        raise ValueError("h must be finite and > 0")
+
+
+def sym_index(n: int, P: int) -> np.ndarray:
+    """Indices into [0, n) for padded positions -P .. n+P-1 under the
+    half-sample symmetric mirror (-1 -> 0, -2 -> 1, n -> n-1)."""
+    k = np.arange(-P, n + P)
+    k = np.where(k < 0, -k - 1, k)
+    k = np.where(k >= n, 2 * n - 1 - k, k)
+    return k
+
+
+def pad_symmetric(z: np.ndarray, P: int) -> np.ndarray:
+    """Mirror-pad by P on every side (numpy's 'symmetric' mode)."""
+    return np.pad(np.asarray(z, dtype=np.float64), P, mode="symmetric")
+
+
+def hat(d: int, S: int) -> float:
+    """One factor of the separable hat Lambda of step S1 at offset d."""
+    return 1.0 - abs(d) / (S + 1.0)
+
+
+# ---------------------------------------------------------------------------
+# Route 1: the matrices of eqs. S1-S3, built densely.
+# ---------------------------------------------------------------------------
+def dense_weights(z, S: int, P: int, h: float) -> dict:
+    """Return the intermediate and final matrices of steps S1-S3 for guide z.
+
+    Keys: K (kernel, zero outside the windows), Lam (hat), W1 (after S1),
+    W2 (after S2), W (after S3), omega (row sums of W1), delta (row sums of
+    W2), m (max of delta).  Pixel s = (i, j) has index i*n2 + j.
+    """
+    z = np.asarray(z, dtype=np.float64)
+    n1, n2 = z.shape
+    check_args(n1, n2, S, P, h)
+    Np = 2 * P + 1
+    zp = pad_symmetric(z, P)
+    n = n1 * n2
+    patches = np.empty((n, Np * Np))
+    for i in range(n1):
+        for j in range(n2):
+            patches[i * n2 + j] = zp[i:i + Np, j:j + Np].ravel()
+    ii = np.repeat(np.arange(n1), n2)
+    jj = np.tile(np.arange(n2), n1)
+    di = ii[:, None] - ii[None, :]
+    dj = jj[:, None] - jj[None, :]
+    inwin = (np.abs(di) <= S) & (np.abs(dj) <= S)
+    rows, cols = np.nonzero(inwin)
+    dist = np.zeros((n, n))
+    dist[rows, cols] = ((patches[rows] - patches[cols]) ** 2).sum(1)
+    K = np.where(inwin, np.exp(-dist / (2.0 * Np * Np * h * h)), 0.0)
+    Lam = np.where(inwin, (1.0 - np.abs(di) / (S + 1.0)) * (1.0 - np.abs(dj) / (S + 1.0)), 0.0)
+    W1 = Lam * K
+    rowsum = W1.sum(1)
+    colsum = W1.sum(0)
+    W2 = W1 * rowsum[:, None] ** -0.5 * colsum[None, :] ** -0.5
+    delta = W2.sum(1)
+    m = delta.max()
+    W = W2 / m
+    full = W.sum(1)
+    W[np.arange(n), np.arange(n)] = 1.0 + np.diag(W) - full
+    return dict(K=K, Lam=Lam, W1=W1, W2=W2, W=W, omega=rowsum, delta=delta, m=m)
+
+
+def dsnlm_dense(x, z, S: int, P: int, h: float) -> np.ndarray:
+    """y = W(z) x via the dense matrix of step S3 (tiny images only)."""
+    x = np.asarray(x, dtype=np.float64)
+    W = dense_weights(z, S, P, h)["W"]
+    return (W @ x.ravel()).reshape(x.shape)
+
+
+# ---------------------------------------------------------------------------
+# Route 2: Algorithm 2 in plain Python loops.
+# ---------------------------------------------------------------------------
+def _refl(k: int, n: int) -> int:
+    """Half-sample symmetric reflection of index k into [0, n) (|k| < 2n)."""
+    if k < 0:
+        return -k - 1
+    if k >= n:
+        return 2 * n - 1 - k
+    return k
+
+
+def _kernel_py(zl, n1, n2, i, j, r, q, P, h):
+    """k_{s,r} of eq. NLM for s = (i, j), r = (r, q), patches read from the
+    guide through the mirror reflection (written independently of np.pad)."""
+    Np = 2 * P + 1
+    d = 0.0
+    for ty in range(-P, P + 1):
+        for tx in range(-P, P + 1):
+            e = (zl[_refl(i + ty, n1)][_refl(j + tx, n2)]
+                 - zl[_refl(r + ty, n1)][_refl(q + tx, n2)])
+            d += e * e
+    return math.exp(-d / (2.0 * Np * Np * h * h))
+
+
+def dsnlm_alg2(x, z, S: int, P: int, h: float) -> np.ndarray:
+    """Algorithm 2 with its three aggregation loops written out (tiny images).
+
+    Loop 1 accumulates the image g of row sums of Lambda*k; loop 2 accumulates
+    (g_s g_r)^(-1/2) Lambda k per pixel and keeps the maximum m; loop 3 forms
+    w = m^-1 (g_s g_r)^(-1/2) Lambda k, accumulates w x_r and w, and finally adds
+    (1 - sum w) x_s.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    n1, n2 = z.shape
+    check_args(n1, n2, S, P, h)
+    zl = z.tolist()
+    xl = x.tolist()
+
+    def window(i, j):
+        for r in range(max(0, i - S), min(n1, i + S + 1)):
+            for q in range(max(0, j - S), min(n2, j + S + 1)):
+                yield r, q
+
+    def lam(i, j, r, q):
+        return hat(i - r, S) * hat(j - q, S)
+
+    g = [[0.0] * n2 for _ in range(n1)]
+    for i in range(n1):
+        for j in range(n2):
+            for r, q in window(i, j):
+                g[i][j] += lam(i, j, r, q) * _kernel_py(zl, n1, n2, i, j, r, q, P, h)
+    m = 0.0
+    for i in range(n1):
+        for j in range(n2):
+            delta = 0.0
+            for r, q in window(i, j):
+                delta += (g[i][j] * g[r][q]) ** -0.5 * lam(i, j, r, q) * _kernel_py(zl, n1, n2, i, j, r, q, P, h)
+            m = max(m, delta)
+    y = [[0.0] * n2 for _ in range(n1)]
+    for i in range(n1):
+        for j in range(n2):
+            acc = 0.0
+            hs = 0.0
+            for r, q in window(i, j):
+                w = (g[i][j] * g[r][q]) ** -0.5 * lam(i, j, r, q) * _kernel_py(zl, n1, n2, i, j, r, q, P, h) / m
+                acc += w * xl[r][q]
+                hs += w
+            y[i][j] = acc + (1.0 - hs) * xl[i][j]
+    return np.asarray(y)
+
+
+# ---------------------------------------------------------------------------
+# Route 3: Algorithm 2 vectorised over pixels, loop over shifts (torch, FP64).
+# ---------------------------------------------------------------------------
+def _as_t(a) -> torch.Tensor:
+    if isinstance(a, torch.Tensor):
+        return a.to(torch.float64)
+    return torch.as_tensor(np.asarray(a, dtype=np.float64))
+
+
+def _shift_ranges(n: int, d: int):
+    """Pixels s with s + d inside [0, n): the half-open range [lo, hi)."""
+    return max(0, -d), min(n, n - d)
+
+
+def dsnlm_shifts(x, z, S: int, P: int, h, want: str = "y") -> dict:
+    """DSG-NLM by Algorithm 2's three passes, pixels vectorised (torch FP64).
+
+    x, z: 2-D arrays or tensors (cast to float64; autograd flows through them
+    and through h when they are tensors that require grad).
+    Returns a dict with y (= W x), omega (loop-1 image g), delta (loop-2 row
+    sums), m (their maximum), argmax (flat index of the first maximal delta,
+    which is where the derivative of the max is routed, reading R10).
+    """
+    xt = _as_t(x)
+    zt = _as_t(z)
+    ht = h if isinstance(h, torch.Tensor) else torch.tensor(float(h), dtype=torch.float64)
+    n1, n2 = zt.shape
+    check_args(n1, n2, S, P, float(ht.detach()))
+    Np = 2 * P + 1
+    ri = torch.as_tensor(sym_index(n1, P))
+    ci = torch.as_tensor(sym_index(n2, P))
+    zp = zt[ri][:, ci]
+    kappa = 1.0 / (2.0 * Np * Np * ht * ht)
+
+    def weight(dy, dx):
+        """Lambda_d * k_{s, s+d} on the pixels s with s + d in the image."""
+        i0, i1 = _shift_ranges(n1, dy)
+        j0, j1 = _shift_ranges(n2, dx)
+        if i0 >= i1 or j0 >= j1:
+            return None
+        D = torch.zeros((i1 - i0, j1 - j0), dtype=torch.float64)
+        for ty in range(Np):
+            for tx in range(Np):
+                a = zp[i0 + ty:i1 + ty, j0 + tx:j1 + tx]
+                b = zp[i0 + dy + ty:i1 + dy + ty, j0 + dx + tx:j1 + dx + tx]
+                D = D + (a - b) ** 2
+        lam = hat(dy, S) * hat(dx, S)
+        return (i0, i1, j0, j1), lam * torch.exp(-kappa * D)
+
+    shifts = [(dy, dx) for dy in range(-S, S + 1) for dx in range(-S, S + 1)]
+
+    # loop 1: g_s = sum_r Lambda k
+    omega = torch.zeros((n1, n2), dtype=torch.float64)
+    for dy, dx in shifts:
+        wres = weight(dy, dx)
+        if wres is None:
+            continue
+        (i0, i1, j0, j1), a = wres
+        omega[i0:i1, j0:j1] += a
+    # loop 2: delta_s = sum_r (g_s g_r)^-1/2 Lambda k
+    delta = torch.zeros((n1, n2), dtype=torch.float64)
+    for dy, dx in shifts:
+        wres = weight(dy, dx)
+        if wres is None:
+            continue
+        (i0, i1, j0, j1), a = wres
+        gs = omega[i0:i1, j0:j1]
+        gr = omega[i0 + dy:i1 + dy, j0 + dx:j1 + dx]
+        delta[i0:i1, j0:j1] += (gs * gr) ** -0.5 * a
+    flat = delta.reshape(-1)
+    am = int(torch.argmax(flat.detach()))
+    m = flat[am]
+    out = dict(omega=omega, delta=delta, m=m, argmax=am)
+    if want == "weights":
+        return out
+    # loop 3: y_s = sum_r w x_r + (1 - sum_r w) x_s, w = m^-1 (g_s g_r)^-1/2 Lambda k
+    acc = torch.zeros((n1, n2), dtype=torch.float64)
+    hs = torch.zeros((n1, n2), dtype=torch.float64)
+    for dy, dx in shifts:
+        wres = weight(dy, dx)
+        if wres is None:
+            continue
+        (i0, i1, j0, j1), a = wres
+        gs = omega[i0:i1, j0:j1]
+        gr = omega[i0 + dy:i1 + dy, j0 + dx:j1 + dx]
+        w = (gs * gr) ** -0.5 * a / m
+        acc[i0:i1, j0:j1] += w * xt[i0 + dy:i1 + dy, j0 + dx:j1 + dx]
+        hs[i0:i1, j0:j1] += w
+    out["y"] = acc + (1.0 - hs) * xt
+    return out

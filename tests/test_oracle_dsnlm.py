@@ -1,0 +1,169 @@
+"""CPU pins for the FP64 DSG-NLM oracle (no GPU).
+
+Each test checks the oracle against something other than itself: a second
+independent coding of the same definition, the properties the cited theorem
+fixes (Section 3: W symmetric, doubly stochastic, eigenvalues in [0, 1]),
+closed forms for special guides, or library constructions.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import synth
+from oracle import dsnlm_ref as R
+
+SHAPES = [
+    # (n1, n2, S, P): tiny shapes incl. S >= size, P >= S, one-row images
+    (7, 6, 2, 1),
+    (6, 7, 3, 2),
+    (5, 5, 1, 3),
+    (4, 4, 6, 1),
+    (1, 6, 2, 0),
+    (6, 1, 3, 0),
+    (3, 8, 0, 1),
+]
+
+
+def _img(n1, n2, seed):
+    _, noisy = synth.piecewise_smooth(n1, n2, seed, 0.05)
+    return noisy
+
+
+@pytest.mark.parametrize("n1,n2,S,P", SHAPES)
+def test_three_routes_agree(n1, n2, S, P):
+    """Dense matrices of S1-S3, Algorithm 2 loops and the shift loop agree."""
+    z = _img(n1, n2, 11)
+    x = _img(n1, n2, 12)
+    h = 0.08
+    yd = R.dsnlm_dense(x, z, S, P, h)
+    ya = R.dsnlm_alg2(x, z, S, P, h)
+    ys = R.dsnlm_shifts(x, z, S, P, h)["y"].numpy()
+    assert np.abs(yd - ya).max() <= 1e-13
+    assert np.abs(yd - ys).max() <= 1e-13
+    dw = R.dense_weights(z, S, P, h)
+    sh = R.dsnlm_shifts(x, z, S, P, h, want="weights")
+    assert np.abs(dw["omega"] - sh["omega"].numpy().ravel()).max() <= 1e-12
+    assert np.abs(dw["delta"] - sh["delta"].numpy().ravel()).max() <= 1e-13
+    assert abs(dw["m"] - float(sh["m"])) <= 1e-13
+
+
+@pytest.mark.parametrize("n1,n2,S,P,h", [(7, 6, 2, 1, 0.1), (8, 8, 3, 1, 0.05), (6, 9, 4, 2, 0.3)])
+def test_theorem_properties(n1, n2, S, P, h):
+    """W symmetric, nonnegative, rows/columns sum to 1, spectrum in (0, 1]
+    with the constant vector as top eigenvector."""
+    z = _img(n1, n2, 21)
+    W = R.dense_weights(z, S, P, h)["W"]
+    n = n1 * n2
+    assert np.abs(W - W.T).max() <= 1e-15
+    assert W.min() >= 0.0
+    assert np.abs(W.sum(0) - 1).max() <= 1e-12
+    assert np.abs(W.sum(1) - 1).max() <= 1e-12
+    ev, V = np.linalg.eigh(W)
+    assert ev[0] > 0.0
+    assert ev[-1] <= 1 + 1e-12 and abs(ev[-1] - 1) <= 1e-12
+    top = V[:, -1] * np.sign(V[0, -1])
+    assert np.abs(top - 1 / math.sqrt(n)).max() <= 1e-8
+
+
+def test_invariants_medium():
+    """Constants are fixed points for any guide; the image mean is preserved;
+    the output stays within [min x, max x]."""
+    z = _img(24, 19, 31)
+    x = _img(24, 19, 32)
+    S, P, h = 4, 2, 0.07
+    y = R.dsnlm_shifts(x, z, S, P, h)["y"].numpy()
+    c = R.dsnlm_shifts(np.full(x.shape, 0.37), z, S, P, h)["y"].numpy()
+    assert np.abs(c - 0.37).max() <= 1e-15
+    assert abs(y.sum() - x.astype(np.float64).sum()) <= 1e-11
+    assert y.min() >= x.min() - 1e-14 and y.max() <= x.max() + 1e-14
+
+
+def test_vanishing_bandwidth_is_identity():
+    """h -> 0 with all patches distinct: every off-diagonal weight underflows,
+    W = I and y equals x bit for bit."""
+    rng = np.random.default_rng(5)
+    z = rng.uniform(0, 1, size=(9, 10)).astype(np.float32)
+    x = rng.uniform(0, 1, size=(9, 10)).astype(np.float32)
+    out = R.dsnlm_shifts(x, z, 3, 1, 1e-6)
+    assert np.array_equal(out["y"].numpy(), x.astype(np.float64))
+    assert float(out["m"]) == 1.0
+
+
+def test_constant_guide_closed_form_max():
+    """Constant guide, S = 1: the weights are the hat alone, separable across
+    axes, and the largest row sum after S2 is (3/4 + 1/(2 sqrt 3))^2
+    (attained one pixel in from a corner, for n1, n2 >= 4)."""
+    for n1, n2 in [(4, 4), (6, 5), (9, 12)]:
+        z = np.full((n1, n2), 0.3)
+        dw = R.dense_weights(z, 1, 1, 0.1)
+        expect = (0.75 + 1.0 / (2.0 * math.sqrt(3.0))) ** 2
+        assert abs(dw["m"] - expect) <= 1e-15
+        sh = R.dsnlm_shifts(z, z, 1, 1, 0.1, want="weights")
+        assert abs(float(sh["m"]) - expect) <= 1e-15
+
+
+@pytest.mark.parametrize("S", [1, 2, 3])
+def test_constant_guide_kron_toeplitz(S):
+    """Constant guide: W1 is the Kronecker product of two 1-D Toeplitz hat
+    matrices (row-major pixel order), and interior row sums equal (S+1)^2."""
+    n1, n2 = 9, 11
+    z = np.full((n1, n2), 0.6)
+    dw = R.dense_weights(z, S, 1, 0.2)
+
+    def toep(n):
+        col = np.array([max(0.0, 1 - k / (S + 1.0)) if k <= S else 0.0 for k in range(n)])
+        return scipy.linalg.toeplitz(col)
+
+    assert np.abs(dw["W1"] - np.kron(toep(n1), toep(n2))).max() <= 1e-15
+    om = dw["omega"].reshape(n1, n2)
+    assert np.abs(om[S:n1 - S, S:n2 - S] - (S + 1) ** 2).max() <= 1e-12
+
+
+@pytest.mark.parametrize("P", [0, 1, 2])
+def test_kernel_normalisation_on_stripes(P):
+    """Guide with rows alternating 0/1: every interior patch differs from the
+    one a row below in all N_p^2 pixels by exactly 1, so D = N_p^2 and the
+    kernel is exp(-1/(2h^2)) whatever the patch size (pins the N_p^2 h^2
+    normalisation of eq. NLM)."""
+    n1, n2, S, h = 12, 10, 2, 0.7
+    z = np.tile((np.arange(n1) % 2)[:, None], (1, n2)).astype(np.float64)
+    dw = R.dense_weights(z, S, P, h)
+    lam = (1 - 1 / (S + 1.0))
+    for i in range(P + 1, n1 - P - 2):
+        for j in range(P, n2 - P):
+            s = i * n2 + j
+            r = (i + 1) * n2 + j
+            assert abs(dw["W1"][s, r] - lam * math.exp(-1 / (2 * h * h))) <= 1e-15
+            r2 = (i + 2) * n2 + j if i + 2 < n1 - P else None
+            if r2 is not None:
+                assert abs(dw["W1"][s, r2] - (1 - 2 / (S + 1.0))) <= 1e-15
+
+
+def test_scale_invariance():
+    """W(c z, c h) = W(z, h): the kernel depends on D/h^2 only."""
+    z = _img(8, 7, 41)
+    a = R.dense_weights(z, 2, 1, 0.1)["W"]
+    b = R.dense_weights(3.0 * z.astype(np.float64), 2, 1, 0.3)["W"]
+    assert np.abs(a - b).max() <= 1e-13
+
+
+def test_mirror_index_matches_numpy_symmetric_pad():
+    for n, P in [(5, 0), (5, 3), (7, 6), (1, 0)]:
+        a = np.arange(n, dtype=np.float64)
+        assert np.array_equal(a[R.sym_index(n, P)], np.pad(a, P, mode="symmetric"))
+
+
+def test_argument_domain():
+    z = np.zeros((4, 4))
+    with pytest.raises(ValueError):
+        R.check_args(4, 4, 1, 4, 0.1)
+    with pytest.raises(ValueError):
+        R.check_args(4, 4, -1, 1, 0.1)
+    with pytest.raises(ValueError):
+        R.check_args(4, 4, 1, 1, 0.0)
+    with pytest.raises(ValueError):
+        R.check_args(4, 4, 1, 1, float("nan"))
+    with pytest.raises(ValueError):
+        R.dsnlm_shifts(z, z, 1, 1, -1.0)

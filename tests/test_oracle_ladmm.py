@@ -1,0 +1,159 @@
+"""CPU pins for the FP64 forward-model and LADMM oracle (no GPU)."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import dsnlm_ref as R
+from oracle import ladmm_ref as L
+
+TAPS = L.gaussian_taps(9, 1.0)
+
+
+@pytest.mark.parametrize("boundary", ["symmetric", "periodic"])
+@pytest.mark.parametrize("shape", [(32, 32), (18, 22), (17, 13)])
+def test_adjoint_dot_product(boundary, shape):
+    """<A x, r> = <x, A^T r> (the adjoint folds the padded margins back)."""
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(shape)
+    lr = L.sr_forward(x, TAPS, 2, boundary).shape
+    r = rng.standard_normal(lr)
+    lhs = np.vdot(L.sr_forward(x, TAPS, 2, boundary), r)
+    rhs = np.vdot(x, L.sr_adjoint(r, TAPS, 2, shape, boundary))
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs))
+
+
+def test_periodic_norm_closed_form():
+    """Periodic blur + decimation by 2: A A^T is diagonalised by the DFT and
+    its largest eigenvalue is 1/4 (1 + beta^2)^2 with beta = sum_k b_k (-1)^k
+    (the four aliases of the zero frequency)."""
+    beta = float((TAPS * (-1.0) ** np.arange(9)).sum())
+    expect = 0.25 * (1 + beta * beta) ** 2
+    A = L.sr_dense((32, 32), TAPS, 2, "periodic")
+    assert abs(np.linalg.norm(A, 2) ** 2 - expect) <= 1e-12
+    pw = L.power_norm2(lambda v: L.sr_adjoint(L.sr_forward(v, TAPS, 2, "periodic"), TAPS, 2,
+                                              (32, 32), "periodic"), (32, 32), iters=400)
+    assert abs(pw - expect) <= 1e-9
+
+
+def test_symmetric_norm_power_iteration_vs_svd():
+    A = L.sr_dense((24, 24), TAPS, 2, "symmetric")
+    svd = np.linalg.norm(A, 2) ** 2
+    pw = L.power_norm2(lambda v: (A.T @ (A @ v.ravel())).reshape(24, 24), (24, 24), iters=600)
+    assert abs(pw - svd) <= 1e-10
+    # a larger grid reaches the same value (the extremal mode lives in the
+    # interior plus mirrored margins)
+    A32 = L.sr_dense((32, 32), TAPS, 2, "symmetric")
+    assert abs(np.linalg.norm(A32, 2) ** 2 - svd) <= 1e-8
+
+
+@pytest.mark.parametrize("boundary", ["symmetric", "periodic"])
+def test_blur_preserves_constants_and_phase(boundary):
+    """Normalised taps keep constants; a symmetric blur keeps a linear ramp in
+    the interior, and the kept samples are the even ones (phase 0)."""
+    n = 24
+    one = np.ones((n, n))
+    assert np.abs(L.sr_forward(one, TAPS, 2, boundary) - 1).max() <= 1e-14
+    ramp = np.add.outer(0.3 * np.arange(n), 0.1 * np.arange(n))
+    y = L.sr_forward(ramp, TAPS, 2, boundary)
+    inner = slice(2, n // 2 - 2)
+    expect = ramp[::2, ::2]
+    assert np.abs(y[inner, inner] - expect[inner, inner]).max() <= 1e-12
+
+
+def test_sr_gradient_central_fd():
+    rng = np.random.default_rng(2)
+    x = rng.uniform(0, 1, (12, 12))
+    y = rng.uniform(0, 1, (6, 6))
+
+    def f(v):
+        r = L.sr_forward(v, TAPS, 2) - y
+        return 0.5 * float((r * r).sum())
+
+    g = L.sr_adjoint(L.sr_forward(x, TAPS, 2) - y, TAPS, 2, x.shape)
+    for k in [0, 5, 13, 77, 143]:
+        e = np.zeros(x.size)
+        e[k] = 1e-4
+        fd = (f(x + e.reshape(x.shape)) - f(x - e.reshape(x.shape))) / 2e-4
+        assert abs(fd - g.ravel()[k]) <= 1e-9
+
+
+def test_spi_gradient_and_ml_point():
+    K, eta = 16, 4.0
+    ones = np.arange(0, K + 1, dtype=np.uint8)
+    t = np.linspace(0.05, 1.5, ones.size)
+    g = L.spi_grad(t, ones, K, eta)
+    step = 1e-6
+    fd = (L.spi_phi(t + step, ones, K, eta) - L.spi_phi(t - step, ones, K, eta)) / (2 * step)
+    assert np.abs(g - fd).max() <= 1e-6
+    inner = (ones > 0) & (ones < K)
+    xs = L.spi_ml(ones[inner], K, eta)
+    assert np.abs(L.spi_grad(xs, ones[inner], K, eta)).max() <= 1e-12
+
+
+def test_spi_counts_statistics():
+    """The empirical rate of ones matches the detection probability."""
+    K, eta = 16, 4.0
+    clean, uni = synth.config4_batch(count=1, n=64, K=K)[0]
+    ones = L.spi_counts(clean, uni, eta)
+    p = -np.expm1(-eta * clean.astype(np.float64) / K)
+    emp = ones.astype(np.float64).mean() / K
+    assert abs(emp - p.mean()) <= 3 * math.sqrt(p.mean() / (K * ones.size))
+
+
+def _fixed_point_setup(n=16, S=3, P=1, h=0.1):
+    clean, _ = synth.piecewise_smooth(n, n, 7, 0.0)
+    A = L.sr_dense((n, n), TAPS, 2, "symmetric")
+    rng = np.random.default_rng(3)
+    y = A @ clean.ravel().astype(np.float64) + 0.01 * rng.standard_normal(A.shape[0])
+    guide = clean.astype(np.float64) + 0.05 * rng.standard_normal((n, n))
+    W = R.dense_weights(guide, S, P, h)["W"]
+    return A, y, guide, W
+
+
+def test_fixed_weights_fixed_point_matches_linear_solve():
+    """With frozen weights W and an inactive box, Algorithm 1 converges to the
+    solution of (W A^T A + rho (I - W)) x = W A^T y: the minimiser of
+    1/2 ||Ax - y||^2 + rho/2 x^T (W^-1 - I) x, whose v-step is v = W z."""
+    n, rho = 16, 1.0
+    A, y, guide, W = _fixed_point_setup(n)
+    xs = np.linalg.solve(W @ A.T @ A + rho * (np.eye(n * n) - W), W @ A.T @ y)
+    alpha = np.linalg.norm(A, 2) ** 2
+    out = L.ladmm(np.full((n, n), 0.5), lambda v: (A.T @ (A @ v.ravel() - y)).reshape(n, n),
+                  alpha=alpha, rho=rho, S=3, P=1, h=0.1, iters=1500, freeze_after=1,
+                  lo=-10.0, hi=10.0, fixed_guide=guide,
+                  denoise=lambda z, g: (W @ z.ravel()).reshape(n, n))
+    assert np.abs(out["x"].ravel() - xs).max() <= 1e-10
+    assert np.abs(out["x"] - out["v"]).max() <= 1e-10
+
+
+def test_fixed_weights_box_constrained_minimum():
+    """With the box [0, 1] active, Algorithm 1 reaches the minimum of
+    F(x) = 1/2||Ax - y||^2 + rho/2 x^T (W^-1 - I) x over the box found by
+    brute-force accelerated projected gradient, and F decreases to it."""
+    n, rho = 16, 1.0
+    A, y, guide, W = _fixed_point_setup(n)
+    Winv = np.linalg.inv(W)
+    Q = A.T @ A + rho * (Winv - np.eye(n * n))
+    b = A.T @ y
+    F = lambda x: 0.5 * float(np.sum((A @ x - y) ** 2)) + 0.5 * rho * float(x @ (Winv - np.eye(n * n)) @ x)
+    Lq = np.linalg.eigvalsh(Q)[-1]
+    xk = np.full(n * n, 0.5)
+    zk, tk = xk.copy(), 1.0
+    for _ in range(20000):
+        xn = np.clip(zk - (Q @ zk - b) / Lq, 0, 1)
+        tn = 0.5 * (1 + math.sqrt(1 + 4 * tk * tk))
+        zk = xn + (tk - 1) / tn * (xn - xk)
+        xk, tk = xn, tn
+    assert xk.max() == 1.0  # the box is active at the minimiser
+    alpha = np.linalg.norm(A, 2) ** 2
+    rec = []
+    out = L.ladmm(np.full((n, n), 0.5), lambda v: (A.T @ (A @ v.ravel() - y)).reshape(n, n),
+                  alpha=alpha, rho=rho, S=3, P=1, h=0.1, iters=3000, freeze_after=1,
+                  fixed_guide=guide, record=rec,
+                  denoise=lambda z, g: (W @ z.ravel()).reshape(n, n))
+    assert np.abs(out["x"].ravel() - xk).max() <= 1e-8
+    assert abs(F(out["x"].ravel()) - F(xk)) <= 1e-10
+    f_hist = [F(r[0].ravel()) for r in rec[::100]]
+    assert f_hist[-1] <= f_hist[1] and f_hist[-1] - F(xk) <= 1e-10
