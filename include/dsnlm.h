@@ -1,0 +1,231 @@
+/*
+ * dsnlm.h -- C ABI of the MI355X (gfx950) library for the doubly stochastic
+ * NLM denoiser (DSG-NLM) and linearized plug-and-play ADMM.
+ *
+ * Paper: Unni, Ghosh, Chaudhury, "Linearized ADMM and Fast Nonlocal Denoising
+ * for Efficient Plug-and-Play Restoration" (arXiv 1901.06110).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Images are single-channel FP32, row-major, contiguous, n1 rows by n2
+ * columns, in DEVICE memory owned by the caller (for example torch tensors'
+ * data pointers).  No call copies between host and device unless it says so.
+ * `stream` is a hipStream_t (NULL = the default stream); all work is enqueued
+ * on it and calls return without synchronising, except the few documented as
+ * synchronous.  Only the opaque `dsnlm_weights` handle is owned by the
+ * library (created by a build call, released by dsnlm_weights_destroy).
+ *
+ * Every call returns a dsnlm_status.  Arguments are validated on the host
+ * before anything is launched; a rejected call returns DSNLM_EINVAL and leaves
+ * all outputs untouched.  A failure reported by the HIP runtime is returned
+ * as DSNLM_EDEVICE.  dsnlm_last_error() returns a per-thread message for the
+ * last non-OK status.  No C++ exception crosses this interface.
+ *
+ * Denoiser parameters (Section 3, eq. NLM and steps S1-S3):
+ *   S  search half-width: the window of pixel s holds the pixels r of the
+ *      image with max(|r1-s1|, |r2-s2|) <= S (the window is cut at the image
+ *      border and includes s itself);
+ *   P  patch half-width: patches are (2P+1) x (2P+1); patch pixels outside
+ *      the image take the half-sample symmetric mirror of the guide
+ *      (index -1 -> 0, n -> n-1), which needs P < min(n1, n2);
+ *   h  bandwidth: k_{s,r} = exp(-||P_s - P_r||^2 / (2 (2P+1)^2 h^2));
+ *      must be finite and > 0.
+ *   Supported: 0 <= S <= 24, 0 <= P <= 5.
+ * The weights are Lambda_{s,r} k_{s,r} with the separable hat
+ * Lambda = (1 - |r1-s1|/(S+1)) (1 - |r2-s2|/(S+1)) (step S1), normalised
+ * symmetrically by the row sums (step S2) and scaled by the largest
+ * resulting row sum m with the diagonal completed to row sum one (step S3).
+ * W is symmetric and doubly stochastic.  W is never stored: a handle keeps
+ * the guide, the per-pixel factors c_s = (row sum of step S1)^(-1/2), the
+ * step-S2 row sums delta_s, and m with the first pixel attaining it.
+ */
+#ifndef DSNLM_H
+#define DSNLM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DSNLM_OK = 0,
+    DSNLM_EINVAL = -1,      /* bad argument; nothing was launched            */
+    DSNLM_ENOMEM = -2,      /* device allocation failed                      */
+    DSNLM_EDEVICE = -3,     /* the HIP runtime reported an error             */
+    DSNLM_ENONFINITE = -4,  /* a solver produced a non-finite residual       */
+    DSNLM_EUNSUPPORTED = -5 /* valid per the paper but outside this build    */
+} dsnlm_status;
+
+typedef struct dsnlm_weights dsnlm_weights;
+
+/* Build the weights of W(guide) (Algorithm 2, first and second aggregation:
+ * row sums of step S1, then the step-S2 row sums and their maximum m).
+ * guide: device, n1*n2 floats.  If *out is NULL a new handle is created;
+ * if *out is an existing handle of the same n1, n2 it is rebuilt in place
+ * (no allocation).  The handle copies the guide, so the caller may reuse the
+ * guide buffer once the stream has passed this call. */
+int dsnlm_build_weights(const float* guide, int n1, int n2, int S, int P, float h,
+                        void* stream, dsnlm_weights** out);
+
+/* y = W x for built weights (Algorithm 2, third aggregation, computed as
+ * y_s = x_s + (1/m) c_s sum_r Lambda k c_r (x_r - x_s), which equals the
+ * loop's sum of w x_r plus (1 - sum w) x_s).  x, y: device, n1*n2 floats;
+ * y must not overlap x.  The handle records the intermediate needed by
+ * dsnlm_apply_backward for this x. */
+int dsnlm_apply(const dsnlm_weights* w, const float* x, float* y, void* stream);
+
+/* Build and apply in one go: y = W(guide) x, two sweeps over the window
+ * instead of three.  out: NULL, or as in dsnlm_build_weights (the handle then
+ * holds everything dsnlm_apply_backward needs).  guide may equal x. */
+int dsnlm_forward(const float* guide, const float* x, float* y, int n1, int n2,
+                  int S, int P, float h, void* stream, dsnlm_weights** out);
+
+/* Vector-Jacobian product of y = W(guide, h) x at the x of the last apply or
+ * forward on this handle (x must be passed again, unchanged).
+ * dy: cotangent of y.  Outputs (each may be NULL to skip it):
+ *   dx     = W dy (W is symmetric), n1*n2 floats;
+ *   dguide = gradient with respect to the guide, n1*n2 floats;
+ *   dh     = gradient with respect to h, one float on the device.
+ * The derivative of the maximum m is routed to the first pixel attaining it.
+ * Outputs are overwritten, not accumulated.  Not defined in the paper: the
+ * chain rule through eq. NLM and steps S1-S3. */
+int dsnlm_apply_backward(const dsnlm_weights* w, const float* x, const float* dy,
+                         float* dx, float* dguide, float* dh, void* stream);
+
+void dsnlm_weights_destroy(dsnlm_weights* w);
+
+/* Copy the handle's scalars to the host (synchronises the stream):
+ * m (largest step-S2 row sum) and the flat index of the first pixel
+ * attaining it.  Either pointer may be NULL. */
+int dsnlm_weights_scalars(const dsnlm_weights* w, float* m, int* argmax, void* stream);
+
+/* Device pointers to the handle's per-pixel arrays (valid until destroy):
+ * which = 0: c (row sums of step S1 to the power -1/2), 1: delta (row sums
+ * after step S2), 2: the guide copy.  Returns NULL for a bad argument. */
+const float* dsnlm_weights_array(const dsnlm_weights* w, int which);
+
+/* ----------------------------------------------------------------------- */
+/* Many images of uneven sizes denoised together: one launch per sweep for  */
+/* the whole batch, each image with its own m (spec batching form).   */
+typedef struct {
+    const float* guide; /* device, n1*n2 */
+    const float* x;     /* device, n1*n2 (may equal guide) */
+    float* y;           /* device, n1*n2, must not overlap x */
+    int n1, n2;
+    float h;            /* per-image bandwidth, > 0 */
+} dsnlm_image;
+
+/* imgs: HOST array of `count` descriptors (count = 0 is a no-op).  The
+ * per-image intermediates live in a grow-only device workspace owned by the
+ * library and reused by later calls; the descriptor list is uploaded only
+ * when it changes.  Calls on different streams must not overlap in time
+ * (they share the workspace). */
+int dsnlm_forward_batched(const dsnlm_image* imgs, int count, int S, int P, void* stream);
+
+/* ----------------------------------------------------------------------- */
+/* Linearized plug-and-play ADMM (Section 2, Algorithm 1).                   */
+/* Problem: min_x f(x) + lambda g(x), x in C = [lo, hi]^n.  f is defined by  */
+/* the forward operator below; g is implicit in the DSG-NLM denoiser, whose  */
+/* bandwidth is sigma = sqrt(lambda / rho) unless h > 0 overrides it.       */
+typedef enum { LADMM_OP_SR = 1, LADMM_OP_SPI = 2 } ladmm_op_kind;
+
+typedef struct {
+    ladmm_op_kind kind;
+    int n1, n2;               /* high-resolution image size */
+    /* Super-resolution (Section 4.1, eq. dataterm): f = 1/2 ||A x - y||^2,
+     * A = keep every `factor`-th sample (phase 0) of the blur of x by the
+     * separable kernel taps (x) taps; blur pixels outside the image take the
+     * half-sample symmetric mirror (boundary = 0) or wrap (boundary = 1).
+     * taps: HOST array of blur_size floats (odd size <= 31, normalised by the
+     * caller); y: device, ceil(n1/factor) x ceil(n2/factor) floats. */
+    const float* taps;
+    int blur_size;
+    int factor;               /* 1..8 */
+    int boundary;             /* 0 symmetric, 1 periodic */
+    const float* y;
+    /* Single-photon imaging (Section 4.2, eqs. obj and photongrad): per pixel
+     * K1 = ones[i] of K binary measurements are 1; f = sum phi(x_i) with
+     * phi(t) = (K-K1) eta t / K - K1 log(1 - exp(-eta t/K)), evaluated at
+     * max(t, t_min).  ones: device, n1*n2 bytes. */
+    const unsigned char* ones;
+    int K;
+    float eta;
+    float t_min;
+} ladmm_operator;
+
+typedef struct {
+    float lambda, rho;        /* Algorithm 1's lambda and rho (> 0) */
+    float gamma;              /* 1/alpha: alpha = 1/gamma must exceed the
+                                 Lipschitz constant of grad f for the
+                                 convergence result of Section 2 */
+    int S, P;                 /* denoiser window and patch half-widths */
+    float h;                  /* > 0: bandwidth; <= 0: sqrt(lambda / rho) */
+    int iters;                /* iterations for ladmm_solve */
+    int freeze_after;         /* k0 >= 1: weights rebuilt from the denoiser's
+                                 input x + u while k <= k0, then frozen */
+    float lo, hi;             /* box C = [lo, hi]^n (lo < hi) */
+} ladmm_params;
+
+/* One iteration k (1-based) of Algorithm 1 in place on x, v, u (device,
+ * n1*n2 each): x <- Pi_C(mu (alpha x + rho (v - u) - grad f(x))),
+ * v <- W (x + u) with W rebuilt from x + u when k <= freeze_after (into *w,
+ * created if NULL) and reused otherwise, u <- u + x - v. */
+int ladmm_step(const ladmm_operator* op, const ladmm_params* p, int k, dsnlm_weights** w,
+               float* x, float* v, float* u, void* stream);
+
+/* Run p->iters iterations from (x, v, u) (device, in place).  residuals:
+ * NULL or device [iters][2]: RMS of x - v and of rho (v_k - v_{k-1}) per
+ * iteration.  checkpoints: NULL or device [iters][4][n1*n2]: x, v, u and the
+ * denoiser input x + u after each iteration.  The iterations after the
+ * weights freeze are captured once in a HIP graph and replayed.
+ * Returns DSNLM_ENONFINITE (after the run) if a residual is not finite;
+ * this check synchronises the stream when residuals is non-NULL. */
+int ladmm_solve(const ladmm_operator* op, const ladmm_params* p, float* x, float* v, float* u,
+                float* residuals, float* checkpoints, void* stream);
+
+/* out = A x (super-resolution operator only; out is the low-resolution
+ * grid) -- used to synthesise observations and by tests. */
+int ladmm_apply_forward(const ladmm_operator* op, const float* x, float* out, void* stream);
+
+/* g = grad f(x) for either operator (device, n1*n2). */
+int ladmm_gradient(const ladmm_operator* op, const float* x, float* g, void* stream);
+
+/* Largest eigenvalue of A^T A by `iters` power iterations from a fixed
+ * start (super-resolution only).  Synchronous; *out is a host float. */
+int ladmm_operator_norm2(const ladmm_operator* op, int iters, float* out, void* stream);
+
+const char* dsnlm_last_error(void);
+
+/* ----------------------------------------------------------------------- */
+/* Instrumentation.  While enabled, every kernel launch of the library is    */
+/* bracketed by HIP events recorded on its launch stream (not inside a graph */
+/* capture), so callers can read per-kernel device time without a profiler.  */
+typedef enum {
+    DSNLM_K_PASS_A = 0,     /* sweep: row sums of step S1 -> c              */
+    DSNLM_K_PASS_B = 1,     /* sweep: step-S2 row sums, B', max m           */
+    DSNLM_K_APPLY = 2,      /* sweep: B' with built weights                 */
+    DSNLM_K_EPILOGUE = 3,   /* y = x + B'/m                                 */
+    DSNLM_K_BWD_PREP = 4,   /* backward: reductions before the sweeps       */
+    DSNLM_K_PASS_C = 5,     /* backward sweep: input-gradient sums          */
+    DSNLM_K_PASS_D = 6,     /* backward sweep: guide and bandwidth sums     */
+    DSNLM_K_BWD_TAIL = 7,   /* backward: fold and final reductions          */
+    DSNLM_K_LADMM = 8,      /* forward-model, gradient and update kernels   */
+    DSNLM_K_COUNT = 9
+} dsnlm_kernel_kind;
+
+int dsnlm_profile_enable(int on);
+/* Total device milliseconds and number of launches of `kind` since the last
+ * reset (waits for the recorded events). */
+int dsnlm_profile_query(int kind, double* total_ms, int* launches);
+int dsnlm_profile_reset(void);
+
+/* Library version string. */
+const char* dsnlm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DSNLM_H */

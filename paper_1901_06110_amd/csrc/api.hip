@@ -1,0 +1,208 @@
+// Host side of the C ABI declared in include/dsnlm.h: argument validation,
+// handle lifetime, error strings, and the launch sequences of the denoiser.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "internal.h"
+
+namespace dsnlm {
+
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int check_hip(hipError_t e, const char* what) {
+    if (e == hipSuccess) return DSNLM_OK;
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? DSNLM_ENOMEM : DSNLM_EDEVICE;
+}
+
+// Validate the denoiser arguments shared by every build/apply entry point.
+int check_denoiser_args(int n1, int n2, int S, int P, float h, const char* who) {
+    std::string w(who);
+    if (n1 < 1 || n2 < 1) return fail(DSNLM_EINVAL, w + ": image must be at least 1x1");
+    if (S < 0 || P < 0) return fail(DSNLM_EINVAL, w + ": S and P must be >= 0");
+    if (P >= n1 || P >= n2) return fail(DSNLM_EINVAL, w + ": P must be < min(n1, n2)");
+    if (!std::isfinite(h) || !(h > 0.f)) return fail(DSNLM_EINVAL, w + ": h must be finite and > 0");
+    if (S > kMaxS || P > kMaxP)
+        return fail(DSNLM_EUNSUPPORTED, w + ": this build supports S <= 24 and P <= 5");
+    if ((long long)n1 * n2 > (1LL << 31) - 1)
+        return fail(DSNLM_EUNSUPPORTED, w + ": images above 2^31-1 pixels are not supported");
+    return DSNLM_OK;
+}
+
+bool overlaps(const void* a, const void* b, size_t bytes) {
+    const char* pa = static_cast<const char*>(a);
+    const char* pb = static_cast<const char*>(b);
+    return pa < pb + bytes && pb < pa + bytes;
+}
+
+ImgDesc base_desc(const dsnlm_weights* w) {
+    ImgDesc d{};
+    d.z = w->guide;
+    d.c = w->c;
+    d.delta = w->delta;
+    d.bp = w->bp;
+    d.key = w->key;
+    d.n1 = w->n1;
+    d.n2 = w->n2;
+    const double np = 2.0 * w->P + 1.0;
+    const double kappa = 1.0 / (2.0 * np * np * (double)w->h * (double)w->h);
+    d.kappa = (float)kappa;
+    d.beta = (float)(kappa * 1.4426950408889634);  // log2(e) * kappa
+    d.h = w->h;
+    return d;
+}
+
+// Create or re-use a handle for an n1 x n2 image.
+int prepare_handle(int n1, int n2, int S, int P, float h, dsnlm_weights** out) {
+    dsnlm_weights* w = *out;
+    if (w && (w->n1 != n1 || w->n2 != n2))
+        return fail(DSNLM_EINVAL, "handle was built for a different image size");
+    if (!w) {
+        w = new (std::nothrow) dsnlm_weights{};
+        if (!w) return fail(DSNLM_ENOMEM, "host allocation failed");
+        w->n1 = n1;
+        w->n2 = n2;
+        (void)hipGetDevice(&w->device);
+        const size_t n = (size_t)n1 * n2;
+        hipError_t e = hipMalloc(&w->guide, n * sizeof(float));
+        if (e == hipSuccess) e = hipMalloc(&w->c, n * sizeof(float));
+        if (e == hipSuccess) e = hipMalloc(&w->delta, n * sizeof(float));
+        if (e == hipSuccess) e = hipMalloc(&w->bp, n * sizeof(float));
+        if (e == hipSuccess) e = hipMalloc(&w->key, sizeof(unsigned long long));
+        if (e != hipSuccess) {
+            dsnlm_weights_destroy(w);
+            return check_hip(e, "hipMalloc");
+        }
+        *out = w;
+    }
+    w->S = S;
+    w->P = P;
+    w->h = h;
+    w->applied = false;
+    return DSNLM_OK;
+}
+
+}  // namespace dsnlm
+
+using namespace dsnlm;
+
+extern "C" {
+
+const char* dsnlm_last_error(void) { return g_err.c_str(); }
+
+const char* dsnlm_version(void) { return "dsnlm-gfx950 0.1"; }
+
+void dsnlm_weights_destroy(dsnlm_weights* w) {
+    if (!w) return;
+    (void)hipFree(w->guide);
+    (void)hipFree(w->c);
+    (void)hipFree(w->delta);
+    (void)hipFree(w->bp);
+    (void)hipFree(w->key);
+    delete w;
+}
+
+int dsnlm_build_weights(const float* guide, int n1, int n2, int S, int P, float h, void* stream,
+                        dsnlm_weights** out) {
+    if (!guide || !out) return fail(DSNLM_EINVAL, "dsnlm_build_weights: null pointer");
+    int rc = check_denoiser_args(n1, n2, S, P, h, "dsnlm_build_weights");
+    if (rc) return rc;
+    rc = prepare_handle(n1, n2, S, P, h, out);
+    if (rc) return rc;
+    dsnlm_weights* w = *out;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t bytes = (size_t)n1 * n2 * sizeof(float);
+    rc = check_hip(hipMemcpyAsync(w->guide, guide, bytes, hipMemcpyDeviceToDevice, st), "copy guide");
+    if (rc) return rc;
+    ImgDesc d = base_desc(w);
+    rc = check_hip(launch_sweep(kPassA, S, P, d, nullptr, nullptr, 0, st), "pass A");
+    if (rc) return rc;
+    return check_hip(launch_sweep(kPassBBuild, S, P, d, nullptr, nullptr, 0, st), "pass B");
+}
+
+int dsnlm_apply(const dsnlm_weights* wc, const float* x, float* y, void* stream) {
+    if (!wc || !x || !y) return fail(DSNLM_EINVAL, "dsnlm_apply: null pointer");
+    dsnlm_weights* w = const_cast<dsnlm_weights*>(wc);
+    const size_t bytes = (size_t)w->n1 * w->n2 * sizeof(float);
+    if (overlaps(x, y, bytes)) return fail(DSNLM_EINVAL, "dsnlm_apply: x and y overlap");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    ImgDesc d = base_desc(w);
+    d.x = x;
+    d.y = y;
+    int rc = check_hip(launch_sweep(kApply, w->S, w->P, d, nullptr, nullptr, 0, st), "apply sweep");
+    if (rc) return rc;
+    rc = check_hip(launch_epilogue(d, nullptr, nullptr, 0, w->S, w->P, st), "epilogue");
+    if (rc) return rc;
+    w->applied = true;
+    return DSNLM_OK;
+}
+
+int dsnlm_forward(const float* guide, const float* x, float* y, int n1, int n2, int S, int P,
+                  float h, void* stream, dsnlm_weights** out) {
+    if (!guide || !x || !y) return fail(DSNLM_EINVAL, "dsnlm_forward: null pointer");
+    int rc = check_denoiser_args(n1, n2, S, P, h, "dsnlm_forward");
+    if (rc) return rc;
+    const size_t bytes = (size_t)n1 * n2 * sizeof(float);
+    if (overlaps(x, y, bytes) || overlaps(guide, y, bytes))
+        return fail(DSNLM_EINVAL, "dsnlm_forward: y overlaps x or the guide");
+    dsnlm_weights* local = nullptr;
+    dsnlm_weights** hp = out ? out : &local;
+    rc = prepare_handle(n1, n2, S, P, h, hp);
+    if (rc) return rc;
+    dsnlm_weights* w = *hp;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    rc = check_hip(hipMemcpyAsync(w->guide, guide, bytes, hipMemcpyDeviceToDevice, st), "copy guide");
+    ImgDesc d = base_desc(w);
+    d.x = x;
+    d.y = y;
+    if (!rc) rc = check_hip(launch_sweep(kPassA, S, P, d, nullptr, nullptr, 0, st), "pass A");
+    if (!rc) rc = check_hip(launch_sweep(kPassBApply, S, P, d, nullptr, nullptr, 0, st), "pass B");
+    if (!rc) rc = check_hip(launch_epilogue(d, nullptr, nullptr, 0, S, P, st), "epilogue");
+    if (!rc) w->applied = true;
+    if (local) {
+        // the temporary handle's buffers must outlive the queued kernels
+        hipError_t e = hipStreamSynchronize(st);
+        dsnlm_weights_destroy(local);
+        if (!rc) rc = check_hip(e, "dsnlm_forward: synchronise");
+    }
+    return rc;
+}
+
+int dsnlm_weights_scalars(const dsnlm_weights* w, float* m, int* argmax, void* stream) {
+    if (!w) return fail(DSNLM_EINVAL, "dsnlm_weights_scalars: null handle");
+    unsigned long long key = 0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int rc = check_hip(hipMemcpyAsync(&key, w->key, sizeof(key), hipMemcpyDeviceToHost, st), "copy key");
+    if (!rc) rc = check_hip(hipStreamSynchronize(st), "synchronise");
+    if (rc) return rc;
+    unsigned bits = (unsigned)(key >> 32);
+    float mv;
+    std::memcpy(&mv, &bits, sizeof(mv));
+    if (m) *m = mv;
+    if (argmax) *argmax = (int)(~(unsigned)(key & 0xffffffffu));
+    return DSNLM_OK;
+}
+
+const float* dsnlm_weights_array(const dsnlm_weights* w, int which) {
+    if (!w) return nullptr;
+    switch (which) {
+        case 0: return w->c;
+        case 1: return w->delta;
+        case 2: return w->guide;
+        default: return nullptr;
+    }
+}
+
+}  // extern "C"

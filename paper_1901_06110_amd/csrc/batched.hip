@@ -1,0 +1,155 @@
+// Batched DSG-NLM forward over images of uneven sizes: one launch per sweep
+// for the whole batch.  Blocks index a flat tile list that spans every image,
+// so small and large images share the machine and each image keeps its own
+// maximum row sum m (one packed key per image).
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "internal.h"
+
+namespace dsnlm {
+
+int check_denoiser_args(int n1, int n2, int S, int P, float h, const char* who);
+bool overlaps(const void* a, const void* b, size_t bytes);
+
+namespace {
+
+// Grow-only device workspace reused across calls (per process).
+struct BatchWorkspace {
+    std::mutex mu;
+    float* arrays = nullptr;  // c, delta, B' for every image
+    size_t arrays_cap = 0;    // floats
+    unsigned long long* keys = nullptr;
+    size_t keys_cap = 0;
+    ImgDesc* descs = nullptr;
+    size_t descs_cap = 0;
+    TileRef* tiles = nullptr;
+    size_t tiles_cap = 0;
+    std::vector<ImgDesc> last_descs;
+    std::vector<TileRef> last_tiles;
+};
+
+BatchWorkspace g_ws;
+
+template <class T>
+hipError_t grow(T** p, size_t* cap, size_t need) {
+    if (need <= *cap) return hipSuccess;
+    if (*p) {
+        hipError_t e = hipFree(*p);
+        if (e != hipSuccess) return e;
+        *p = nullptr;
+    }
+    size_t n = need + need / 4 + 16;
+    hipError_t e = hipMalloc(p, n * sizeof(T));
+    if (e != hipSuccess) {
+        *cap = 0;
+        return e;
+    }
+    *cap = n;
+    return hipSuccess;
+}
+
+bool same_descs(const std::vector<ImgDesc>& a, const std::vector<ImgDesc>& b) {
+    return a.size() == b.size() &&
+           (a.empty() || std::memcmp(a.data(), b.data(), a.size() * sizeof(ImgDesc)) == 0);
+}
+
+bool same_tiles(const std::vector<TileRef>& a, const std::vector<TileRef>& b) {
+    return a.size() == b.size() &&
+           (a.empty() || std::memcmp(a.data(), b.data(), a.size() * sizeof(TileRef)) == 0);
+}
+
+}  // namespace
+
+}  // namespace dsnlm
+
+using namespace dsnlm;
+
+extern "C" int dsnlm_forward_batched(const dsnlm_image* imgs, int count, int S, int P, void* stream) {
+    if (count < 0) return fail(DSNLM_EINVAL, "dsnlm_forward_batched: negative count");
+    if (count == 0) return DSNLM_OK;
+    if (!imgs) return fail(DSNLM_EINVAL, "dsnlm_forward_batched: null descriptor array");
+    size_t total = 0;
+    for (int k = 0; k < count; ++k) {
+        const dsnlm_image& im = imgs[k];
+        if (!im.guide || !im.x || !im.y)
+            return fail(DSNLM_EINVAL, "dsnlm_forward_batched: null pointer in image " + std::to_string(k));
+        int rc = check_denoiser_args(im.n1, im.n2, S, P, im.h, "dsnlm_forward_batched");
+        if (rc) return rc;
+        const size_t bytes = (size_t)im.n1 * im.n2 * sizeof(float);
+        if (overlaps(im.x, im.y, bytes) || overlaps(im.guide, im.y, bytes))
+            return fail(DSNLM_EINVAL, "dsnlm_forward_batched: y overlaps x or the guide in image " +
+                                          std::to_string(k));
+        total += (size_t)im.n1 * im.n2;
+    }
+    const TileCfg cfg = sweep_tile_cfg(P, kPassA);
+    std::lock_guard<std::mutex> lk(g_ws.mu);
+    int rc = check_hip(grow(&g_ws.arrays, &g_ws.arrays_cap, 3 * total), "batch workspace");
+    if (!rc) rc = check_hip(grow(&g_ws.keys, &g_ws.keys_cap, (size_t)count), "batch keys");
+    if (!rc) rc = check_hip(grow(&g_ws.descs, &g_ws.descs_cap, (size_t)count), "batch descriptors");
+    if (rc) return rc;
+
+    std::vector<ImgDesc> descs(count);
+    std::vector<TileRef> tiles;
+    size_t off = 0;
+    const double log2e = 1.4426950408889634;
+    for (int k = 0; k < count; ++k) {
+        const dsnlm_image& im = imgs[k];
+        const size_t n = (size_t)im.n1 * im.n2;
+        ImgDesc d{};
+        d.z = im.guide;
+        d.x = im.x;
+        d.y = im.y;
+        d.c = g_ws.arrays + off;
+        d.delta = g_ws.arrays + total + off;
+        d.bp = g_ws.arrays + 2 * total + off;
+        d.key = g_ws.keys + k;
+        d.n1 = im.n1;
+        d.n2 = im.n2;
+        const double np = 2.0 * P + 1.0;
+        const double kappa = 1.0 / (2.0 * np * np * (double)im.h * (double)im.h);
+        d.kappa = (float)kappa;
+        d.beta = (float)(kappa * log2e);
+        d.h = im.h;
+        d.tile_base = (int)tiles.size();
+        descs[k] = d;
+        const int nty = (im.n1 + cfg.TH - 1) / cfg.TH, ntx = (im.n2 + cfg.TW - 1) / cfg.TW;
+        for (int ty = 0; ty < nty; ++ty)
+            for (int tx = 0; tx < ntx; ++tx)
+                tiles.push_back(TileRef{k, ty * cfg.TH, tx * cfg.TW, (ty == 0 && tx == 0) ? 1 : 0});
+        off += n;
+    }
+    rc = check_hip(grow(&g_ws.tiles, &g_ws.tiles_cap, tiles.size()), "batch tiles");
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // descriptors only change when the batch does; re-upload in stream order
+    // (the host copies kept in the workspace stay alive as copy sources)
+    if (!same_descs(descs, g_ws.last_descs)) {
+        g_ws.last_descs = descs;
+        rc = check_hip(hipMemcpyAsync(g_ws.descs, g_ws.last_descs.data(),
+                                      descs.size() * sizeof(ImgDesc), hipMemcpyHostToDevice, st),
+                       "upload descriptors");
+        if (rc) {
+            g_ws.last_descs.clear();
+            return rc;
+        }
+    }
+    if (!same_tiles(tiles, g_ws.last_tiles)) {
+        g_ws.last_tiles = tiles;
+        rc = check_hip(hipMemcpyAsync(g_ws.tiles, g_ws.last_tiles.data(),
+                                      tiles.size() * sizeof(TileRef), hipMemcpyHostToDevice, st),
+                       "upload tiles");
+        if (rc) {
+            g_ws.last_tiles.clear();
+            return rc;
+        }
+    }
+    const int nt = (int)tiles.size();
+    ImgDesc none{};
+    rc = check_hip(launch_sweep(kPassA, S, P, none, g_ws.descs, g_ws.tiles, nt, st), "batch pass A");
+    if (!rc) rc = check_hip(launch_sweep(kPassBApply, S, P, none, g_ws.descs, g_ws.tiles, nt, st), "batch pass B");
+    if (!rc) rc = check_hip(launch_epilogue(none, g_ws.descs, g_ws.tiles, nt, S, P, st), "batch epilogue");
+    return rc;
+}

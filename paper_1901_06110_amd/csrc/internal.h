@@ -1,0 +1,111 @@
+// Internal declarations of the DSG-NLM / LADMM HIP library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/dsnlm.h"
+
+namespace dsnlm {
+
+constexpr int kMaxS = 24;
+constexpr int kMaxP = 5;
+
+// log2 of one factor of the separable hat of step S1, for offsets -S..S.
+struct HatTable {
+    float lg[2 * kMaxS + 1];
+};
+HatTable make_hat(int S);
+
+// Per-image view used by the sweep kernels.  Unused pointers may be null.
+struct ImgDesc {
+    const float* z;        // guide (n1 x n2)
+    const float* x;        // image being filtered (n1 x n2)
+    float* y;              // output of the epilogue
+    float* c;              // c_s = omega_s^(-1/2)
+    float* delta;          // delta_s = c_s sum_r a c_r
+    float* bp;             // B'_s = c_s sum_r a c_r (x_r - x_s)
+    unsigned long long* key;  // packed (bits(m) << 32) | (~argmax)
+    // backward
+    const float* dy;       // cotangent of y
+    float* dx;             // W dy
+    float* cbar_aux;       // per-pixel arrays used by the backward sweeps
+    float* gz;             // gradient w.r.t. the padded guide ((n1+2P) x (n2+2P))
+    float* dz;             // gradient w.r.t. the guide
+    float* hpart;          // per-tile partial sums for dh
+    float* mbar;           // device scalar: derivative of the loss w.r.t. m
+    int n1, n2;
+    float beta;            // log2(e) / (2 (2P+1)^2 h^2)
+    float kappa;           // 1 / (2 (2P+1)^2 h^2)
+    float h;
+    int tile_base;         // first entry of this image in a batch tile list
+};
+
+// One tile of a batch: image index and tile origin.
+struct TileRef {
+    int img;
+    int ti0;
+    int tj0;
+    int flags;             // bit 0: first tile of its image
+};
+
+enum SweepMode : int {
+    kPassA = 0,        // row sums of step S1 -> c
+    kPassBApply = 1,   // delta, B' and the running max key (x known)
+    kPassBBuild = 2,   // delta and the key only
+    kApply = 3,        // B' only (weights already built)
+    kPassC = 4,        // backward: sum a t_r, sum a w_r
+};
+
+struct TileCfg {
+    int TH, TW, threads;
+};
+
+// Launchers (dsnlm_sweep.hip).
+TileCfg sweep_tile_cfg(int P, int mode);
+size_t sweep_lds_bytes(int S, int P, int mode);
+hipError_t launch_sweep(int mode, int S, int P, const ImgDesc& one, const ImgDesc* batch,
+                        const TileRef* tiles, int ntiles, hipStream_t st);
+hipError_t launch_epilogue(const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
+                           int ntiles, int S, int P, hipStream_t st);
+
+// Backward launchers (dsnlm_backward.hip).
+hipError_t launch_backward(const ImgDesc& d, int S, int P, hipStream_t st, void* scratch,
+                           size_t scratch_bytes);
+size_t backward_scratch_bytes(int n1, int n2, int S, int P);
+
+// Brackets one kernel launch with events when instrumentation is enabled.
+class ProfScope {
+  public:
+    ProfScope(int kind, hipStream_t st);
+    ~ProfScope();
+    ProfScope(const ProfScope&) = delete;
+    ProfScope& operator=(const ProfScope&) = delete;
+
+  private:
+    int kind_;
+    hipStream_t st_;
+    hipEvent_t ev_;
+};
+
+// Error state.
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int check_hip(hipError_t e, const char* what);
+
+}  // namespace dsnlm
+
+struct dsnlm_weights {
+    int n1, n2, S, P;
+    float h;
+    int device;
+    float* guide;      // copy of the guide
+    float* c;
+    float* delta;
+    float* bp;
+    unsigned long long* key;
+    float* xsave;      // not used by the kernels; kept null
+    bool applied;      // bp holds B' of the last apply
+};

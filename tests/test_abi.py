@@ -1,0 +1,69 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function declared in include/dsnlm.h, and rejects bad arguments with
+DSNLM_EINVAL before touching the device."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dsnlm.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z_0-9\s\*]*?\b([a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n.startswith(("dsnlm_", "ladmm_"))))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1901_06110_amd import _lib
+    return _lib.get()
+
+
+def test_header_lists_the_entry_points():
+    names = _declared_functions()
+    for must in ["dsnlm_build_weights", "dsnlm_apply", "dsnlm_apply_backward", "dsnlm_forward",
+                 "dsnlm_forward_batched", "ladmm_step", "ladmm_solve", "ladmm_operator_norm2"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_1901_06110_amd import _lib
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (\w+)$", out, flags=re.M))
+    missing = [n for n in _declared_functions() if n not in exported]
+    assert not missing, missing
+    assert set(_lib.EXPORTED) <= exported
+
+
+def test_invalid_arguments_rejected_on_host(lib):
+    hp = C.c_void_p()
+    fake = C.c_void_p(0x1000)
+    cases = [
+        lib.dsnlm_build_weights(None, 8, 8, 1, 1, 0.1, None, C.byref(hp)),
+        lib.dsnlm_build_weights(fake, 0, 8, 1, 1, 0.1, None, C.byref(hp)),
+        lib.dsnlm_build_weights(fake, 8, 8, -1, 1, 0.1, None, C.byref(hp)),
+        lib.dsnlm_build_weights(fake, 8, 8, 1, -1, 0.1, None, C.byref(hp)),
+        lib.dsnlm_build_weights(fake, 8, 8, 1, 8, 0.1, None, C.byref(hp)),
+        lib.dsnlm_build_weights(fake, 8, 8, 1, 1, 0.0, None, C.byref(hp)),
+        lib.dsnlm_build_weights(fake, 8, 8, 1, 1, float("nan"), None, C.byref(hp)),
+        lib.dsnlm_build_weights(fake, 8, 8, 1, 1, float("inf"), None, C.byref(hp)),
+        lib.dsnlm_forward(fake, fake, fake, 8, 8, 1, 1, 0.1, None, None),  # y aliases x
+        lib.dsnlm_apply(None, fake, fake, None),
+    ]
+    assert all(c == -1 for c in cases), cases
+    assert not hp.value
+    assert b"overlap" in lib.dsnlm_last_error() or len(lib.dsnlm_last_error()) > 0
+
+
+def test_unsupported_sizes_reported(lib):
+    hp = C.c_void_p()
+    fake = C.c_void_p(0x1000)
+    assert lib.dsnlm_build_weights(fake, 64, 64, 25, 1, 0.1, None, C.byref(hp)) == -5
+    assert lib.dsnlm_build_weights(fake, 64, 64, 3, 6, 0.1, None, C.byref(hp)) == -5
