@@ -221,6 +221,20 @@ int dsnlm_profile_enable(int on);
 int dsnlm_profile_query(int kind, double* total_ms, int* launches);
 int dsnlm_profile_reset(void);
 
+/* ----------------------------------------------------------------------- */
+/* Autotuning of the window sweeps.  Every sweep kind has several compiled   */
+/* schedules ("variants"); a table keyed by (kind, S <= 12 or not, P) picks  */
+/* the one launched.  kind: 0 = pass A, 1 = pass B (build and fused forward),*/
+/* 2 = apply with built weights, 3 = backward input-gradient sweep.          */
+/* If the environment variable DSNLM_TUNE_CACHE names a file, the table is   */
+/* read from it on first use and written back by dsnlm_tune.                 */
+int dsnlm_tune_set(int kind, int S, int P, int variant);
+int dsnlm_tune_get(int kind, int S, int P, int* variant);
+/* Time every variant of every kind on an n1 x n2 image (guide: device, the
+ * image used for timing), `reps` launches each, and keep the fastest.
+ * Synchronous. */
+int dsnlm_tune(const float* guide, int n1, int n2, int S, int P, float h, int reps, void* stream);
+
 /* Library version string. */
 const char* dsnlm_version(void);
 

@@ -111,6 +111,7 @@ void dsnlm_weights_destroy(dsnlm_weights* w) {
     (void)hipFree(w->delta);
     (void)hipFree(w->bp);
     (void)hipFree(w->key);
+    (void)hipFree(w->scratch);
     delete w;
 }
 

@@ -41,19 +41,41 @@ __device__ __forceinline__ int reflect_clamp(int k, int n) {
     return k;
 }
 
-template <int P, int TH, int TW, int R, int L>
+// Tile geometry.  S_CLASS is the largest search half-width the instance
+// serves; it fixes the LDS row strides at compile time so every LDS access in
+// the shift loop is a base register plus an immediate offset.
+template <int P, int S_CLASS>
 struct Geo {
-    static constexpr int NT = TH * (TW / L);        // threads per block
-    static constexpr int TWE = TW + 2 * P;          // tile widened by the patch
-    static constexpr int NITEM1 = TWE * (TH / R);   // phase-1 work items
+    static constexpr int TH = 32, TW = 64;   // output tile
+    static constexpr int R = 8;              // phase-1 strip height
+    static constexpr int L = 8;              // phase-2 segment length
+    static constexpr int NT = TH * (TW / L);  // 256 threads
+    static constexpr int TWE = TW + 2 * P;   // tile widened by the patch
+    static constexpr int NITEM1 = TWE * (TH / R);
     static constexpr int ROUNDS1 = (NITEM1 + NT - 1) / NT;
-    static constexpr int VW = ((TWE + 3) / 4) * 4 + 4;  // padded row of V
-    static_assert(TH % R == 0, "strip height must divide the tile height");
-    static_assert(TW % L == 0, "segment length must divide the tile width");
-    static_assert(L % 4 == 0, "segments are read as float4");
+    static constexpr int ZW = TW + 2 * (S_CLASS + P);  // guide tile row stride
+    // aux row stride: odd, so lanes walking down rows hit distinct banks
+    static constexpr int AW = ((TW + 2 * S_CLASS) % 2) ? (TW + 2 * S_CLASS) : (TW + 2 * S_CLASS + 1);
+    // V row stride: 4 * odd, for conflict-free float4 reads down rows
+    static constexpr int VW0 = ((TWE + 3) / 4) * 4;
+    static constexpr int VW = ((VW0 / 4) % 2) ? VW0 : VW0 + 4;
+    static_assert(TH % R == 0 && TW % L == 0 && L % 4 == 0, "tile shape");
 };
 
-constexpr int naux(int mode) { return mode == kPassA ? 1 : 2; }
+// Floats per pixel of the per-pixel input tile: pass A needs none (pairs that
+// leave the image are masked arithmetically), the other passes stage two.
+constexpr int naux(int mode) { return mode == kPassA ? 0 : 2; }
+
+template <int P, int S_CLASS>
+size_t lds_floats(int S, int mode) {
+    using G = Geo<P, S_CLASS>;
+    const size_t ZH = G::TH + 2 * (S + P);
+    const size_t AH = G::TH + 2 * S;
+    size_t n = (ZH * G::ZW + 3) & ~(size_t)3;
+    n += (AH * G::AW * naux(mode) + 3) & ~(size_t)3;
+    n += (size_t)2 * G::TH * G::VW;
+    return n;
+}
 
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
 #pragma unroll
@@ -64,13 +86,15 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
     return v;
 }
 
-template <int P, int TH, int TW, int R, int L, int MODE, bool BATCH>
-__global__ void __launch_bounds__(TH * (TW / L))
+template <int P, int S_CLASS, int MODE, bool BATCH, int PIPE>
+__global__ void __launch_bounds__(256)
 k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__ tiles, int S,
         HatTable hat) {
-    using G = Geo<P, TH, TW, R, L>;
-    constexpr int NT = G::NT;
+    using G = Geo<P, S_CLASS>;
+    constexpr int NT = G::NT, TH = G::TH, TW = G::TW, R = G::R, L = G::L;
+    constexpr int ZW = G::ZW, AW = G::AW, VW = G::VW;
     constexpr int NA = naux(MODE);
+    constexpr int NE = R + 2 * P;  // phase-1 rows per strip
     extern __shared__ __align__(16) float lds[];
     const int tid = threadIdx.x;
 
@@ -90,8 +114,8 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
         first = blockIdx.x == 0 && blockIdx.y == 0;
     }
     const int n1 = d.n1, n2 = d.n2;
-    const int ZH = TH + 2 * (S + P), ZW = TW + 2 * (S + P);
-    const int AH = TH + 2 * S, AW = TW + 2 * S;
+    const int ZH = TH + 2 * (S + P), ZWr = TW + 2 * (S + P);
+    const int AH = TH + 2 * S, AWr = TW + 2 * S;
     float* Zs = lds;
     int off = (ZH * ZW + 3) & ~3;
     float* Aux = lds + off;
@@ -99,33 +123,30 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
     float* Vb = lds + off;
 
     // ---- stage the guide tile (halo S+P, mirrored) and the per-pixel inputs
-    for (int idx = tid; idx < ZH * ZW; idx += NT) {
-        const int r = idx / ZW, q = idx - r * ZW;
+    for (int idx = tid; idx < ZH * ZWr; idx += NT) {
+        const int r = idx / ZWr, q = idx - r * ZWr;
         const int gi = reflect_clamp(ti0 - S - P + r, n1);
         const int gj = reflect_clamp(tj0 - S - P + q, n2);
-        Zs[idx] = d.z[(size_t)gi * n2 + gj];
+        Zs[r * ZW + q] = d.z[(size_t)gi * n2 + gj];
     }
-    for (int idx = tid; idx < AH * AW; idx += NT) {
-        const int r = idx / AW, q = idx - r * AW;
-        const int gi = ti0 - S + r, gj = tj0 - S + q;
-        const bool in = (unsigned)gi < (unsigned)n1 && (unsigned)gj < (unsigned)n2;
-        if constexpr (MODE == kPassA) {
-            Aux[idx] = in ? 1.f : 0.f;  // pairs leaving the image get weight 0
-        } else {
-            float2 v = make_float2(0.f, 0.f);
+    if constexpr (NA == 2) {
+        for (int idx = tid; idx < AH * AWr; idx += NT) {
+            const int r = idx / AWr, q = idx - r * AWr;
+            const int gi = ti0 - S + r, gj = tj0 - S + q;
+            const bool in = (unsigned)gi < (unsigned)n1 && (unsigned)gj < (unsigned)n2;
+            float2 v = make_float2(0.f, 0.f);  // zero outside: those pairs drop out
             if (in) {
                 const size_t p = (size_t)gi * n2 + gj;
                 if constexpr (MODE == kPassC) {
                     // backward: t_r = c_r B'bar_r, w_r = c_r (f_r - B'bar_r x_r)
-                    v.x = d.cbar_aux[2 * p];
-                    v.y = d.cbar_aux[2 * p + 1];
+                    v = reinterpret_cast<const float2*>(d.cbar_aux)[p];
                 } else {
                     const float cc = d.c[p];
                     v.x = cc;
                     v.y = (MODE == kPassBBuild) ? 0.f : cc * d.x[p];
                 }
             }
-            reinterpret_cast<float2*>(Aux)[idx] = v;
+            reinterpret_cast<float2*>(Aux)[r * AW + q] = v;
         }
     }
     if constexpr (MODE == kPassA) {
@@ -133,8 +154,24 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
     }
     __syncthreads();
 
-    const int pi = tid / (TW / L);        // phase-2 output row in the tile
-    const int pj = (tid % (TW / L)) * L;  // first phase-2 output column
+    // ---- phase-1 items of this thread: reference columns kept in registers
+    float ref[G::ROUNDS1][NE];
+    int zoff[G::ROUNDS1];  // LDS index of the first reference element
+    int voff[G::ROUNDS1];  // LDS index (in V) of the first output
+#pragma unroll
+    for (int k1 = 0; k1 < G::ROUNDS1; ++k1) {
+        int it = tid + k1 * NT;
+        it = it < G::NITEM1 ? it : G::NITEM1 - 1;  // idle lanes shadow a valid item
+        const int strip = it / G::TWE;
+        const int c = it - strip * G::TWE;
+        zoff[k1] = (strip * R + S) * ZW + c + S;
+        voff[k1] = strip * R * VW + c;
+#pragma unroll
+        for (int q = 0; q < NE; ++q) ref[k1][q] = Zs[zoff[k1] + q * ZW];
+    }
+
+    const int pi = tid % TH;             // phase-2 output row in the tile
+    const int pj = (tid / TH) * L;       // first phase-2 output column
     float acc0[L], acc1[L];
 #pragma unroll
     for (int k = 0; k < L; ++k) {
@@ -143,81 +180,131 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
     }
     const float beta = d.beta;
 
-    int buf = 0;
-    for (int dy = -S; dy <= S; ++dy) {
-        const float lgy = hat.lg[dy + S];
-        for (int dx = -S; dx <= S; ++dx) {
-            const float lg = lgy + hat.lg[dx + S];
-            float* V = Vb + buf * (TH * G::VW);
-            // ---- phase 1: vertical sliding box sums of e_d down column strips
+    const int NS = (2 * S + 1) * (2 * S + 1);
+    const int gi_own = ti0 + pi;
+    const int gj_own = tj0 + pj;
+
+    // phase 1: vertical sliding box sums of e_d = (z(p) - z(p+d))^2 down the
+    // column strips, written to V.  The running sum adds the entering square
+    // and removes the leaving one with two FMAs.
+    auto phase1 = [&](int dy, int dx, float* V) {
+        const int sh = dy * ZW + dx;
 #pragma unroll
-            for (int k1 = 0; k1 < G::ROUNDS1; ++k1) {
-                const int it = tid + k1 * NT;
-                if (it < G::NITEM1) {
-                    const int strip = it / G::TWE;
-                    const int c = it - strip * G::TWE;
-                    const int r0 = strip * R;
-                    const float* zr = Zs + (r0 + S) * ZW + c + S;
-                    const float* zq = zr + dy * ZW + dx;
-                    float e[R + 2 * P];
+        for (int k1 = 0; k1 < G::ROUNDS1; ++k1) {
+            if (tid + k1 * NT < G::NITEM1) {
+                const float* zq = Zs + zoff[k1] + sh;
+                // all reads first: the V stores below may not be reordered
+                // above later reads of the same LDS array
+                float tq[NE];
 #pragma unroll
-                    for (int q = 0; q < R + 2 * P; ++q) {
-                        const float t = zr[q * ZW] - zq[q * ZW];
-                        e[q] = t * t;
-                    }
-                    float v = 0.f;
+                for (int q = 0; q < NE; ++q) tq[q] = ref[k1][q] - zq[q * ZW];
+                float v = 0.f;
 #pragma unroll
-                    for (int q = 0; q <= 2 * P; ++q) v += e[q];
-                    float* vo = V + r0 * G::VW + c;
-                    vo[0] = v;
+                for (int q = 0; q <= 2 * P; ++q) v = fmaf(tq[q], tq[q], v);
+                float* vo = V + voff[k1];
+                vo[0] = v;
 #pragma unroll
-                    for (int q = 1; q < R; ++q) {
-                        v += e[q + 2 * P] - e[q - 1];
-                        vo[q * G::VW] = v;
-                    }
+                for (int q = 1; q < R; ++q) {
+                    v = fmaf(tq[q + 2 * P], tq[q + 2 * P], v);
+                    v = fmaf(-tq[q - 1], tq[q - 1], v);
+                    vo[q * VW] = v;
                 }
             }
-            __syncthreads();
-            // ---- phase 2: horizontal sliding sums -> D, weights, accumulate
-            const float* vr = V + pi * G::VW + pj;
-            float vv[((L + 2 * P + 3) / 4) * 4];
+        }
+    };
+
+    // phase 2 is split so its LDS reads can be issued before the next
+    // shift's phase 1: load() fetches V (and the per-pixel inputs), math()
+    // forms D by horizontal sliding sums and a = exp2(log2 Lambda - beta D).
+    constexpr int NV = ((L + 2 * P + 3) / 4) * 4;
+    float vv[NV];
+    float2 cv[L];
+    auto load2 = [&](int dy, int dx, const float* V) {
+        const float* vr = V + pi * VW + pj;
 #pragma unroll
-            for (int q = 0; q < (L + 2 * P + 3) / 4; ++q) {
-                const float4 t4 = reinterpret_cast<const float4*>(vr)[q];
-                vv[4 * q + 0] = t4.x;
-                vv[4 * q + 1] = t4.y;
-                vv[4 * q + 2] = t4.z;
-                vv[4 * q + 3] = t4.w;
-            }
-            float hs = 0.f;
+        for (int q = 0; q < NV / 4; ++q) {
+            const float4 t4 = reinterpret_cast<const float4*>(vr)[q];
+            vv[4 * q + 0] = t4.x;
+            vv[4 * q + 1] = t4.y;
+            vv[4 * q + 2] = t4.z;
+            vv[4 * q + 3] = t4.w;
+        }
+        if constexpr (NA == 2) {
+            const float2* ap = reinterpret_cast<const float2*>(Aux) + (pi + dy + S) * AW + pj + dx + S;
 #pragma unroll
-            for (int q = 0; q <= 2 * P; ++q) hs += vv[q];
-            float Dk[L];
-            Dk[0] = hs;
+            for (int k = 0; k < L; ++k) cv[k] = ap[k];
+        }
+    };
+    auto math2 = [&](int dy, int dx) {
+        const float lg = hat.lg[dy + S] + hat.lg[dx + S];
+        float hs = 0.f;
 #pragma unroll
-            for (int k = 1; k < L; ++k) {
-                hs += vv[k + 2 * P] - vv[k - 1];
-                Dk[k] = hs;
-            }
-            const int arow = (pi + dy + S) * AW + pj + dx + S;
-            if constexpr (NA == 1) {
-                const float* ap = Aux + arow;
+        for (int q = 0; q <= 2 * P; ++q) hs += vv[q];
+        float Dk[L];
+        Dk[0] = hs;
 #pragma unroll
-                for (int k = 0; k < L; ++k) {
-                    const float a = __builtin_amdgcn_exp2f(lg - beta * Dk[k]);
-                    acc0[k] = fmaf(a, ap[k], acc0[k]);
-                }
+        for (int k = 1; k < L; ++k) {
+            hs += vv[k + 2 * P] - vv[k - 1];
+            Dk[k] = hs;
+        }
+        if constexpr (NA == 0) {
+            // the whole tile keeps its partners inside the image for this shift?
+            const bool inside = ti0 + dy >= 0 && ti0 + TH - 1 + dy < n1 && tj0 + dx >= 0 &&
+                                tj0 + TW - 1 + dx < n2;
+            if (inside) {
+#pragma unroll
+                for (int k = 0; k < L; ++k) acc0[k] += __builtin_amdgcn_exp2f(lg - beta * Dk[k]);
             } else {
-                const float2* ap = reinterpret_cast<const float2*>(Aux) + arow;
+                const bool rowok = (unsigned)(gi_own + dy) < (unsigned)n1;
 #pragma unroll
                 for (int k = 0; k < L; ++k) {
                     const float a = __builtin_amdgcn_exp2f(lg - beta * Dk[k]);
-                    const float2 cv = ap[k];
-                    acc0[k] = fmaf(a, cv.x, acc0[k]);
-                    if constexpr (MODE != kPassBBuild) acc1[k] = fmaf(a, cv.y, acc1[k]);
+                    const bool ok = rowok && (unsigned)(gj_own + k + dx) < (unsigned)n2;
+                    acc0[k] += ok ? a : 0.f;
                 }
             }
-            buf ^= 1;
+        } else {
+#pragma unroll
+            for (int k = 0; k < L; ++k) {
+                const float a = __builtin_amdgcn_exp2f(lg - beta * Dk[k]);
+                acc0[k] = fmaf(a, cv[k].x, acc0[k]);
+                if constexpr (MODE != kPassBBuild) acc1[k] = fmaf(a, cv[k].y, acc1[k]);
+            }
+        }
+    };
+
+    // The shift counters advance incrementally (no integer division).  Both
+    // schedules use one barrier per shift thanks to the two V buffers.
+    int dy = -S, dx = -S;
+    if constexpr (PIPE) {
+        // software pipeline: phase 1 of shift t+1 and phase 2 of shift t share
+        // one barrier interval (they touch different V buffers)
+        phase1(dy, dx, Vb);
+        __syncthreads();
+        for (int t = 0; t < NS; ++t) {
+            int ndx = dx + 1, ndy = dy;
+            if (ndx > S) {
+                ndx = -S;
+                ++ndy;
+            }
+            load2(dy, dx, Vb + (t & 1) * (TH * VW));
+            if (t + 1 < NS) phase1(ndy, ndx, Vb + ((t + 1) & 1) * (TH * VW));
+            math2(dy, dx);
+            __syncthreads();
+            dy = ndy;
+            dx = ndx;
+        }
+    } else {
+        for (int t = 0; t < NS; ++t) {
+            float* V = Vb + (t & 1) * (TH * VW);
+            phase1(dy, dx, V);
+            __syncthreads();
+            load2(dy, dx, V);
+            math2(dy, dx);
+            if (++dx > S) {
+                dx = -S;
+                ++dy;
+            }
         }
     }
 
@@ -233,9 +320,8 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
                 if constexpr (MODE == kPassA) {
                     d.c[p] = 1.0f / sqrtf(acc0[k]);
                 } else if constexpr (MODE == kPassC) {
-                    // acc0 = sum a t_r = U_s, acc1 = sum a w_r
-                    d.cbar_aux[2 * p] = acc0[k];
-                    d.cbar_aux[2 * p + 1] = acc1[k];
+                    // acc0 = sum a t_r, acc1 = sum a w_r
+                    reinterpret_cast<float2*>(d.cbar_aux)[p] = make_float2(acc0[k], acc1[k]);
                 } else {
                     const float cs = reinterpret_cast<const float2*>(Aux)[(pi + S) * AW + pj + k + S].x;
                     if constexpr (MODE == kPassBApply || MODE == kApply) {
@@ -286,63 +372,104 @@ k_epilogue(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __rest
     }
 }
 
-// Tile shape per patch half-width: TH x TW outputs, strips of R rows,
-// segments of L columns (256 threads).
-template <int P>
-struct Shape {
-    static constexpr int TH = 32, TW = 64, R = 8, L = 8;
-};
+constexpr int kSmallS = 12;  // S <= 12 uses the compact-stride instances
 
-template <int P, int MODE, bool BATCH>
-hipError_t launch_one(int S, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
-                      int ntiles, hipStream_t st) {
-    using Sh = Shape<P>;
-    using G = Geo<P, Sh::TH, Sh::TW, Sh::R, Sh::L>;
-    auto kern = k_sweep<P, Sh::TH, Sh::TW, Sh::R, Sh::L, MODE, BATCH>;
-    const size_t lds = sweep_lds_bytes(S, P, MODE);
+template <int P, int S_CLASS, int MODE, bool BATCH, int PIPE>
+hipError_t ensure_attr() {
     static bool attr_set = false;
     if (!attr_set) {
+        auto kern = k_sweep<P, S_CLASS, MODE, BATCH, PIPE>;
         hipError_t e = hipFuncSetAttribute((const void*)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    dim3 grid;
-    if (BATCH) {
-        grid = dim3(ntiles);
-    } else {
-        grid = dim3((one.n2 + Sh::TW - 1) / Sh::TW, (one.n1 + Sh::TH - 1) / Sh::TH);
-    }
+    return hipSuccess;
+}
+
+template <int P, int S_CLASS, int MODE, bool BATCH, int PIPE>
+hipError_t launch_var(int S, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
+                      int ntiles, hipStream_t st) {
+    using G = Geo<P, S_CLASS>;
+    const size_t lds = lds_floats<P, S_CLASS>(S, MODE) * sizeof(float);
+    hipError_t e = ensure_attr<P, S_CLASS, MODE, BATCH, PIPE>();
+    if (e != hipSuccess) return e;
+    dim3 grid = BATCH ? dim3(ntiles)
+                      : dim3((one.n2 + G::TW - 1) / G::TW, (one.n1 + G::TH - 1) / G::TH);
     HatTable hat = make_hat(S);
-    hipLaunchKernelGGL(kern, grid, dim3(G::NT), lds, st, one, batch, tiles, S, hat);
+    hipLaunchKernelGGL((k_sweep<P, S_CLASS, MODE, BATCH, PIPE>), grid, dim3(G::NT), lds, st, one,
+                       batch, tiles, S, hat);
     return hipGetLastError();
 }
 
-template <int P, bool BATCH>
+template <int P, int S_CLASS, int MODE, bool BATCH>
+hipError_t launch_one(int S, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
+                      int ntiles, hipStream_t st) {
+    if (sweep_variant(MODE, S, P) == 1)
+        return launch_var<P, S_CLASS, MODE, BATCH, 1>(S, one, batch, tiles, ntiles, st);
+    return launch_var<P, S_CLASS, MODE, BATCH, 0>(S, one, batch, tiles, ntiles, st);
+}
+
+template <int P, int S_CLASS, bool BATCH>
 hipError_t dispatch_mode(int mode, int S, const ImgDesc& one, const ImgDesc* batch,
                          const TileRef* tiles, int ntiles, hipStream_t st) {
     switch (mode) {
-        case kPassA: return launch_one<P, kPassA, BATCH>(S, one, batch, tiles, ntiles, st);
-        case kPassBApply: return launch_one<P, kPassBApply, BATCH>(S, one, batch, tiles, ntiles, st);
-        case kPassBBuild: return launch_one<P, kPassBBuild, BATCH>(S, one, batch, tiles, ntiles, st);
-        case kApply: return launch_one<P, kApply, BATCH>(S, one, batch, tiles, ntiles, st);
-        case kPassC: return launch_one<P, kPassC, BATCH>(S, one, batch, tiles, ntiles, st);
-        default: return hipErrorInvalidValue;
+        case kPassA: return launch_one<P, S_CLASS, kPassA, BATCH>(S, one, batch, tiles, ntiles, st);
+        case kPassBApply: return launch_one<P, S_CLASS, kPassBApply, BATCH>(S, one, batch, tiles, ntiles, st);
+        default: break;
     }
+    if constexpr (!BATCH) {
+        switch (mode) {
+            case kPassBBuild: return launch_one<P, S_CLASS, kPassBBuild, false>(S, one, batch, tiles, ntiles, st);
+            case kApply: return launch_one<P, S_CLASS, kApply, false>(S, one, batch, tiles, ntiles, st);
+            case kPassC: return launch_one<P, S_CLASS, kPassC, false>(S, one, batch, tiles, ntiles, st);
+            default: break;
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int P, bool BATCH>
+hipError_t dispatch_s(int mode, int S, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
+                      int ntiles, hipStream_t st) {
+    if (S <= kSmallS) return dispatch_mode<P, kSmallS, BATCH>(mode, S, one, batch, tiles, ntiles, st);
+    return dispatch_mode<P, kMaxS, BATCH>(mode, S, one, batch, tiles, ntiles, st);
 }
 
 template <bool BATCH>
 hipError_t dispatch_p(int mode, int S, int P, const ImgDesc& one, const ImgDesc* batch,
                       const TileRef* tiles, int ntiles, hipStream_t st) {
     switch (P) {
-        case 0: return dispatch_mode<0, BATCH>(mode, S, one, batch, tiles, ntiles, st);
-        case 1: return dispatch_mode<1, BATCH>(mode, S, one, batch, tiles, ntiles, st);
-        case 2: return dispatch_mode<2, BATCH>(mode, S, one, batch, tiles, ntiles, st);
-        case 3: return dispatch_mode<3, BATCH>(mode, S, one, batch, tiles, ntiles, st);
-        case 4: return dispatch_mode<4, BATCH>(mode, S, one, batch, tiles, ntiles, st);
-        case 5: return dispatch_mode<5, BATCH>(mode, S, one, batch, tiles, ntiles, st);
+        case 0: return dispatch_s<0, BATCH>(mode, S, one, batch, tiles, ntiles, st);
+        case 1: return dispatch_s<1, BATCH>(mode, S, one, batch, tiles, ntiles, st);
+        case 2: return dispatch_s<2, BATCH>(mode, S, one, batch, tiles, ntiles, st);
+        case 3: return dispatch_s<3, BATCH>(mode, S, one, batch, tiles, ntiles, st);
+        case 4: return dispatch_s<4, BATCH>(mode, S, one, batch, tiles, ntiles, st);
+        case 5: return dispatch_s<5, BATCH>(mode, S, one, batch, tiles, ntiles, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+template <int P, int S_CLASS, int PIPE>
+hipError_t prepare_var() {
+    hipError_t e = ensure_attr<P, S_CLASS, kPassA, false, PIPE>();
+    if (e == hipSuccess) e = ensure_attr<P, S_CLASS, kPassBApply, false, PIPE>();
+    if (e == hipSuccess) e = ensure_attr<P, S_CLASS, kPassBBuild, false, PIPE>();
+    if (e == hipSuccess) e = ensure_attr<P, S_CLASS, kApply, false, PIPE>();
+    if (e == hipSuccess) e = ensure_attr<P, S_CLASS, kPassC, false, PIPE>();
+    return e;
+}
+
+template <int P, int S_CLASS>
+hipError_t prepare_all() {
+    hipError_t e = prepare_var<P, S_CLASS, 0>();
+    if (e == hipSuccess) e = prepare_var<P, S_CLASS, 1>();
+    return e;
+}
+
+template <int P>
+hipError_t prepare_p(int S) {
+    return S <= kSmallS ? prepare_all<P, kSmallS>() : prepare_all<P, kMaxS>();
 }
 
 }  // namespace
@@ -356,6 +483,18 @@ HatTable make_hat(int S) {
     return t;
 }
 
+hipError_t prepare_sweeps(int S, int P) {
+    switch (P) {
+        case 0: return prepare_p<0>(S);
+        case 1: return prepare_p<1>(S);
+        case 2: return prepare_p<2>(S);
+        case 3: return prepare_p<3>(S);
+        case 4: return prepare_p<4>(S);
+        case 5: return prepare_p<5>(S);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 TileCfg sweep_tile_cfg(int P, int mode) {
     (void)P;
     (void)mode;
@@ -363,13 +502,11 @@ TileCfg sweep_tile_cfg(int P, int mode) {
 }
 
 size_t sweep_lds_bytes(int S, int P, int mode) {
+    // upper bound over the instances (S_CLASS = 24 for S > 12)
+    const int SC = S <= kSmallS ? kSmallS : kMaxS;
     const int TH = 32, TW = 64;
-    const int ZH = TH + 2 * (S + P), ZW = TW + 2 * (S + P);
-    const int AH = TH + 2 * S, AW = TW + 2 * S;
-    const int VW = ((TW + 2 * P + 3) / 4) * 4 + 4;
-    size_t n = ((size_t)ZH * ZW + 3) & ~(size_t)3;
-    n += ((size_t)AH * AW * naux(mode) + 3) & ~(size_t)3;
-    n += (size_t)2 * TH * VW;
+    const size_t ZW = TW + 2 * (SC + P), AW = TW + 2 * SC + 1, VW = TW + 2 * P + 8;
+    size_t n = (TH + 2 * (S + P)) * ZW + (TH + 2 * S) * AW * (mode == kPassA ? 0 : 2) + 2 * TH * VW + 8;
     return n * sizeof(float);
 }
 

@@ -59,6 +59,12 @@ enum SweepMode : int {
     kPassC = 4,        // backward: sum a t_r, sum a w_r
 };
 
+// Variant table of the sweeps (tuning.hip).
+constexpr int kSweepVariants = 2;
+int sweep_variant(int mode, int S, int P);
+void set_sweep_variant(int kind, int S, int P, int v);
+void save_tuning();
+
 struct TileCfg {
     int TH, TW, threads;
 };
@@ -66,6 +72,9 @@ struct TileCfg {
 // Launchers (dsnlm_sweep.hip).
 TileCfg sweep_tile_cfg(int P, int mode);
 size_t sweep_lds_bytes(int S, int P, int mode);
+// Set the dynamic-LDS attribute of every single-image sweep kernel for patch
+// half-widths S and P (needed once before a stream capture).
+hipError_t prepare_sweeps(int S, int P);
 hipError_t launch_sweep(int mode, int S, int P, const ImgDesc& one, const ImgDesc* batch,
                         const TileRef* tiles, int ntiles, hipStream_t st);
 hipError_t launch_epilogue(const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
@@ -106,6 +115,8 @@ struct dsnlm_weights {
     float* delta;
     float* bp;
     unsigned long long* key;
-    float* xsave;      // not used by the kernels; kept null
+    float* scratch;    // solver scratch (grow-only), freed with the handle
+    size_t scratch_cap;
+    float* zbuf;       // denoiser input x + u inside the solver (in scratch)
     bool applied;      // bp holds B' of the last apply
 };

@@ -1,0 +1,695 @@
+// Linearized plug-and-play ADMM (Section 2, Algorithm 1) on gfx950.
+//
+// One iteration k:
+//   x <- Pi_C(mu (alpha x + rho (v - u) - grad f(x)))        (linearized x-step)
+//   z  = x + u                                               (denoiser input)
+//   v <- W_k z, W_k = W(z) while k <= k0, else W_{k0}         (DSG-NLM)
+//   u <- u + x - v                                           (dual update)
+// with mu = 1/(alpha + rho), alpha = 1/gamma.  grad f is
+//   super-resolution (Section 4.1): A^T (A x - y), A = decimation after a
+//     separable blur with mirrored or periodic boundary;
+//   single-photon imaging (Section 4.2): phi'(x_i) per pixel.
+// The forward operator and its exact adjoint are evaluated directly (no FFT):
+// the adjoint gathers, for each high-resolution pixel, every low-resolution
+// sample whose blur footprint covers it or one of its mirrored/wrapped copies.
+// Residual norms are reduced in two fixed-order stages (per-block partials,
+// then one block), so repeated runs give identical bits.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace dsnlm {
+
+int check_denoiser_args(int n1, int n2, int S, int P, float h, const char* who);
+int prepare_handle(int n1, int n2, int S, int P, float h, dsnlm_weights** out);
+ImgDesc base_desc(const dsnlm_weights* w);
+
+namespace {
+
+constexpr int kMaxTaps = 31;
+
+struct Taps {
+    float t[kMaxTaps];
+};
+
+struct SRGeom {
+    int n1, n2;   // high-resolution size
+    int m1, m2;   // low-resolution size, ceil(n / factor)
+    int f;        // decimation factor
+    int bs;       // blur size (odd)
+    int R;        // (bs - 1) / 2
+};
+
+// Source index in [0, n) of padded position k (|k| < 2n).
+template <int BOUNDARY>
+__device__ __forceinline__ int src_index(int k, int n) {
+    if (BOUNDARY == 0) {
+        if (k < 0) return -k - 1;
+        if (k >= n) return 2 * n - 1 - k;
+        return k;
+    }
+    if (k < 0) return k + n;
+    if (k >= n) return k - n;
+    return k;
+}
+
+// r = A x - y on the low-resolution grid (y may be null: r = A x).
+template <int BOUNDARY>
+__global__ void __launch_bounds__(256)
+k_sr_forward(const float* __restrict__ x, const float* __restrict__ y, float* __restrict__ r,
+             SRGeom g, Taps taps) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= g.m1 * g.m2) return;
+    const int I = idx / g.m2, J = idx - I * g.m2;
+    float acc = 0.f;
+    for (int a = 0; a < g.bs; ++a) {
+        const int i = src_index<BOUNDARY>(g.f * I + a - g.R, g.n1);
+        const float* row = x + (size_t)i * g.n2;
+        float ra = 0.f;
+        for (int b = 0; b < g.bs; ++b) {
+            const int j = src_index<BOUNDARY>(g.f * J + b - g.R, g.n2);
+            ra = fmaf(taps.t[b], row[j], ra);
+        }
+        acc = fmaf(taps.t[a], ra, acc);
+    }
+    r[idx] = y ? acc - y[idx] : acc;
+}
+
+// The padded positions that map onto pixel i (itself and up to two copies).
+template <int BOUNDARY>
+__device__ __forceinline__ int preimages(int i, int n, int R, int* out) {
+    int c = 0;
+    out[c++] = i;
+    if (BOUNDARY == 0) {
+        if (i <= R - 1) out[c++] = -1 - i;
+        if (i >= n - R) out[c++] = 2 * n - 1 - i;
+    } else {
+        if (i <= R - 1) out[c++] = i + n;
+        if (i >= n - R) out[c++] = i - n;
+    }
+    return c;
+}
+
+// (A^T r)(i, j): gather over the low-resolution samples whose footprint covers
+// a preimage of (i, j).
+template <int BOUNDARY>
+__device__ __forceinline__ float sr_adjoint_at(const float* __restrict__ r, int i, int j,
+                                               const SRGeom& g, const Taps& taps) {
+    int pi[3], pj[3];
+    const int ci = preimages<BOUNDARY>(i, g.n1, g.R, pi);
+    const int cj = preimages<BOUNDARY>(j, g.n2, g.R, pj);
+    float acc = 0.f;
+    for (int a = 0; a < ci; ++a) {
+        const int ip = pi[a];
+        // I with 0 <= ip - f I + R <= bs - 1
+        int Ilo = ip + g.R - (g.bs - 1);
+        Ilo = Ilo <= 0 ? 0 : (Ilo + g.f - 1) / g.f;
+        int Ihi = ip + g.R;
+        Ihi = Ihi < 0 ? -1 : Ihi / g.f;
+        if (Ihi > g.m1 - 1) Ihi = g.m1 - 1;
+        for (int I = Ilo; I <= Ihi; ++I) {
+            const float ta = taps.t[ip - g.f * I + g.R];
+            const float* rr = r + (size_t)I * g.m2;
+            float rowacc = 0.f;
+            for (int b = 0; b < cj; ++b) {
+                const int jp = pj[b];
+                int Jlo = jp + g.R - (g.bs - 1);
+                Jlo = Jlo <= 0 ? 0 : (Jlo + g.f - 1) / g.f;
+                int Jhi = jp + g.R;
+                Jhi = Jhi < 0 ? -1 : Jhi / g.f;
+                if (Jhi > g.m2 - 1) Jhi = g.m2 - 1;
+                for (int J = Jlo; J <= Jhi; ++J) rowacc = fmaf(taps.t[jp - g.f * J + g.R], rr[J], rowacc);
+            }
+            acc = fmaf(ta, rowacc, acc);
+        }
+    }
+    return acc;
+}
+
+struct StepScalars {
+    float alpha, rho, mu, lo, hi;
+};
+
+// x <- clip(mu (alpha x + rho (v - u) - A^T r)); z = x + u.
+// With step == 0 it only writes g = A^T r into xo (gradient / adjoint).
+template <int BOUNDARY>
+__global__ void __launch_bounds__(256)
+k_sr_adjoint_step(const float* __restrict__ r, float* __restrict__ x, const float* __restrict__ v,
+                  const float* __restrict__ u, float* __restrict__ z, SRGeom g, Taps taps,
+                  StepScalars s, int step) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= g.n1 * g.n2) return;
+    const int i = idx / g.n2, j = idx - i * g.n2;
+    const float grad = sr_adjoint_at<BOUNDARY>(r, i, j, g, taps);
+    if (!step) {
+        x[idx] = grad;
+        return;
+    }
+    float xn = s.mu * (s.alpha * x[idx] + s.rho * (v[idx] - u[idx]) - grad);
+    xn = fminf(fmaxf(xn, s.lo), s.hi);
+    x[idx] = xn;
+    z[idx] = xn + u[idx];
+}
+
+struct SPIScalars {
+    float eta_over_K;  // eta / K
+    float K;
+    float t_min;
+};
+
+__device__ __forceinline__ float spi_dphi(float t, float ones, const SPIScalars& q) {
+    t = fmaxf(t, q.t_min);
+    const float a = q.eta_over_K * t;
+    const float e = expf(-a);
+    const float denom = -expm1f(-a);  // 1 - exp(-eta t / K)
+    return q.eta_over_K * ((q.K - ones) - ones * e / denom);
+}
+
+// SPI: x <- clip(mu (alpha x + rho (v - u) - phi'(x))); z = x + u
+// (step == 0: write phi'(x) into z).
+__global__ void __launch_bounds__(256)
+k_spi_step(float* __restrict__ x, const float* __restrict__ v, const float* __restrict__ u,
+           float* __restrict__ z, const unsigned char* __restrict__ ones, int n, SPIScalars q,
+           StepScalars s, int step) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= n) return;
+    const float xv = x[idx];
+    const float grad = spi_dphi(xv, (float)ones[idx], q);
+    if (!step) {
+        z[idx] = grad;
+        return;
+    }
+    float xn = s.mu * (s.alpha * xv + s.rho * (v[idx] - u[idx]) - grad);
+    xn = fminf(fmaxf(xn, s.lo), s.hi);
+    x[idx] = xn;
+    z[idx] = xn + u[idx];
+}
+
+// v_new = z + B'/m (denoiser output); u <- u + x - v_new; v <- v_new; per-block
+// partial sums of (x - v_new)^2 and (v_new - v_old)^2.
+__global__ void __launch_bounds__(256)
+k_ladmm_epilogue(const float* __restrict__ z, const float* __restrict__ bp,
+                 const unsigned long long* __restrict__ key, const float* __restrict__ x,
+                 float* __restrict__ v, float* __restrict__ u, int n, float* __restrict__ partials) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    const float m = __uint_as_float((unsigned)(*key >> 32));
+    float p = 0.f, d = 0.f;
+    if (idx < n) {
+        const float vn = z[idx] + bp[idx] / m;
+        const float xv = x[idx];
+        const float vo = v[idx];
+        u[idx] = u[idx] + xv - vn;
+        v[idx] = vn;
+        p = (xv - vn) * (xv - vn);
+        d = (vn - vo) * (vn - vo);
+    }
+    if (!partials) return;
+    __shared__ float sp[256], sd[256];
+    sp[threadIdx.x] = p;
+    sd[threadIdx.x] = d;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            sp[threadIdx.x] += sp[threadIdx.x + w];
+            sd[threadIdx.x] += sd[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = sp[0];
+        partials[2 * blockIdx.x + 1] = sd[0];
+    }
+}
+
+// out[0] = sqrt(sum_p / n), out[1] = rho sqrt(sum_d / n); fixed order.
+__global__ void __launch_bounds__(256)
+k_residual_final(const float* __restrict__ partials, int nblk, int n, float rho, float* __restrict__ out) {
+    __shared__ double sp[256], sd[256];
+    double p = 0.0, d = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) {
+        p += partials[2 * b];
+        d += partials[2 * b + 1];
+    }
+    sp[threadIdx.x] = p;
+    sd[threadIdx.x] = d;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            sp[threadIdx.x] += sp[threadIdx.x + w];
+            sd[threadIdx.x] += sd[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = (float)sqrt(sp[0] / n);
+        out[1] = (float)(rho * sqrt(sd[0] / n));
+    }
+}
+
+// ---- power iteration helpers -------------------------------------------
+__device__ __forceinline__ float hash_uniform(unsigned k) {
+    // integer hash (xorshift-multiply), mapped to [-1, 1)
+    k ^= k >> 16;
+    k *= 0x7feb352dU;
+    k ^= k >> 15;
+    k *= 0x846ca68bU;
+    k ^= k >> 16;
+    return (float)(k >> 8) * (2.0f / 16777216.0f) - 1.0f;
+}
+
+__global__ void k_fill_hash(float* __restrict__ v, int n) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx < n) v[idx] = hash_uniform((unsigned)idx * 2654435761u + 12345u);
+}
+
+// partials[b] = (sum v.g, sum g.g) over block b
+__global__ void __launch_bounds__(256)
+k_dot2(const float* __restrict__ v, const float* __restrict__ g, int n, double* __restrict__ partials) {
+    __shared__ double s0[256], s1[256];
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    double a = 0.0, b = 0.0;
+    if (idx < n) {
+        a = (double)v[idx] * g[idx];
+        b = (double)g[idx] * g[idx];
+    }
+    s0[threadIdx.x] = a;
+    s1[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            s0[threadIdx.x] += s0[threadIdx.x + w];
+            s1[threadIdx.x] += s1[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = s0[0];
+        partials[2 * blockIdx.x + 1] = s1[0];
+    }
+}
+
+// out[0] = sum v.g (Rayleigh quotient, v unit), out[1] = ||g||
+__global__ void __launch_bounds__(256)
+k_dot2_final(const double* __restrict__ partials, int nblk, double* __restrict__ out) {
+    __shared__ double s0[256], s1[256];
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += 256) {
+        a += partials[2 * k];
+        b += partials[2 * k + 1];
+    }
+    s0[threadIdx.x] = a;
+    s1[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            s0[threadIdx.x] += s0[threadIdx.x + w];
+            s1[threadIdx.x] += s1[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = s0[0];
+        out[1] = sqrt(s1[0]);
+    }
+}
+
+__global__ void k_scale_into(const float* __restrict__ g, const double* __restrict__ nrm,
+                             float* __restrict__ v, int n) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx < n) v[idx] = (float)(g[idx] / nrm[1]);
+}
+
+__global__ void k_normalize(float* __restrict__ v, const double* __restrict__ nrm, int n) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx < n) v[idx] = (float)(v[idx] / nrm[1]);
+}
+
+// ---- host helpers --------------------------------------------------------
+inline int blocks(size_t n) { return (int)((n + 255) / 256); }
+
+struct OpView {
+    SRGeom g;
+    Taps taps;
+    SPIScalars q;
+};
+
+int check_operator(const ladmm_operator* op, bool need_y, const char* who, OpView* ov) {
+    std::string w(who);
+    if (!op) return fail(DSNLM_EINVAL, w + ": null operator");
+    if (op->n1 < 1 || op->n2 < 1) return fail(DSNLM_EINVAL, w + ": image must be at least 1x1");
+    if ((long long)op->n1 * op->n2 > (1LL << 31) - 1)
+        return fail(DSNLM_EUNSUPPORTED, w + ": images above 2^31-1 pixels are not supported");
+    std::memset(ov, 0, sizeof(*ov));
+    if (op->kind == LADMM_OP_SR) {
+        if (!op->taps) return fail(DSNLM_EINVAL, w + ": null blur taps");
+        if (op->blur_size < 1 || op->blur_size > kMaxTaps || op->blur_size % 2 == 0)
+            return fail(DSNLM_EINVAL, w + ": blur_size must be odd and <= 31");
+        if (op->factor < 1 || op->factor > 8) return fail(DSNLM_EINVAL, w + ": factor must be in 1..8");
+        if (op->boundary != 0 && op->boundary != 1) return fail(DSNLM_EINVAL, w + ": boundary must be 0 or 1");
+        const int R = (op->blur_size - 1) / 2;
+        if (R >= op->n1 || R >= op->n2)
+            return fail(DSNLM_EINVAL, w + ": blur radius must be smaller than the image");
+        for (int k = 0; k < op->blur_size; ++k)
+            if (!std::isfinite(op->taps[k])) return fail(DSNLM_EINVAL, w + ": non-finite blur tap");
+        if (need_y && !op->y) return fail(DSNLM_EINVAL, w + ": null observation y");
+        ov->g = SRGeom{op->n1, op->n2, (op->n1 + op->factor - 1) / op->factor,
+                       (op->n2 + op->factor - 1) / op->factor, op->factor, op->blur_size, R};
+        for (int k = 0; k < op->blur_size; ++k) ov->taps.t[k] = op->taps[k];
+        return DSNLM_OK;
+    }
+    if (op->kind == LADMM_OP_SPI) {
+        if (!op->ones) return fail(DSNLM_EINVAL, w + ": null counts");
+        if (op->K < 1 || op->K > 255) return fail(DSNLM_EINVAL, w + ": K must be in 1..255");
+        if (!std::isfinite(op->eta) || !(op->eta > 0.f)) return fail(DSNLM_EINVAL, w + ": eta must be > 0");
+        if (!std::isfinite(op->t_min) || !(op->t_min > 0.f)) return fail(DSNLM_EINVAL, w + ": t_min must be > 0");
+        ov->q = SPIScalars{op->eta / (float)op->K, (float)op->K, op->t_min};
+        return DSNLM_OK;
+    }
+    return fail(DSNLM_EINVAL, w + ": unknown operator kind");
+}
+
+int check_params(const ladmm_params* p, int n1, int n2, const char* who, float* h_eff) {
+    std::string w(who);
+    if (!p) return fail(DSNLM_EINVAL, w + ": null params");
+    if (!(p->lambda > 0.f) || !(p->rho > 0.f) || !(p->gamma > 0.f) || !std::isfinite(p->lambda) ||
+        !std::isfinite(p->rho) || !std::isfinite(p->gamma))
+        return fail(DSNLM_EINVAL, w + ": lambda, rho and gamma must be finite and > 0");
+    if (!(p->lo < p->hi) || !std::isfinite(p->lo) || !std::isfinite(p->hi))
+        return fail(DSNLM_EINVAL, w + ": need finite lo < hi");
+    if (p->freeze_after < 1) return fail(DSNLM_EINVAL, w + ": freeze_after must be >= 1");
+    if (p->iters < 0) return fail(DSNLM_EINVAL, w + ": iters must be >= 0");
+    if (!std::isfinite(p->h)) return fail(DSNLM_EINVAL, w + ": h must be finite");
+    const float h = p->h > 0.f ? p->h : std::sqrt(p->lambda / p->rho);
+    *h_eff = h;
+    return check_denoiser_args(n1, n2, p->S, p->P, h, who);
+}
+
+// Scratch carried by the weights handle for the solver (grow-only).
+float* scratch_floats(dsnlm_weights* w, size_t n, int* rc) {
+    if (w->scratch_cap < n) {
+        if (w->scratch) (void)hipFree(w->scratch);
+        w->scratch = nullptr;
+        w->scratch_cap = 0;
+        hipError_t e = hipMalloc(&w->scratch, n * sizeof(float));
+        if (e != hipSuccess) {
+            *rc = check_hip(e, "solver scratch");
+            return nullptr;
+        }
+        w->scratch_cap = n;
+    }
+    *rc = DSNLM_OK;
+    return w->scratch;
+}
+
+// Enqueue iteration k of Algorithm 1.  lr: scratch for the low-resolution
+// residual (SR); partials: scratch for residual partials or null; res: device
+// [2] or null; ckpt: device [4][n] or null.
+int enqueue_step(const ladmm_operator* op, const OpView& ov, const ladmm_params* p, float h, int k,
+                 dsnlm_weights* w, float* x, float* v, float* u, float* lr, float* partials,
+                 float* res, float* ckpt, hipStream_t st) {
+    const int n = op->n1 * op->n2;
+    const float alpha = 1.0f / p->gamma;
+    StepScalars s{alpha, p->rho, 1.0f / (alpha + p->rho), p->lo, p->hi};
+    float* z = w->zbuf;
+    {
+        ProfScope prof(DSNLM_K_LADMM, st);
+        if (op->kind == LADMM_OP_SR) {
+            const int mlr = ov.g.m1 * ov.g.m2;
+            if (op->boundary == 0) {
+                hipLaunchKernelGGL(k_sr_forward<0>, dim3(blocks(mlr)), dim3(256), 0, st, x, op->y, lr, ov.g, ov.taps);
+                hipLaunchKernelGGL(k_sr_adjoint_step<0>, dim3(blocks(n)), dim3(256), 0, st, lr, x, v, u, z, ov.g,
+                                   ov.taps, s, 1);
+            } else {
+                hipLaunchKernelGGL(k_sr_forward<1>, dim3(blocks(mlr)), dim3(256), 0, st, x, op->y, lr, ov.g, ov.taps);
+                hipLaunchKernelGGL(k_sr_adjoint_step<1>, dim3(blocks(n)), dim3(256), 0, st, lr, x, v, u, z, ov.g,
+                                   ov.taps, s, 1);
+            }
+        } else {
+            hipLaunchKernelGGL(k_spi_step, dim3(blocks(n)), dim3(256), 0, st, x, v, u, z, op->ones, n, ov.q, s, 1);
+        }
+        int rc = check_hip(hipGetLastError(), "x-step");
+        if (rc) return rc;
+    }
+    ImgDesc d = base_desc(w);
+    d.x = z;
+    int rc;
+    if (k <= p->freeze_after) {
+        // adaptive weights: guide = the denoiser's own input z
+        rc = check_hip(hipMemcpyAsync(w->guide, z, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st),
+                       "copy guide");
+        d.z = w->guide;
+        if (!rc) rc = check_hip(launch_sweep(kPassA, p->S, p->P, d, nullptr, nullptr, 0, st), "pass A");
+        if (!rc) rc = check_hip(launch_sweep(kPassBApply, p->S, p->P, d, nullptr, nullptr, 0, st), "pass B");
+    } else {
+        rc = check_hip(launch_sweep(kApply, p->S, p->P, d, nullptr, nullptr, 0, st), "apply sweep");
+    }
+    if (rc) return rc;
+    {
+        ProfScope prof(DSNLM_K_LADMM, st);
+        hipLaunchKernelGGL(k_ladmm_epilogue, dim3(blocks(n)), dim3(256), 0, st, z, w->bp, w->key, x, v, u, n,
+                           res ? partials : nullptr);
+        if (res)
+            hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(256), 0, st, partials, blocks(n), n, p->rho, res);
+        rc = check_hip(hipGetLastError(), "dual update");
+        if (rc) return rc;
+    }
+    w->applied = true;
+    if (ckpt) {
+        const size_t b = (size_t)n * sizeof(float);
+        rc = check_hip(hipMemcpyAsync(ckpt, x, b, hipMemcpyDeviceToDevice, st), "checkpoint");
+        if (!rc) rc = check_hip(hipMemcpyAsync(ckpt + n, v, b, hipMemcpyDeviceToDevice, st), "checkpoint");
+        if (!rc) rc = check_hip(hipMemcpyAsync(ckpt + 2 * (size_t)n, u, b, hipMemcpyDeviceToDevice, st), "checkpoint");
+        if (!rc) rc = check_hip(hipMemcpyAsync(ckpt + 3 * (size_t)n, z, b, hipMemcpyDeviceToDevice, st), "checkpoint");
+    }
+    return rc;
+}
+
+// Solver scratch layout inside the handle: [z: n][lr: m][partials: 2*blocks(n)]
+int ensure_solver_scratch(dsnlm_weights* w, const OpView& ov, const ladmm_operator* op, float** lr,
+                          float** partials) {
+    const size_t n = (size_t)op->n1 * op->n2;
+    const size_t mlr = op->kind == LADMM_OP_SR ? (size_t)ov.g.m1 * ov.g.m2 : 0;
+    const size_t need = n + mlr + 2 * (size_t)blocks(n) + 64;
+    int rc;
+    float* base = scratch_floats(w, need, &rc);
+    if (!base) return rc;
+    w->zbuf = base;
+    *lr = base + n;
+    *partials = base + n + mlr;
+    return DSNLM_OK;
+}
+
+}  // namespace
+}  // namespace dsnlm
+
+using namespace dsnlm;
+
+extern "C" {
+
+int ladmm_step(const ladmm_operator* op, const ladmm_params* p, int k, dsnlm_weights** w, float* x, float* v,
+               float* u, void* stream) {
+    OpView ov;
+    int rc = check_operator(op, true, "ladmm_step", &ov);
+    if (rc) return rc;
+    float h;
+    rc = check_params(p, op->n1, op->n2, "ladmm_step", &h);
+    if (rc) return rc;
+    if (!w || !x || !v || !u) return fail(DSNLM_EINVAL, "ladmm_step: null pointer");
+    if (k < 1) return fail(DSNLM_EINVAL, "ladmm_step: k is 1-based");
+    if (k > p->freeze_after && !*w)
+        return fail(DSNLM_EINVAL, "ladmm_step: frozen iteration without built weights");
+    if (*w && ((*w)->n1 != op->n1 || (*w)->n2 != op->n2))
+        return fail(DSNLM_EINVAL, "ladmm_step: weights built for another image size");
+    if (k <= p->freeze_after) {
+        rc = prepare_handle(op->n1, op->n2, p->S, p->P, h, w);
+        if (rc) return rc;
+    }
+    float *lr, *partials;
+    rc = ensure_solver_scratch(*w, ov, op, &lr, &partials);
+    if (rc) return rc;
+    return enqueue_step(op, ov, p, h, k, *w, x, v, u, lr, partials, nullptr, nullptr,
+                        static_cast<hipStream_t>(stream));
+}
+
+int ladmm_solve(const ladmm_operator* op, const ladmm_params* p, float* x, float* v, float* u, float* residuals,
+                float* checkpoints, void* stream) {
+    OpView ov;
+    int rc = check_operator(op, true, "ladmm_solve", &ov);
+    if (rc) return rc;
+    float h;
+    rc = check_params(p, op->n1, op->n2, "ladmm_solve", &h);
+    if (rc) return rc;
+    if (!x || !v || !u) return fail(DSNLM_EINVAL, "ladmm_solve: null pointer");
+    if (p->iters == 0) return DSNLM_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    dsnlm_weights* w = nullptr;
+    rc = prepare_handle(op->n1, op->n2, p->S, p->P, h, &w);
+    if (rc) return rc;
+    float *lr, *partials;
+    rc = ensure_solver_scratch(w, ov, op, &lr, &partials);
+    if (rc) {
+        dsnlm_weights_destroy(w);
+        return rc;
+    }
+    rc = check_hip(prepare_sweeps(p->S, p->P), "sweep attributes");
+    if (rc) {
+        dsnlm_weights_destroy(w);
+        return rc;
+    }
+    const size_t n = (size_t)op->n1 * op->n2;
+    auto res_at = [&](int k) { return residuals ? residuals + 2 * (size_t)(k - 1) : nullptr; };
+    auto ck_at = [&](int k) { return checkpoints ? checkpoints + 4 * n * (size_t)(k - 1) : nullptr; };
+    int k = 1;
+    const int adaptive_end = p->freeze_after < p->iters ? p->freeze_after : p->iters;
+    for (; k <= adaptive_end && !rc; ++k)
+        rc = enqueue_step(op, ov, p, h, k, w, x, v, u, lr, partials, res_at(k), ck_at(k), st);
+    if (!rc && k <= p->iters) {
+        // frozen iterations: capture them once into a graph and launch it
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        bool use_graph = st != nullptr && hipStreamIsCapturing(st, &cs) == hipSuccess &&
+                         cs == hipStreamCaptureStatusNone;
+        if (use_graph && hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            use_graph = false;
+        }
+        int k0 = k;
+        for (; k <= p->iters && !rc; ++k)
+            rc = enqueue_step(op, ov, p, h, k, w, x, v, u, lr, partials, res_at(k), ck_at(k), st);
+        if (use_graph) {
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(st, &graph);
+            if (!rc) rc = check_hip(e, "end capture");
+            hipGraphExec_t exec = nullptr;
+            if (!rc) rc = check_hip(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate");
+            if (!rc) rc = check_hip(hipGraphLaunch(exec, st), "graph launch");
+            // the executable graph must outlive its launch
+            if (exec) {
+                (void)hipStreamSynchronize(st);
+                (void)hipGraphExecDestroy(exec);
+            }
+            if (graph) (void)hipGraphDestroy(graph);
+        }
+        (void)k0;
+    }
+    if (!rc) rc = check_hip(hipStreamSynchronize(st), "solve synchronise");
+    dsnlm_weights_destroy(w);
+    if (rc) return rc;
+    if (residuals) {
+        std::vector<float> host(2 * (size_t)p->iters);
+        rc = check_hip(hipMemcpy(host.data(), residuals, host.size() * sizeof(float), hipMemcpyDeviceToHost),
+                       "copy residuals");
+        if (rc) return rc;
+        for (float r : host)
+            if (!std::isfinite(r)) return fail(DSNLM_ENONFINITE, "ladmm_solve: non-finite residual");
+    }
+    return DSNLM_OK;
+}
+
+int ladmm_apply_forward(const ladmm_operator* op, const float* x, float* out, void* stream) {
+    OpView ov;
+    int rc = check_operator(op, false, "ladmm_apply_forward", &ov);
+    if (rc) return rc;
+    if (op->kind != LADMM_OP_SR) return fail(DSNLM_EINVAL, "ladmm_apply_forward: super-resolution only");
+    if (!x || !out) return fail(DSNLM_EINVAL, "ladmm_apply_forward: null pointer");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    ProfScope prof(DSNLM_K_LADMM, st);
+    const int mlr = ov.g.m1 * ov.g.m2;
+    if (op->boundary == 0)
+        hipLaunchKernelGGL(k_sr_forward<0>, dim3(blocks(mlr)), dim3(256), 0, st, x, nullptr, out, ov.g, ov.taps);
+    else
+        hipLaunchKernelGGL(k_sr_forward<1>, dim3(blocks(mlr)), dim3(256), 0, st, x, nullptr, out, ov.g, ov.taps);
+    return check_hip(hipGetLastError(), "ladmm_apply_forward");
+}
+
+int ladmm_gradient(const ladmm_operator* op, const float* x, float* g, void* stream) {
+    OpView ov;
+    int rc = check_operator(op, true, "ladmm_gradient", &ov);
+    if (rc) return rc;
+    if (!x || !g) return fail(DSNLM_EINVAL, "ladmm_gradient: null pointer");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int n = op->n1 * op->n2;
+    StepScalars s{};
+    if (op->kind == LADMM_OP_SPI) {
+        ProfScope prof(DSNLM_K_LADMM, st);
+        hipLaunchKernelGGL(k_spi_step, dim3(blocks(n)), dim3(256), 0, st, const_cast<float*>(x), nullptr, nullptr,
+                           g, op->ones, n, ov.q, s, 0);
+        return check_hip(hipGetLastError(), "ladmm_gradient");
+    }
+    float* lr = nullptr;
+    rc = check_hip(hipMalloc(&lr, (size_t)ov.g.m1 * ov.g.m2 * sizeof(float)), "gradient scratch");
+    if (rc) return rc;
+    {
+        ProfScope prof(DSNLM_K_LADMM, st);
+        const int mlr = ov.g.m1 * ov.g.m2;
+        if (op->boundary == 0) {
+            hipLaunchKernelGGL(k_sr_forward<0>, dim3(blocks(mlr)), dim3(256), 0, st, x, op->y, lr, ov.g, ov.taps);
+            hipLaunchKernelGGL(k_sr_adjoint_step<0>, dim3(blocks(n)), dim3(256), 0, st, lr, g, nullptr, nullptr,
+                               nullptr, ov.g, ov.taps, s, 0);
+        } else {
+            hipLaunchKernelGGL(k_sr_forward<1>, dim3(blocks(mlr)), dim3(256), 0, st, x, op->y, lr, ov.g, ov.taps);
+            hipLaunchKernelGGL(k_sr_adjoint_step<1>, dim3(blocks(n)), dim3(256), 0, st, lr, g, nullptr, nullptr,
+                               nullptr, ov.g, ov.taps, s, 0);
+        }
+        rc = check_hip(hipGetLastError(), "ladmm_gradient");
+    }
+    hipError_t e = hipStreamSynchronize(st);
+    (void)hipFree(lr);
+    if (!rc) rc = check_hip(e, "gradient synchronise");
+    return rc;
+}
+
+int ladmm_operator_norm2(const ladmm_operator* op, int iters, float* out, void* stream) {
+    OpView ov;
+    int rc = check_operator(op, false, "ladmm_operator_norm2", &ov);
+    if (rc) return rc;
+    if (op->kind != LADMM_OP_SR) return fail(DSNLM_EINVAL, "ladmm_operator_norm2: super-resolution only");
+    if (!out || iters < 1) return fail(DSNLM_EINVAL, "ladmm_operator_norm2: need out and iters >= 1");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int n = op->n1 * op->n2;
+    const int mlr = ov.g.m1 * ov.g.m2;
+    float *v = nullptr, *g = nullptr, *lr = nullptr;
+    double *part = nullptr, *red = nullptr;
+    rc = check_hip(hipMalloc(&v, (size_t)n * sizeof(float)), "norm scratch");
+    if (!rc) rc = check_hip(hipMalloc(&g, (size_t)n * sizeof(float)), "norm scratch");
+    if (!rc) rc = check_hip(hipMalloc(&lr, (size_t)mlr * sizeof(float)), "norm scratch");
+    if (!rc) rc = check_hip(hipMalloc(&part, 2 * (size_t)blocks(n) * sizeof(double)), "norm scratch");
+    if (!rc) rc = check_hip(hipMalloc(&red, 2 * sizeof(double)), "norm scratch");
+    StepScalars s{};
+    if (!rc) {
+        ProfScope prof(DSNLM_K_LADMM, st);
+        hipLaunchKernelGGL(k_fill_hash, dim3(blocks(n)), dim3(256), 0, st, v, n);
+        // normalise the start vector: reuse dot2 with g = v
+        hipLaunchKernelGGL(k_dot2, dim3(blocks(n)), dim3(256), 0, st, v, v, n, part);
+        hipLaunchKernelGGL(k_dot2_final, dim3(1), dim3(256), 0, st, part, blocks(n), red);
+        hipLaunchKernelGGL(k_normalize, dim3(blocks(n)), dim3(256), 0, st, v, red, n);
+        for (int it = 0; it < iters; ++it) {
+            if (op->boundary == 0) {
+                hipLaunchKernelGGL(k_sr_forward<0>, dim3(blocks(mlr)), dim3(256), 0, st, v, nullptr, lr, ov.g, ov.taps);
+                hipLaunchKernelGGL(k_sr_adjoint_step<0>, dim3(blocks(n)), dim3(256), 0, st, lr, g, nullptr, nullptr,
+                                   nullptr, ov.g, ov.taps, s, 0);
+            } else {
+                hipLaunchKernelGGL(k_sr_forward<1>, dim3(blocks(mlr)), dim3(256), 0, st, v, nullptr, lr, ov.g, ov.taps);
+                hipLaunchKernelGGL(k_sr_adjoint_step<1>, dim3(blocks(n)), dim3(256), 0, st, lr, g, nullptr, nullptr,
+                                   nullptr, ov.g, ov.taps, s, 0);
+            }
+            hipLaunchKernelGGL(k_dot2, dim3(blocks(n)), dim3(256), 0, st, v, g, n, part);
+            hipLaunchKernelGGL(k_dot2_final, dim3(1), dim3(256), 0, st, part, blocks(n), red);
+            hipLaunchKernelGGL(k_scale_into, dim3(blocks(n)), dim3(256), 0, st, g, red, v, n);
+        }
+        rc = check_hip(hipGetLastError(), "power iteration");
+    }
+    double host[2] = {0, 0};
+    if (!rc) rc = check_hip(hipMemcpyAsync(host, red, sizeof(host), hipMemcpyDeviceToHost, st), "copy norm");
+    if (!rc) rc = check_hip(hipStreamSynchronize(st), "synchronise");
+    (void)hipFree(v);
+    (void)hipFree(g);
+    (void)hipFree(lr);
+    (void)hipFree(part);
+    (void)hipFree(red);
+    if (!rc) *out = (float)host[0];
+    return rc;
+}
+
+}  // extern "C"
