@@ -24,4 +24,6 @@ from .api import (  # noqa: F401
     LadmmParams,
 )
 
+from .autograd import DSNLMFunction, dsnlm  # noqa: F401,E402
+
 __version__ = "0.1.0"

@@ -112,6 +112,7 @@ void dsnlm_weights_destroy(dsnlm_weights* w) {
     (void)hipFree(w->bp);
     (void)hipFree(w->key);
     (void)hipFree(w->scratch);
+    (void)hipFree(w->bscratch);
     delete w;
 }
 

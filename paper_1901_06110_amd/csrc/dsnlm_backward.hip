@@ -1,0 +1,555 @@
+// Backward pass (vector-Jacobian product) of y = W(z, h) x on gfx950.
+//
+// The paper defines the forward map only (Section 3: eq. NLM, steps S1-S3,
+// Algorithm 2); the backward below is the chain rule through it, written in
+// gather form so that no pixel is ever updated by two threads (no atomics).
+// With a_{s,d} = Lambda_d exp(-kappa D_{s,d}), omega_s = sum_d a_{s,d},
+// c_s = omega_s^(-1/2), B'_s = c_s sum_d a c_{s+d} (x_{s+d} - x_s),
+// delta_s = c_s sum_d a c_{s+d}, m = delta_{s*} and y = x + B'/m:
+//
+//   B'bar = ybar / m,   mbar = -sum ybar B' / m^2,   f_s = [s = s*] mbar
+//   t_r = c_r B'bar_r,  w_r = c_r (f_r - B'bar_r x_r)
+//   U_s = sum_d a t_{s+d},  Wc_s = sum_d a w_{s+d}                 (sweep C)
+//   xbar = ybar - delta B'bar + c U                                 (= W ybar)
+//   cbar = B'bar B'/c + f delta/c + x U + Wc,  omegabar = -cbar c^3 / 2
+//   abar_{s,d} = omegabar_s + c_{s+d} (beta_s x_{s+d} + gamma_s),
+//        beta_s = c_s B'bar_s,  gamma_s = c_s (f_s - x_s B'bar_s)
+//   Dbar_{s,d} = -kappa a (abar_{s,d} + abar_{s+d,-d})            (both orders)
+//   hbar = -(1/h) sum_{s,d} Dbar_{s,d} D_{s,d}
+//   zbar(p) = 2 sum_d (z(p) - z(p+d)) sum_{|s-p| <= P} Dbar_{s,d}  (padded grid)
+//   dguide = fold of zbar through the mirror padding.
+// Sweep D recomputes D_{s,d} for an s-tile, forms Dbar_{s,d} in LDS, box-sums
+// it over the patch, and accumulates zbar for the s-tile's core pixels.
+#include <cmath>
+
+#include "internal.h"
+
+namespace dsnlm {
+
+namespace {
+
+__device__ __forceinline__ int reflect_clamp_b(int k, int n) {
+    if (k < 0) k = -k - 1;
+    if (k >= n) k = 2 * n - 1 - k;
+    k = k < 0 ? 0 : k;
+    k = k >= n ? n - 1 : k;
+    return k;
+}
+
+struct BwdArgs {
+    const float* x;      // image of the forward
+    const float* dy;     // cotangent of y
+    const float* c;      // c_s
+    const float* delta;  // delta_s
+    const float* bp;     // B'_s
+    const unsigned long long* key;  // (m, s*)
+    float* pairs;        // [2n] t, w  (input of sweep C)
+    float* cw;           // [2n] U, Wc (output of sweep C)
+    float* aux5;         // [5n] omegabar, beta, gamma, c, c x
+    float* dx;           // W ybar (nullable)
+    float* partials;     // per-block partial sums
+    float* mbar;         // device scalar
+    int n;
+};
+
+// B'bar, the (t, w) pairs, and per-block sums of ybar B'.
+__global__ void __launch_bounds__(256) k_bwd_prep(BwdArgs a) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    const float m = __uint_as_float((unsigned)(*a.key >> 32));
+    float part = 0.f;
+    if (idx < a.n) {
+        const float yb = a.dy[idx];
+        const float bb = yb / m;
+        const float cc = a.c[idx];
+        a.pairs[2 * idx] = cc * bb;
+        a.pairs[2 * idx + 1] = -cc * bb * a.x[idx];
+        part = yb * a.bp[idx];
+    }
+    __shared__ double sh[256];
+    sh[threadIdx.x] = part;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.partials[blockIdx.x] = (float)sh[0];
+}
+
+// mbar = -sum / m^2 (fixed-order reduction) and the f term of w at s*.
+__global__ void __launch_bounds__(256) k_bwd_mbar(BwdArgs a, int nblk) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) acc += a.partials[b];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const unsigned long long key = *a.key;
+        const float m = __uint_as_float((unsigned)(key >> 32));
+        const int sstar = (int)(~(unsigned)(key & 0xffffffffu));
+        const float mb = (float)(-sh[0] / ((double)m * m));
+        *a.mbar = mb;
+        a.pairs[2 * sstar + 1] += a.c[sstar] * mb;
+    }
+}
+
+// xbar, cbar and the per-pixel factors of sweep D.
+__global__ void __launch_bounds__(256) k_bwd_mid(BwdArgs a) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= a.n) return;
+    const unsigned long long key = *a.key;
+    const float m = __uint_as_float((unsigned)(key >> 32));
+    const int sstar = (int)(~(unsigned)(key & 0xffffffffu));
+    const float f = idx == sstar ? *a.mbar : 0.f;
+    const float yb = a.dy[idx];
+    const float bb = yb / m;
+    const float cc = a.c[idx];
+    const float dl = a.delta[idx];
+    const float xv = a.x[idx];
+    const float U = a.cw[2 * idx];
+    const float Wc = a.cw[2 * idx + 1];
+    if (a.dx) a.dx[idx] = yb - dl * bb + cc * U;
+    const float cbar = bb * a.bp[idx] / cc + f * dl / cc + xv * U + Wc;
+    const float obar = -0.5f * cbar * cc * cc * cc;
+    float* o = a.aux5 + 5 * (size_t)idx;
+    o[0] = obar;
+    o[1] = cc * bb;
+    o[2] = cc * (f - xv * bb);
+    o[3] = cc;
+    o[4] = cc * xv;
+}
+
+// ---- sweep D -----------------------------------------------------------
+// s-tile 32 x 32 (128 threads), core = the s-tile minus P on each side; the
+// cores tile the padded grid [-P, n+P)^2.
+template <int P, int S_CLASS>
+struct GeoD {
+    static constexpr int TH = 32, TW = 32;
+    static constexpr int R = 8, L = 8;
+    static constexpr int NT = TH * (TW / L);  // 128
+    static constexpr int TWE = TW + 2 * P;
+    static constexpr int NITEM1 = TWE * (TH / R);
+    static constexpr int ROUNDS1 = (NITEM1 + NT - 1) / NT;
+    static constexpr int CH = TH - 2 * P, CW = TW - 2 * P;  // core
+    static constexpr int ZW = TW + 2 * (S_CLASS + P);
+    static constexpr int AW = TW + 2 * S_CLASS + 1;          // aux5 row stride (pixels)
+    static constexpr int VW0 = ((TWE + 3) / 4) * 4;
+    static constexpr int VW = ((VW0 / 4) % 2) ? VW0 : VW0 + 4;
+    static constexpr int BW = TW + 2 * P + 1;                // Dbar / its vertical sums
+};
+
+template <int P, int S_CLASS>
+size_t lds_floats_d(int S) {
+    using G = GeoD<P, S_CLASS>;
+    const size_t ZH = G::TH + 2 * (S + P);
+    const size_t AH = G::TH + 2 * S;
+    size_t n = (ZH * G::ZW + 3) & ~(size_t)3;
+    n += (AH * G::AW * 5 + 3) & ~(size_t)3;
+    n += (size_t)2 * G::TH * G::VW;          // V (double buffer)
+    n += (size_t)G::TH * G::BW;              // Dbar
+    n += (size_t)G::TH * G::BW;              // vertical sums of Dbar
+    return n;
+}
+
+struct DArgs {
+    const float* z;      // guide
+    const float* aux5;   // [5n]
+    float* gz;           // padded-grid gradient (n1 + 2P) x (n2 + 2P)
+    float* hpart;        // per-block partial of sum Dbar D
+    int n1, n2;
+    float beta;          // log2(e) kappa
+    float kappa;
+    int tiles_x;         // core tiles along columns
+};
+
+template <int P, int S_CLASS>
+__global__ void __launch_bounds__(128) k_sweep_d(DArgs A, int S, HatTable hat) {
+    using G = GeoD<P, S_CLASS>;
+    constexpr int NT = G::NT, TH = G::TH, TW = G::TW, R = G::R, L = G::L;
+    constexpr int ZW = G::ZW, AW = G::AW, VW = G::VW, BW = G::BW;
+    constexpr int NE = R + 2 * P;
+    extern __shared__ __align__(16) float lds[];
+    const int tid = threadIdx.x;
+    const int n1 = A.n1, n2 = A.n2;
+    // core origin on the padded grid and the s-tile origin (image coordinates)
+    const int cti = blockIdx.x / A.tiles_x, ctj = blockIdx.x - cti * A.tiles_x;
+    const int ti0 = -P + cti * G::CH - P;  // s-tile row origin
+    const int tj0 = -P + ctj * G::CW - P;
+    const int ZH = TH + 2 * (S + P), ZWr = TW + 2 * (S + P);
+    const int AH = TH + 2 * S, AWr = TW + 2 * S;
+    float* Zs = lds;
+    int off = (ZH * ZW + 3) & ~3;
+    float* Aux = lds + off;
+    off += (AH * AW * 5 + 3) & ~3;
+    float* Vb = lds + off;
+    off += 2 * TH * VW;
+    float* Db = lds + off;
+    off += TH * BW;
+    float* VDb = lds + off;
+
+    for (int idx = tid; idx < ZH * ZWr; idx += NT) {
+        const int r = idx / ZWr, q = idx - r * ZWr;
+        const int gi = reflect_clamp_b(ti0 - S - P + r, n1);
+        const int gj = reflect_clamp_b(tj0 - S - P + q, n2);
+        Zs[r * ZW + q] = A.z[(size_t)gi * n2 + gj];
+    }
+    for (int idx = tid; idx < AH * AWr; idx += NT) {
+        const int r = idx / AWr, q = idx - r * AWr;
+        const int gi = ti0 - S + r, gj = tj0 - S + q;
+        const bool in = (unsigned)gi < (unsigned)n1 && (unsigned)gj < (unsigned)n2;
+        float* dst = Aux + 5 * (r * AW + q);
+        const float* src = A.aux5 + 5 * ((size_t)gi * n2 + gj);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) dst[k] = in ? src[k] : 0.f;
+    }
+    // zero the padding column of Dbar (read by the horizontal box sums)
+    for (int idx = tid; idx < TH * BW; idx += NT) {
+        Db[idx] = 0.f;
+        VDb[idx] = 0.f;
+    }
+    __syncthreads();
+
+    // phase-1 reference columns (registers)
+    float ref[G::ROUNDS1][NE];
+    int zoff[G::ROUNDS1], voff[G::ROUNDS1];
+#pragma unroll
+    for (int k1 = 0; k1 < G::ROUNDS1; ++k1) {
+        int it = tid + k1 * NT;
+        it = it < G::NITEM1 ? it : G::NITEM1 - 1;
+        const int strip = it / G::TWE;
+        const int c = it - strip * G::TWE;
+        zoff[k1] = (strip * R + S) * ZW + c + S;
+        voff[k1] = strip * R * VW + c;
+#pragma unroll
+        for (int q = 0; q < NE; ++q) ref[k1][q] = Zs[zoff[k1] + q * ZW];
+    }
+
+    const int pi = tid % TH;
+    const int pj = (tid / TH) * L;
+    const int gi = ti0 + pi;
+    // own per-pixel factors (zero outside the image)
+    float own[L][5];
+    bool sin[L], core[L];
+    float zown[L];
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        const float* src = Aux + 5 * ((pi + S) * AW + pj + k + S);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) own[k][q] = src[q];
+        const int gj = tj0 + pj + k;
+        sin[k] = (unsigned)gi < (unsigned)n1 && (unsigned)gj < (unsigned)n2;
+        core[k] = pi >= P && pi < TH - P && pj + k >= P && pj + k < TW - P;
+        zown[k] = Zs[(pi + S + P) * ZW + pj + k + S + P];
+    }
+    float accz[L];
+#pragma unroll
+    for (int k = 0; k < L; ++k) accz[k] = 0.f;
+    float hacc = 0.f;
+    const float beta = A.beta, kappa = A.kappa;
+
+    int buf = 0;
+    for (int dy = -S; dy <= S; ++dy) {
+        for (int dx = -S; dx <= S; ++dx) {
+            const float lg = hat.lg[dy + S] + hat.lg[dx + S];
+            float* V = Vb + buf * (TH * VW);
+            const int sh = dy * ZW + dx;
+            // phase 1: vertical box sums of e_d over the s-tile (+P columns)
+#pragma unroll
+            for (int k1 = 0; k1 < G::ROUNDS1; ++k1) {
+                if (tid + k1 * NT < G::NITEM1) {
+                    const float* zq = Zs + zoff[k1] + sh;
+                    float tq[NE];
+#pragma unroll
+                    for (int q = 0; q < NE; ++q) tq[q] = ref[k1][q] - zq[q * ZW];
+                    float v = 0.f;
+#pragma unroll
+                    for (int q = 0; q <= 2 * P; ++q) v = fmaf(tq[q], tq[q], v);
+                    float* vo = V + voff[k1];
+                    vo[0] = v;
+#pragma unroll
+                    for (int q = 1; q < R; ++q) {
+                        v = fmaf(tq[q + 2 * P], tq[q + 2 * P], v);
+                        v = fmaf(-tq[q - 1], tq[q - 1], v);
+                        vo[q * VW] = v;
+                    }
+                }
+            }
+            __syncthreads();
+            // phase 2: D, a, Dbar (both orders of the pair) -> LDS
+            {
+                const float* vr = V + pi * VW + pj;
+                constexpr int NV = ((L + 2 * P + 3) / 4) * 4;
+                float vv[NV];
+#pragma unroll
+                for (int q = 0; q < NV / 4; ++q) {
+                    const float4 t4 = reinterpret_cast<const float4*>(vr)[q];
+                    vv[4 * q + 0] = t4.x;
+                    vv[4 * q + 1] = t4.y;
+                    vv[4 * q + 2] = t4.z;
+                    vv[4 * q + 3] = t4.w;
+                }
+                float hs = 0.f;
+#pragma unroll
+                for (int q = 0; q <= 2 * P; ++q) hs += vv[q];
+                const bool rowok = (unsigned)(gi + dy) < (unsigned)n1;
+                const float* nb = Aux + 5 * ((pi + dy + S) * AW + pj + dx + S);
+#pragma unroll
+                for (int k = 0; k < L; ++k) {
+                    if (k > 0) hs += vv[k + 2 * P] - vv[k - 1];
+                    const float D = hs;
+                    const float a = __builtin_amdgcn_exp2f(lg - beta * D);
+                    const float* r5 = nb + 5 * k;
+                    // abar_{s,d} + abar_{s+d,-d}
+                    float as = own[k][0] + r5[0];
+                    as = fmaf(own[k][1], r5[4], as);
+                    as = fmaf(own[k][2], r5[3], as);
+                    as = fmaf(r5[1], own[k][4], as);
+                    as = fmaf(r5[2], own[k][3], as);
+                    const bool ok = sin[k] && rowok && (unsigned)(tj0 + pj + k + dx) < (unsigned)n2;
+                    const float db = ok ? -kappa * a * as : 0.f;
+                    if (core[k]) hacc = fmaf(db, D, hacc);
+                    Db[pi * BW + pj + k + P] = db;
+                }
+            }
+            __syncthreads();
+            // phase 3: vertical box sums of Dbar for the core rows
+            for (int idx = tid; idx < G::CH * TW; idx += NT) {
+                const int r = P + idx / TW, c = idx - (idx / TW) * TW;
+                float v = 0.f;
+#pragma unroll
+                for (int t = -P; t <= P; ++t) v += Db[(r + t) * BW + c + P];
+                VDb[r * BW + c + P] = v;
+            }
+            __syncthreads();
+            // phase 4: horizontal box sums -> G, accumulate zbar on the core
+            {
+                const float* vr = VDb + pi * BW + pj;  // column pj + k - P + P
+                float hs = 0.f;
+#pragma unroll
+                for (int q = 0; q <= 2 * P; ++q) hs += vr[q];
+                const float* zq = Zs + (pi + S + P + dy) * ZW + pj + S + P + dx;
+#pragma unroll
+                for (int k = 0; k < L; ++k) {
+                    if (k > 0) hs += vr[k + 2 * P] - vr[k - 1];
+                    accz[k] = fmaf(2.f * (zown[k] - zq[k]), hs, accz[k]);
+                }
+            }
+            buf ^= 1;
+        }
+    }
+    // write zbar on the core (padded-grid coordinates, offset by P)
+    const int W2 = n2 + 2 * P;
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        const int gj = tj0 + pj + k;
+        if (core[k] && gi >= -P && gi < n1 + P && gj >= -P && gj < n2 + P)
+            A.gz[(size_t)(gi + P) * W2 + gj + P] = accz[k];
+    }
+    // block partial of sum Dbar D (fixed order: LDS tree in the V buffer,
+    // whose last reads were in phase 2, two barriers ago)
+    float* red = Vb;
+    red[tid] = hacc;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) A.hpart[blockIdx.x] = red[0];
+}
+
+// dguide(q) = sum of zbar over the padded positions that mirror onto q.
+__global__ void __launch_bounds__(256) k_fold(const float* __restrict__ gz, float* __restrict__ dz, int n1,
+                                              int n2, int P) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= n1 * n2) return;
+    const int i = idx / n2, j = idx - i * n2;
+    int pi[3], pj[3];
+    int ci = 0, cj = 0;
+    pi[ci++] = i;
+    if (i <= P - 1) pi[ci++] = -1 - i;
+    if (i >= n1 - P) pi[ci++] = 2 * n1 - 1 - i;
+    pj[cj++] = j;
+    if (j <= P - 1) pj[cj++] = -1 - j;
+    if (j >= n2 - P) pj[cj++] = 2 * n2 - 1 - j;
+    const int W2 = n2 + 2 * P;
+    float acc = 0.f;
+    for (int a = 0; a < ci; ++a)
+        for (int b = 0; b < cj; ++b) acc += gz[(size_t)(pi[a] + P) * W2 + pj[b] + P];
+    dz[idx] = acc;
+}
+
+// dh = -(1/h) sum of the block partials (fixed order).
+__global__ void __launch_bounds__(256) k_dh(const float* __restrict__ hpart, int nblk, float h,
+                                            float* __restrict__ dh) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) acc += hpart[b];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *dh = (float)(-sh[0] / h);
+}
+
+template <int P, int S_CLASS>
+hipError_t launch_d(const DArgs& a, int S, int nblk, hipStream_t st) {
+    auto kern = k_sweep_d<P, S_CLASS>;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           160 * 1024);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const size_t lds = lds_floats_d<P, S_CLASS>(S) * sizeof(float);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    HatTable hat = make_hat(S);
+    hipLaunchKernelGGL(kern, dim3(nblk), dim3(GeoD<P, S_CLASS>::NT), lds, st, a, S, hat);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_d_s(const DArgs& a, int S, int nblk, hipStream_t st) {
+    if (S <= 12) return launch_d<P, 12>(a, S, nblk, st);
+    return launch_d<P, kMaxS>(a, S, nblk, st);
+}
+
+hipError_t launch_sweep_d(const DArgs& a, int S, int P, int nblk, hipStream_t st) {
+    switch (P) {
+        case 0: return launch_d_s<0>(a, S, nblk, st);
+        case 1: return launch_d_s<1>(a, S, nblk, st);
+        case 2: return launch_d_s<2>(a, S, nblk, st);
+        case 3: return launch_d_s<3>(a, S, nblk, st);
+        case 4: return launch_d_s<4>(a, S, nblk, st);
+        case 5: return launch_d_s<5>(a, S, nblk, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+inline int blocks256(size_t n) { return (int)((n + 255) / 256); }
+
+}  // namespace
+
+size_t sweep_d_lds_bytes(int S, int P) {
+    const int SC = S <= 12 ? 12 : kMaxS;
+    const size_t TH = 32, TW = 32;
+    const size_t ZW = TW + 2 * (SC + P), AW = TW + 2 * SC + 1, VW = TW + 2 * P + 8, BW = TW + 2 * P + 1;
+    const size_t n = (TH + 2 * (S + P)) * ZW + (TH + 2 * S) * AW * 5 + 2 * TH * VW + 2 * TH * BW + 16;
+    return n * sizeof(float);
+}
+
+ImgDesc base_desc(const dsnlm_weights* w);
+bool overlaps(const void* a, const void* b, size_t bytes);
+
+// Scratch (floats) needed by dsnlm_apply_backward for an n1 x n2 image.
+size_t backward_scratch_floats(int n1, int n2, int S, int P) {
+    (void)S;
+    const size_t n = (size_t)n1 * n2;
+    const int CH = 32 - 2 * P, CW = 32 - 2 * P;
+    const size_t tiles = (size_t)((n1 + 2 * P + CH - 1) / CH) * ((n2 + 2 * P + CW - 1) / CW);
+    return 2 * n + 2 * n + 5 * n + (size_t)(n1 + 2 * P) * (n2 + 2 * P) + blocks256(n) + tiles + 8;
+}
+
+int enqueue_backward(dsnlm_weights* w, const float* x, const float* dy, float* dx, float* dguide, float* dh,
+                     float* scratch, hipStream_t st) {
+    const int n1 = w->n1, n2 = w->n2, S = w->S, P = w->P;
+    const size_t n = (size_t)n1 * n2;
+    float* pairs = scratch;
+    float* cw = pairs + 2 * n;
+    float* aux5 = cw + 2 * n;
+    float* gz = aux5 + 5 * n;
+    float* partials = gz + (size_t)(n1 + 2 * P) * (n2 + 2 * P);
+    const int nb = blocks256(n);
+    const int CH = 32 - 2 * P, CW = 32 - 2 * P;
+    const int tiles_y = (n1 + 2 * P + CH - 1) / CH, tiles_x = (n2 + 2 * P + CW - 1) / CW;
+    float* hpart = partials + nb;
+    float* mbar = hpart + (size_t)tiles_y * tiles_x;
+
+    BwdArgs a{};
+    a.x = x;
+    a.dy = dy;
+    a.c = w->c;
+    a.delta = w->delta;
+    a.bp = w->bp;
+    a.key = w->key;
+    a.pairs = pairs;
+    a.cw = cw;
+    a.aux5 = aux5;
+    a.dx = dx;
+    a.partials = partials;
+    a.mbar = mbar;
+    a.n = (int)n;
+    {
+        ProfScope prof(DSNLM_K_BWD_PREP, st);
+        hipLaunchKernelGGL(k_bwd_prep, dim3(nb), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_bwd_mbar, dim3(1), dim3(256), 0, st, a, nb);
+        int rc = check_hip(hipGetLastError(), "backward prep");
+        if (rc) return rc;
+    }
+    ImgDesc d = base_desc(w);
+    d.x = x;
+    d.aux_in = pairs;
+    d.aux_out = cw;
+    int rc = check_hip(launch_sweep(kPassC, S, P, d, nullptr, nullptr, 0, st), "backward sweep C");
+    if (rc) return rc;
+    {
+        ProfScope prof(DSNLM_K_BWD_PREP, st);
+        hipLaunchKernelGGL(k_bwd_mid, dim3(nb), dim3(256), 0, st, a);
+        rc = check_hip(hipGetLastError(), "backward mid");
+        if (rc) return rc;
+    }
+    if (!dguide && !dh) return DSNLM_OK;
+    DArgs da{};
+    da.z = w->guide;
+    da.aux5 = aux5;
+    da.gz = gz;
+    da.hpart = hpart;
+    da.n1 = n1;
+    da.n2 = n2;
+    da.beta = d.beta;
+    da.kappa = d.kappa;
+    da.tiles_x = tiles_x;
+    {
+        ProfScope prof(DSNLM_K_PASS_D, st);
+        rc = check_hip(launch_sweep_d(da, S, P, tiles_y * tiles_x, st), "backward sweep D");
+        if (rc) return rc;
+    }
+    ProfScope prof(DSNLM_K_BWD_TAIL, st);
+    if (dguide) hipLaunchKernelGGL(k_fold, dim3(nb), dim3(256), 0, st, gz, dguide, n1, n2, P);
+    if (dh) hipLaunchKernelGGL(k_dh, dim3(1), dim3(256), 0, st, hpart, tiles_y * tiles_x, w->h, dh);
+    return check_hip(hipGetLastError(), "backward tail");
+}
+
+}  // namespace dsnlm
+
+using namespace dsnlm;
+
+extern "C" int dsnlm_apply_backward(const dsnlm_weights* wc, const float* x, const float* dy, float* dx,
+                                    float* dguide, float* dh, void* stream) {
+    if (!wc || !x || !dy) return fail(DSNLM_EINVAL, "dsnlm_apply_backward: null pointer");
+    dsnlm_weights* w = const_cast<dsnlm_weights*>(wc);
+    if (!w->applied)
+        return fail(DSNLM_EINVAL, "dsnlm_apply_backward: the handle holds no forward to differentiate");
+    if ((dguide || dh) && sweep_d_lds_bytes(w->S, w->P) > 160 * 1024)
+        return fail(DSNLM_EUNSUPPORTED, "dsnlm_apply_backward: guide/bandwidth gradients support S <= 16");
+    const size_t bytes = (size_t)w->n1 * w->n2 * sizeof(float);
+    if (dx && (overlaps(dx, x, bytes) || overlaps(dx, dy, bytes)))
+        return fail(DSNLM_EINVAL, "dsnlm_apply_backward: dx overlaps x or dy");
+    if (dguide && (overlaps(dguide, x, bytes) || overlaps(dguide, dy, bytes)))
+        return fail(DSNLM_EINVAL, "dsnlm_apply_backward: dguide overlaps x or dy");
+    const size_t need = backward_scratch_floats(w->n1, w->n2, w->S, w->P);
+    if (w->bscratch_cap < need) {
+        if (w->bscratch) (void)hipFree(w->bscratch);
+        w->bscratch = nullptr;
+        w->bscratch_cap = 0;
+        int rc = check_hip(hipMalloc(&w->bscratch, need * sizeof(float)), "backward scratch");
+        if (rc) return rc;
+        w->bscratch_cap = need;
+    }
+    return enqueue_backward(w, x, dy, dx, dguide, dh, w->bscratch, static_cast<hipStream_t>(stream));
+}

@@ -139,7 +139,7 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
                 const size_t p = (size_t)gi * n2 + gj;
                 if constexpr (MODE == kPassC) {
                     // backward: t_r = c_r B'bar_r, w_r = c_r (f_r - B'bar_r x_r)
-                    v = reinterpret_cast<const float2*>(d.cbar_aux)[p];
+                    v = reinterpret_cast<const float2*>(d.aux_in)[p];
                 } else {
                     const float cc = d.c[p];
                     v.x = cc;
@@ -321,7 +321,7 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
                     d.c[p] = 1.0f / sqrtf(acc0[k]);
                 } else if constexpr (MODE == kPassC) {
                     // acc0 = sum a t_r, acc1 = sum a w_r
-                    reinterpret_cast<float2*>(d.cbar_aux)[p] = make_float2(acc0[k], acc1[k]);
+                    reinterpret_cast<float2*>(d.aux_out)[p] = make_float2(acc0[k], acc1[k]);
                 } else {
                     const float cs = reinterpret_cast<const float2*>(Aux)[(pi + S) * AW + pj + k + S].x;
                     if constexpr (MODE == kPassBApply || MODE == kApply) {

@@ -29,13 +29,8 @@ struct ImgDesc {
     float* bp;             // B'_s = c_s sum_r a c_r (x_r - x_s)
     unsigned long long* key;  // packed (bits(m) << 32) | (~argmax)
     // backward
-    const float* dy;       // cotangent of y
-    float* dx;             // W dy
-    float* cbar_aux;       // per-pixel arrays used by the backward sweeps
-    float* gz;             // gradient w.r.t. the padded guide ((n1+2P) x (n2+2P))
-    float* dz;             // gradient w.r.t. the guide
-    float* hpart;          // per-tile partial sums for dh
-    float* mbar;           // device scalar: derivative of the loss w.r.t. m
+    const float* aux_in;   // per-pixel float2 inputs of the backward sweep C
+    float* aux_out;        // its per-pixel float2 outputs
     int n1, n2;
     float beta;            // log2(e) / (2 (2P+1)^2 h^2)
     float kappa;           // 1 / (2 (2P+1)^2 h^2)
@@ -81,9 +76,12 @@ hipError_t launch_epilogue(const ImgDesc& one, const ImgDesc* batch, const TileR
                            int ntiles, int S, int P, hipStream_t st);
 
 // Backward launchers (dsnlm_backward.hip).
-hipError_t launch_backward(const ImgDesc& d, int S, int P, hipStream_t st, void* scratch,
-                           size_t scratch_bytes);
-size_t backward_scratch_bytes(int n1, int n2, int S, int P);
+// Backward (dsnlm_backward.hip): LDS bytes of sweep D and the largest S it
+// supports for patch half-width P.
+size_t sweep_d_lds_bytes(int S, int P);
+int enqueue_backward(dsnlm_weights* w, const float* x, const float* dy, float* dx, float* dguide,
+                     float* dh, float* scratch, hipStream_t st);
+size_t backward_scratch_floats(int n1, int n2, int S, int P);
 
 // Brackets one kernel launch with events when instrumentation is enabled.
 class ProfScope {
@@ -118,5 +116,7 @@ struct dsnlm_weights {
     float* scratch;    // solver scratch (grow-only), freed with the handle
     size_t scratch_cap;
     float* zbuf;       // denoiser input x + u inside the solver (in scratch)
+    float* bscratch;   // backward scratch (grow-only), freed with the handle
+    size_t bscratch_cap;
     bool applied;      // bp holds B' of the last apply
 };

@@ -123,7 +123,7 @@ extern "C" int dsnlm_tune(const float* guide, int n1, int n2, int S, int P, floa
     if (rc) return rc;
     const size_t n = (size_t)n1 * n2;
     float* scratch = nullptr;  // y and the backward per-pixel pair array
-    rc = check_hip(hipMalloc(&scratch, 3 * n * sizeof(float)), "dsnlm_tune scratch");
+    rc = check_hip(hipMalloc(&scratch, 5 * n * sizeof(float)), "dsnlm_tune scratch");
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (!rc) rc = check_hip(hipEventCreate(&e0), "event");
     if (!rc) rc = check_hip(hipEventCreate(&e1), "event");
@@ -131,7 +131,8 @@ extern "C" int dsnlm_tune(const float* guide, int n1, int n2, int S, int P, floa
     ImgDesc d = base_desc(w);
     d.x = w->guide;
     d.y = scratch;
-    d.cbar_aux = scratch + n;
+    d.aux_in = scratch + n;       // timing only: the values are irrelevant
+    d.aux_out = scratch + 3 * n;
     // build once so c, delta and m hold meaningful values
     if (!rc) rc = check_hip(launch_sweep(kPassA, S, P, d, nullptr, nullptr, 0, st), "tune build");
     if (!rc) rc = check_hip(launch_sweep(kPassBApply, S, P, d, nullptr, nullptr, 0, st), "tune build");
