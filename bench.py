@@ -24,16 +24,35 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Peak rates of one MI355X used for the roofline (derivation in the design notes):
-# 256 CUs x 64 FP32 lanes x 2.4 GHz = 39.3e12 non-packed FP32 VALU lane-ops/s;
-# a transcendental (v_exp_f32) occupies 4 lane-op slots.
+# Peak rate of one MI355X used for the roofline: 256 CUs x 64 FP32 lanes x
+# 2.4 GHz = 39.3e12 non-packed FP32 VALU lane-ops/s (the library is built
+# without packed FP32 ops).  A v_exp_f32 occupies EXP_SLOTS lane-op slots;
+# the value is measured on the device by dsnlm_peak_probe (4 = quarter rate
+# is the fallback when the probe is unavailable).
 VALU_LANE_OPS_PER_S = 256 * 64 * 2.4e9
-EXP_SLOTS = 4
-# Algorithmic work per (pixel, in-window shift), in lane-op slots:
-#   weight: diff 1 + square 1 + separable sliding box 4 + exponent 1 + exp2 (4)
+EXP_SLOTS_FALLBACK = 4.0
+# Algorithmic FP32 VALU ops per (pixel, in-window shift), transcendental apart:
+#   weight: diff 1 + square 1 + separable sliding box 4 + exponent 1 (+ 1 exp)
 #   pass A adds 1 (accumulate omega); pass B adds 2 (two FMAs)
-OPS_PASS_A = 8 + EXP_SLOTS
-OPS_PASS_B = 9 + EXP_SLOTS
+VALU_PASS_A = 8
+VALU_PASS_B = 9
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweep_batched64_S10P3.md")
+
+
+def measured_traffic(kind: str):
+    """HBM bytes per launch from the committed counter summary, or None when
+    the kernel source changed after the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+        src = open(os.path.join(ROOT, "paper_1901_06110_amd", "csrc", "dsnlm_sweep.hip"), "rb").read()
+    except OSError:
+        return None
+    vals = dict(l.split(": ", 1) for l in text.splitlines() if ": " in l and not l.startswith(("|", "#")))
+    if vals.get("source_sha256_dsnlm_sweep.hip", "").strip() != hashlib.sha256(src).hexdigest():
+        return None
+    v = vals.get(f"traffic_bytes_per_launch_{kind}")
+    return float(v) if v else None
 
 
 def window_pairs(n1: int, n2: int, S: int) -> int:
@@ -69,6 +88,86 @@ def cpu_baseline(images, S, P, budget_s: float = 20.0):
                        f"{done_px} px in {dt:.1f} s (FP64 shift loop, torch CPU)")
 
 
+def fwd_bwd_ratio(M, xs, hs, S, P, steps):
+    """Time the forward alone and forward + backward (input, guide and h
+    gradients) over the batch with per-image launches; return the ratio."""
+    import torch
+    ys, handles, ybars = [], [], []
+    for x, h in zip(xs, hs):
+        y, w = M.dsnlm_forward(x, None, S, P, h, keep=True)
+        ys.append(y)
+        handles.append(w)
+        ybars.append(2.0 * (y - x))
+    outs = [(torch.empty_like(x), torch.empty_like(x)) for x in xs]
+
+    def fwd():
+        for x, y, h, w in zip(xs, ys, hs, handles):
+            M.dsnlm_forward(x, None, S, P, h, y=y, weights=w)
+
+    def fwd_bwd():
+        fwd()
+        for x, w, yb in zip(xs, handles, ybars):
+            M.dsnlm_apply_backward(w, x, yb)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    tf = timed(fwd)
+    tfb = timed(fwd_bwd)
+    return {"fwd_ms": tf, "fwd_bwd_ms": tfb, "ratio": tfb / tf,
+            "fwd_bwd_mpx_s": sum(x.numel() for x in xs) / (tfb * 1e-3) / 1e6,
+            "note": "per-image launches, 64 images, S=10, P=3; backward = d/dx, d/dguide, d/dh"}
+
+
+def ladmm_sr_timing(M, S, P):
+    """2x super-resolution of a 512x512 synthetic image: 50 iterations of
+    Algorithm 1, weights rebuilt for 5 iterations then frozen (graph-captured)."""
+    import numpy as np
+    import torch
+    import synth
+    cfg = synth.config1_inputs(512)
+    b = np.exp(-np.arange(-4, 5) ** 2 / 2.0)
+    taps = (b / b.sum()).astype(np.float32)
+    op = M.SROperator(n1=512, n2=512, taps=taps, factor=2, y=None, boundary=0)
+    xc = torch.as_tensor(cfg["clean"]).cuda()
+    y = M.ladmm_apply_forward(op, xc) + torch.as_tensor(cfg["lr_noise"]).cuda()
+    op.y = y
+    x0 = torch.as_tensor(synth.bicubic_upsample(y.cpu().numpy(), 2)).cuda()
+    gamma = 1.0 / M.ladmm_operator_norm2(op, 300)
+    prm = M.LadmmParams(lam=cfg["lam"], rho=cfg["rho"], gamma=gamma, S=S, P=P, h=cfg["h"],
+                        freeze_after=cfg["freeze_after"], iters=cfg["iters"])
+    res = torch.zeros((cfg["iters"], 2), device="cuda")
+    st = torch.cuda.Stream()
+    times = []
+    for rep in range(3):
+        x, v, u = x0.clone(), x0.clone(), torch.zeros_like(x0)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(st):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            M.ladmm_solve(op, prm, x, v, u, residuals=res)
+            e1.record(st)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    err0 = float(torch.sqrt(torch.mean((x0 - xc) ** 2)))
+    err = float(torch.sqrt(torch.mean((x - xc) ** 2)))
+    return {"ms_per_solve": min(times), "iters": cfg["iters"], "freeze_after": cfg["freeze_after"],
+            "rmse_bicubic": err0, "rmse_ladmm": err,
+            "final_primal_residual": float(res[-1, 0]), "final_dual_residual": float(res[-1, 1]),
+            "note": "includes weight rebuilds (5), frozen applies (45), graph capture and one "
+                    "host synchronisation per solve"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +176,8 @@ def main():
     ap.add_argument("--mode", choices=["batched", "perimage"], default="batched")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--count", type=int, default=64)
+    ap.add_argument("--no-ladmm", action="store_true", help="skip the LADMM solve timing")
+    ap.add_argument("--no-fb", action="store_true", help="skip the forward+backward timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -142,12 +243,30 @@ def main():
         lib.dsnlm_profile_query(kind, C.byref(t), C.byref(n))
         tot[name] = (t.value, n.value)
     lib.dsnlm_profile_enable(0)
+    # ---- measured peak rates of this device (context for the roofline)
+    probes = {}
+    for kind, name in [(0, "fp32_fma_flop_s"), (1, "exp_per_s"), (2, "hbm_copy_bytes_s")]:
+        r = C.c_double()
+        if lib.dsnlm_peak_probe(kind, C.byref(r), C.c_void_p(torch.cuda.current_stream().cuda_stream)) == 0:
+            probes[name] = r.value
+    if "fp32_fma_flop_s" in probes and "exp_per_s" in probes:
+        probes["exp_cost_in_fma_slots"] = probes["fp32_fma_flop_s"] / 2 / probes["exp_per_s"]
+
+    exp_slots = probes.get("exp_cost_in_fma_slots", EXP_SLOTS_FALLBACK)
     pb_ms, pb_n = tot["pass_b"]
     launches_per_step = pb_n / prof_steps
     pb_avg_ms = pb_ms / max(pb_n, 1)
-    ops_per_launch = OPS_PASS_B * pairs / launches_per_step
+    ops_pair_b = VALU_PASS_B + exp_slots
+    ops_pair_a = VALU_PASS_A + exp_slots
+    ops_per_launch = ops_pair_b * pairs / launches_per_step
     achieved = ops_per_launch / (pb_avg_ms * 1e-3) / 1e12
     peak = VALU_LANE_OPS_PER_S / 1e12
+
+    # ---- forward + backward vs forward, per-image launches over the batch
+    fb = None if args.no_fb else fwd_bwd_ratio(M, xs, hs, S, P, steps=max(1, min(args.steps, 3)))
+
+    # ---- linearized PnP-ADMM super-resolution solve (512x512, 50 iterations)
+    lad = ladmm_sr_timing(M, S, P) if not args.no_ladmm else None
 
     out = {
         "metric": "DSG-NLM Mpixel/s @21x21 search, 7x7 patch (forward)",
@@ -174,13 +293,19 @@ def main():
             "peak": peak,
             "unit": "Tops/s",
             "frac": achieved / peak,
-            "traffic": None,
-            "ops_per_pair": OPS_PASS_B,
+            "frac_vs_packed_fp32_peak": achieved / (2 * peak),
+            "traffic": measured_traffic("pass_b"),
+            "ops_per_pair": ops_pair_b,
+            "exp_slots": exp_slots,
             "pairs_per_launch": pairs / launches_per_step,
             "avg_launch_ms": pb_avg_ms,
         },
         "kernel_ms_per_step": {k: v[0] / prof_steps for k, v in tot.items()},
-        "forward_roofline_frac": (OPS_PASS_A + OPS_PASS_B) * pairs / (ms * 1e-3) / VALU_LANE_OPS_PER_S,
+        "measured_peaks": probes,
+        "fwd_bwd_over_fwd": fb["ratio"] if fb else None,
+        "fwd_bwd": fb,
+        "ladmm_sr_512": lad,
+        "forward_roofline_frac": (ops_pair_a + ops_pair_b) * pairs / (ms * 1e-3) / VALU_LANE_OPS_PER_S,
         "wall_s_timed": wall,
     }
     if not args.no_cpu:

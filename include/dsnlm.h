@@ -108,7 +108,7 @@ const float* dsnlm_weights_array(const dsnlm_weights* w, int which);
 
 /* ----------------------------------------------------------------------- */
 /* Many images of uneven sizes denoised together: one launch per sweep for  */
-/* the whole batch, each image with its own m (spec batching form).   */
+/* the whole batch, each image with its own m.                              */
 typedef struct {
     const float* guide; /* device, n1*n2 */
     const float* x;     /* device, n1*n2 (may equal guide) */
@@ -234,6 +234,13 @@ int dsnlm_tune_get(int kind, int S, int P, int* variant);
  * image used for timing), `reps` launches each, and keep the fastest.
  * Synchronous. */
 int dsnlm_tune(const float* guide, int n1, int n2, int S, int P, float h, int reps, void* stream);
+
+/* Measured peak of one rate on the current device, used as a roofline
+ * denominator: kind 0 = FP32 FMA throughput in FLOP/s (2 per FMA, non-packed
+ * VALU), 1 = v_exp_f32 throughput in exp/s, 2 = HBM copy bandwidth in bytes/s
+ * (1 GiB read + 1 GiB written per launch).  Synchronous; allocates 2 GiB for
+ * kind 2. */
+int dsnlm_peak_probe(int kind, double* rate, void* stream);
 
 /* Library version string. */
 const char* dsnlm_version(void);

@@ -7,15 +7,18 @@ What is computed (Section 3 of the paper):
 
 * patches P_s of side N_p = 2P+1 centred at each pixel s (eq. NLM); pixels of
   a patch that fall outside the image take the half-sample symmetric mirror of
-  the guide (index -1 -> 0, n -> n-1; the paper is silent, reading R4);
+  the guide (index -1 -> 0, n -> n-1; the paper does not say how patches
+  at the border are formed);
 * kernel k_{s,r} = exp(-||P_s - P_r||^2 / (2 N_p^2 h^2)) for r in the search
   window Omega_s = {r in the image : ||r - s||_inf <= S}; the window is cut at
-  the image border and includes r = s (eq. NLM; readings R1, R3, R6);
+  the image border and includes r = s (eq. NLM, with the bandwidth h in
+  place of the paper's sigma);
 * step S1: w = Lambda_{s,r} k_{s,r}, Lambda the separable hat with argument
   (s - r)/(S + 1);
 * step S2: w <- w (row sum_s)^(-1/2) (column sum_r)^(-1/2);
 * step S3: with m the largest row sum after S2, w <- w/m and then the diagonal
-  w_ss <- 1 + w_ss - sum_r w_sr (the sum includes the diagonal, reading R9);
+  w_ss <- 1 + w_ss - sum_r w_sr (the sum includes the diagonal term, which
+  makes every row sum exactly one);
 * output W x.  Algorithm 2 computes the same product with three aggregation
   loops over (pixel, window) pairs without storing W.
 
@@ -226,7 +229,8 @@ def dsnlm_shifts(x, z, S: int, P: int, h, want: str = "y") -> dict:
     and through h when they are tensors that require grad).
     Returns a dict with y (= W x), omega (loop-1 image g), delta (loop-2 row
     sums), m (their maximum), argmax (flat index of the first maximal delta,
-    which is where the derivative of the max is routed, reading R10).
+    which is where the derivative of the max is routed; the paper does not
+    differentiate, so ties are broken towards the lowest index).
     """
     xt = _as_t(x)
     zt = _as_t(z)

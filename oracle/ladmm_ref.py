@@ -8,19 +8,22 @@ factor*I, phase 0) after a blur with kernel b (a separable, normalised Gaussian
 in the experiments).  Pixels of the blur support outside the image take the
 half-sample symmetric mirror ("symmetric boundary") or wrap around
 ("periodic").  f(x) = 1/2 ||A x - y||^2 (eq. dataterm) with gradient
-A^T (A x - y) -- the paper prints A^T (y - A x), the negative gradient;
-reading R13.
+A^T (A x - y); the paper prints A^T (y - A x), which is the negative
+gradient, so the sign is taken from the data term itself.
 
 Single-photon imaging (Section 4.2): f(x) = sum_i phi(x_i) with
 phi(t) = K0 eta t / K - K1 log(1 - exp(-eta t / K)) (eq. obj) and derivative
 phi'(t) = (eta/K) (K0 - K1 exp(-eta t/K) / (1 - exp(-eta t/K))) (eq. photongrad),
-evaluated at max(t, t_min) (reading R18).
+evaluated at max(t, t_min) so that the logarithm stays finite at t = 0
+(the paper leaves the behaviour at the origin open).
 
 Algorithm 1 (Section 2): mu = 1/(alpha + rho); loop
   x <- mu (alpha x + rho (v - u) - grad f(x));  x <- Pi_C(x);
   v <- D(x + u);  u <- u + x - v.
 Here D is DSG-NLM with guide x + u (adaptive) for the first k0 iterations and
-the weights of iteration k0 afterwards (fixed); alpha = 1/gamma (reading R12).
+the weights of iteration k0 afterwards (fixed).  The caller passes alpha
+directly; the C library takes gamma = 1/alpha, so that gamma = 1/||A||^2
+gives alpha = lambda_max(A^T A), the Lipschitz constant of grad f.
 """
 from __future__ import annotations
 

@@ -95,6 +95,7 @@ def _load():
         "dsnlm_tune_set": (i, [i, i, i, i]),
         "dsnlm_tune_get": (i, [i, i, i, C.POINTER(i)]),
         "dsnlm_tune": (i, [vp, i, i, i, i, f, i, vp]),
+        "dsnlm_peak_probe": (i, [i, C.POINTER(C.c_double), vp]),
         "dsnlm_profile_enable": (i, [i]),
         "dsnlm_profile_query": (i, [i, C.POINTER(C.c_double), C.POINTER(i)]),
         "dsnlm_profile_reset": (i, []),
@@ -124,7 +125,7 @@ EXPORTED = [
     "dsnlm_forward_batched", "ladmm_step", "ladmm_solve", "ladmm_apply_forward",
     "ladmm_gradient", "ladmm_operator_norm2", "dsnlm_last_error", "dsnlm_version",
     "dsnlm_profile_enable", "dsnlm_profile_query", "dsnlm_profile_reset",
-    "dsnlm_tune_set", "dsnlm_tune_get", "dsnlm_tune",
+    "dsnlm_tune_set", "dsnlm_tune_get", "dsnlm_tune", "dsnlm_peak_probe",
 ]
 
 K_PASS_A, K_PASS_B, K_APPLY, K_EPILOGUE, K_BWD_PREP, K_PASS_C, K_PASS_D, K_BWD_TAIL, K_LADMM = range(9)
