@@ -53,7 +53,14 @@ struct Geo {
     static constexpr int TWE = TW + 2 * P;   // tile widened by the patch
     static constexpr int NITEM1 = TWE * (TH / R);
     static constexpr int ROUNDS1 = (NITEM1 + NT - 1) / NT;
-    static constexpr int ZW = TW + 2 * (S_CLASS + P);  // guide tile row stride
+    // guide tile, stored column-major: column stride ZC (odd, so lanes that
+    // walk along columns hit distinct banks) and at most ZWmax columns
+    // (+ GWIN - 1 rows of slack: the register window of the grouped schedule
+    // may read past the last valid row of a column; those values are unused)
+    static constexpr int GWIN = 7;
+    static constexpr int ZC0 = TH + 2 * (S_CLASS + P) + GWIN - 1;
+    static constexpr int ZC = (ZC0 % 2) ? ZC0 : ZC0 + 1;
+    static constexpr int ZWmax = TW + 2 * (S_CLASS + P);
     // aux row stride: odd, so lanes walking down rows hit distinct banks
     static constexpr int AW = ((TW + 2 * S_CLASS) % 2) ? (TW + 2 * S_CLASS) : (TW + 2 * S_CLASS + 1);
     // V row stride: 4 * odd, for conflict-free float4 reads down rows
@@ -69,9 +76,9 @@ constexpr int naux(int mode) { return mode == kPassA ? 0 : 2; }
 template <int P, int S_CLASS>
 size_t lds_floats(int S, int mode) {
     using G = Geo<P, S_CLASS>;
-    const size_t ZH = G::TH + 2 * (S + P);
+    const size_t ZWr = G::TW + 2 * (S + P);
     const size_t AH = G::TH + 2 * S;
-    size_t n = (ZH * G::ZW + 3) & ~(size_t)3;
+    size_t n = (ZWr * G::ZC + 3) & ~(size_t)3;
     n += (AH * G::AW * naux(mode) + 3) & ~(size_t)3;
     n += (size_t)2 * G::TH * G::VW;
     return n;
@@ -92,7 +99,7 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
         HatTable hat) {
     using G = Geo<P, S_CLASS>;
     constexpr int NT = G::NT, TH = G::TH, TW = G::TW, R = G::R, L = G::L;
-    constexpr int ZW = G::ZW, AW = G::AW, VW = G::VW;
+    constexpr int ZC = G::ZC, AW = G::AW, VW = G::VW;
     constexpr int NA = naux(MODE);
     constexpr int NE = R + 2 * P;  // phase-1 rows per strip
     extern __shared__ __align__(16) float lds[];
@@ -117,7 +124,7 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
     const int ZH = TH + 2 * (S + P), ZWr = TW + 2 * (S + P);
     const int AH = TH + 2 * S, AWr = TW + 2 * S;
     float* Zs = lds;
-    int off = (ZH * ZW + 3) & ~3;
+    int off = (ZWr * ZC + 3) & ~3;
     float* Aux = lds + off;
     off += (AH * AW * NA + 3) & ~3;
     float* Vb = lds + off;
@@ -127,7 +134,7 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
         const int r = idx / ZWr, q = idx - r * ZWr;
         const int gi = reflect_clamp(ti0 - S - P + r, n1);
         const int gj = reflect_clamp(tj0 - S - P + q, n2);
-        Zs[r * ZW + q] = d.z[(size_t)gi * n2 + gj];
+        Zs[q * ZC + r] = d.z[(size_t)gi * n2 + gj];
     }
     if constexpr (NA == 2) {
         for (int idx = tid; idx < AH * AWr; idx += NT) {
@@ -164,10 +171,10 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
         it = it < G::NITEM1 ? it : G::NITEM1 - 1;  // idle lanes shadow a valid item
         const int strip = it / G::TWE;
         const int c = it - strip * G::TWE;
-        zoff[k1] = (strip * R + S) * ZW + c + S;
+        zoff[k1] = (c + S) * ZC + strip * R + S;
         voff[k1] = strip * R * VW + c;
 #pragma unroll
-        for (int q = 0; q < NE; ++q) ref[k1][q] = Zs[zoff[k1] + q * ZW];
+        for (int q = 0; q < NE; ++q) ref[k1][q] = Zs[zoff[k1] + q];
     }
 
     const int pi = tid % TH;             // phase-2 output row in the tile
@@ -181,6 +188,7 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
     const float beta = d.beta;
 
     const int NS = (2 * S + 1) * (2 * S + 1);
+    const int aux_base = (pi + S) * AW + pj + S;  // own pixel in the per-pixel tile
     const int gi_own = ti0 + pi;
     const int gj_own = tj0 + pj;
 
@@ -188,7 +196,7 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
     // column strips, written to V.  The running sum adds the entering square
     // and removes the leaving one with two FMAs.
     auto phase1 = [&](int dy, int dx, float* V) {
-        const int sh = dy * ZW + dx;
+        const int sh = dx * ZC + dy;
 #pragma unroll
         for (int k1 = 0; k1 < G::ROUNDS1; ++k1) {
             if (tid + k1 * NT < G::NITEM1) {
@@ -197,10 +205,10 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
                 // above later reads of the same LDS array
                 float tq[NE];
 #pragma unroll
-                for (int q = 0; q < NE; ++q) tq[q] = ref[k1][q] - zq[q * ZW];
-                float v = 0.f;
+                for (int q = 0; q < NE; ++q) tq[q] = ref[k1][q] - zq[q];
+                float v = tq[0] * tq[0];
 #pragma unroll
-                for (int q = 0; q <= 2 * P; ++q) v = fmaf(tq[q], tq[q], v);
+                for (int q = 1; q <= 2 * P; ++q) v = fmaf(tq[q], tq[q], v);
                 float* vo = V + voff[k1];
                 vo[0] = v;
 #pragma unroll
@@ -230,16 +238,16 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
             vv[4 * q + 3] = t4.w;
         }
         if constexpr (NA == 2) {
-            const float2* ap = reinterpret_cast<const float2*>(Aux) + (pi + dy + S) * AW + pj + dx + S;
+            const float2* ap = reinterpret_cast<const float2*>(Aux) + aux_base + (dy * AW + dx);
 #pragma unroll
             for (int k = 0; k < L; ++k) cv[k] = ap[k];
         }
     };
     auto math2 = [&](int dy, int dx) {
         const float lg = hat.lg[dy + S] + hat.lg[dx + S];
-        float hs = 0.f;
+        float hs = vv[0];
 #pragma unroll
-        for (int q = 0; q <= 2 * P; ++q) hs += vv[q];
+        for (int q = 1; q <= 2 * P; ++q) hs += vv[q];
         float Dk[L];
         Dk[0] = hs;
 #pragma unroll
@@ -276,7 +284,55 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
     // The shift counters advance incrementally (no integer division).  Both
     // schedules use one barrier per shift thanks to the two V buffers.
     int dy = -S, dx = -S;
-    if constexpr (PIPE) {
+    if constexpr (PIPE == 2) {
+        // grouped schedule: dx outer, dy inner in groups of GWIN shifts.  The
+        // shifted column of a strip slides down one row per dy, so one register
+        // window of NE + GWIN - 1 values serves the whole group (static indices,
+        // fully unrolled) instead of NE LDS reads per shift.
+        constexpr int GW = G::GWIN;
+        constexpr int NW = NE + GW - 1;
+        int t = 0;
+        for (dx = -S; dx <= S; ++dx) {
+            for (int dy0 = -S; dy0 <= S; dy0 += GW) {
+                float win[G::ROUNDS1][NW];
+#pragma unroll
+                for (int k1 = 0; k1 < G::ROUNDS1; ++k1) {
+                    const float* zq = Zs + zoff[k1] + dx * ZC + dy0;
+#pragma unroll
+                    for (int q = 0; q < NW; ++q) win[k1][q] = zq[q];
+                }
+#pragma unroll
+                for (int g = 0; g < GW; ++g) {
+                    if (dy0 + g <= S) {
+                        float* V = Vb + (t & 1) * (TH * VW);
+#pragma unroll
+                        for (int k1 = 0; k1 < G::ROUNDS1; ++k1) {
+                            if (tid + k1 * NT < G::NITEM1) {
+                                float tq[NE];
+#pragma unroll
+                                for (int q = 0; q < NE; ++q) tq[q] = ref[k1][q] - win[k1][g + q];
+                                float v = tq[0] * tq[0];
+#pragma unroll
+                                for (int q = 1; q <= 2 * P; ++q) v = fmaf(tq[q], tq[q], v);
+                                float* vo = V + voff[k1];
+                                vo[0] = v;
+#pragma unroll
+                                for (int q = 1; q < R; ++q) {
+                                    v = fmaf(tq[q + 2 * P], tq[q + 2 * P], v);
+                                    v = fmaf(-tq[q - 1], tq[q - 1], v);
+                                    vo[q * VW] = v;
+                                }
+                            }
+                        }
+                        __syncthreads();
+                        load2(dy0 + g, dx, V);
+                        math2(dy0 + g, dx);
+                        ++t;
+                    }
+                }
+            }
+        }
+    } else if constexpr (PIPE == 1) {
         // software pipeline: phase 1 of shift t+1 and phase 2 of shift t share
         // one barrier interval (they touch different V buffers)
         phase1(dy, dx, Vb);
@@ -405,9 +461,11 @@ hipError_t launch_var(int S, const ImgDesc& one, const ImgDesc* batch, const Til
 template <int P, int S_CLASS, int MODE, bool BATCH>
 hipError_t launch_one(int S, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
                       int ntiles, hipStream_t st) {
-    if (sweep_variant(MODE, S, P) == 1)
-        return launch_var<P, S_CLASS, MODE, BATCH, 1>(S, one, batch, tiles, ntiles, st);
-    return launch_var<P, S_CLASS, MODE, BATCH, 0>(S, one, batch, tiles, ntiles, st);
+    switch (sweep_variant(MODE, S, P)) {
+        case 1: return launch_var<P, S_CLASS, MODE, BATCH, 1>(S, one, batch, tiles, ntiles, st);
+        case 2: return launch_var<P, S_CLASS, MODE, BATCH, 2>(S, one, batch, tiles, ntiles, st);
+        default: return launch_var<P, S_CLASS, MODE, BATCH, 0>(S, one, batch, tiles, ntiles, st);
+    }
 }
 
 template <int P, int S_CLASS, bool BATCH>
@@ -464,6 +522,7 @@ template <int P, int S_CLASS>
 hipError_t prepare_all() {
     hipError_t e = prepare_var<P, S_CLASS, 0>();
     if (e == hipSuccess) e = prepare_var<P, S_CLASS, 1>();
+    if (e == hipSuccess) e = prepare_var<P, S_CLASS, 2>();
     return e;
 }
 
@@ -505,8 +564,8 @@ size_t sweep_lds_bytes(int S, int P, int mode) {
     // upper bound over the instances (S_CLASS = 24 for S > 12)
     const int SC = S <= kSmallS ? kSmallS : kMaxS;
     const int TH = 32, TW = 64;
-    const size_t ZW = TW + 2 * (SC + P), AW = TW + 2 * SC + 1, VW = TW + 2 * P + 8;
-    size_t n = (TH + 2 * (S + P)) * ZW + (TH + 2 * S) * AW * (mode == kPassA ? 0 : 2) + 2 * TH * VW + 8;
+    const size_t ZC = TH + 2 * (SC + P) + 8, AW = TW + 2 * SC + 1, VW = TW + 2 * P + 8;
+    size_t n = (TW + 2 * (S + P)) * ZC + (TH + 2 * S) * AW * (mode == kPassA ? 0 : 2) + 2 * TH * VW + 8;
     return n * sizeof(float);
 }
 

@@ -55,7 +55,7 @@ enum SweepMode : int {
 };
 
 // Variant table of the sweeps (tuning.hip).
-constexpr int kSweepVariants = 2;
+constexpr int kSweepVariants = 3;
 int sweep_variant(int mode, int S, int P);
 void set_sweep_variant(int kind, int S, int P, int v);
 void save_tuning();
