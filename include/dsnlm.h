@@ -185,6 +185,35 @@ int ladmm_step(const ladmm_operator* op, const ladmm_params* p, int k, dsnlm_wei
 int ladmm_solve(const ladmm_operator* op, const ladmm_params* p, float* x, float* v, float* u,
                 float* residuals, float* checkpoints, void* stream);
 
+/* Reverse mode through iteration k of Algorithm 1 (unrolled differentiation;
+ * not in the paper: the chain rule through the x-step, the projection, the
+ * denoiser and the dual update).  Inputs: the iteration's guide (z_k while
+ * k <= freeze_after, else z_{freeze_after}), the state before the iteration
+ * (x_prev, v_prev, u_prev) and x_k, z_k = x_k + u_prev after it -- all device
+ * n1*n2.  In/out: xbar, vbar, ubar hold the adjoints of (x_k, v_k, u_k) on
+ * entry and of (x_prev, v_prev, u_prev) on return.  gacc: device n1*n2
+ * accumulator of the frozen guide's adjoint (required when k > freeze_after;
+ * it is added into z's adjoint at k = freeze_after).  dparams: device
+ * float[2], incremented by the explicit derivative with respect to rho and by
+ * the derivative with respect to the bandwidth h.  The weights are rebuilt
+ * from the guide (checkpointing: nothing per iteration is kept besides the
+ * states).  Synchronous (frees its scratch). */
+int ladmm_step_backward(const ladmm_operator* op, const ladmm_params* p, int k, const float* guide,
+                        const float* x_prev, const float* v_prev, const float* u_prev,
+                        const float* x_k, const float* z_k, float* xbar, float* vbar, float* ubar,
+                        float* gacc, float* dparams, void* stream);
+
+/* All iterations in reverse from the checkpoints written by ladmm_solve
+ * ([iters][4][n1*n2]: x, v, u, z after each iteration) and the initial state
+ * (x0, v0, u0).  xbar, vbar, ubar: adjoints of the final (x, v, u) on entry,
+ * of (x0, v0, u0) on return.  dparams as in ladmm_step_backward (the caller
+ * zeroes it).  With h <= 0 in the params (h = sqrt(lambda / rho)), the
+ * derivatives follow as dL/dlambda = dparams[1] h / (2 lambda) and
+ * dL/drho = dparams[0] - dparams[1] h / (2 rho).  Synchronous. */
+int ladmm_solve_backward(const ladmm_operator* op, const ladmm_params* p, const float* x0,
+                         const float* v0, const float* u0, const float* checkpoints, float* xbar,
+                         float* vbar, float* ubar, float* dparams, void* stream);
+
 /* out = A x (super-resolution operator only; out is the low-resolution
  * grid) -- used to synthesise observations and by tests. */
 int ladmm_apply_forward(const ladmm_operator* op, const float* x, float* out, void* stream);

@@ -58,3 +58,58 @@ def central_fd(fun, arr, idx_list, step: float = 1e-3) -> np.ndarray:
         am[k] -= step
         out.append((fun(ap.reshape(a.shape)) - fun(am.reshape(a.shape))) / (2 * step))
     return np.asarray(out)
+
+
+# ---------------------------------------------------------------------------
+# Unrolled Algorithm 1 in torch FP64 (differentiable in lambda, rho, h)
+# ---------------------------------------------------------------------------
+def _box(q, lo, hi):
+    """Pi_C with derivative 1 strictly inside the box and 0 elsewhere."""
+    inside = (q > lo) & (q < hi)
+    return torch.where(inside, q, torch.clamp(q, lo, hi).detach())
+
+
+def spi_grad_torch(t, ones, K, eta, t_min=1e-6):
+    """phi'(t) of the single-photon likelihood at max(t, t_min) (derivative of
+    the max taken as 1 above t_min and 0 below)."""
+    t = torch.where(t > t_min, t, torch.full_like(t, t_min))
+    K1 = torch.as_tensor(np.asarray(ones, dtype=np.float64))
+    K0 = K - K1
+    a = eta * t / K
+    return (eta / K) * (K0 - K1 * torch.exp(-a) / (-torch.expm1(-a)))
+
+
+def sr_forward_torch(x, taps, factor, boundary="symmetric"):
+    from .ladmm_ref import pad_index
+    taps = torch.as_tensor(np.asarray(taps, dtype=np.float64))
+    n1, n2 = x.shape
+    size = taps.numel()
+    r = (size - 1) // 2
+    xp = x[torch.as_tensor(pad_index(n1, r, boundary))][:, torch.as_tensor(pad_index(n2, r, boundary))]
+    out = torch.zeros((n1, n2), dtype=torch.float64)
+    for a in range(size):
+        for b in range(size):
+            out = out + taps[a] * taps[b] * xp[a:a + n1, b:b + n2]
+    return out[::factor, ::factor]
+
+
+def unrolled_ladmm_torch(x0, grad_f, *, alpha, rho, lam, S, P, iters, freeze_after, lo=0.0, hi=1.0,
+                         h=None, v0=None, u0=None):
+    """Algorithm 1 unrolled in torch FP64.  rho, lam (and h, if given) may be
+    tensors requiring grad; without h the bandwidth is sqrt(lam / rho).
+    Returns the final (x, v, u)."""
+    x = x0
+    v = x0 if v0 is None else v0
+    u = torch.zeros_like(x0) if u0 is None else u0
+    hh = torch.sqrt(lam / rho) if h is None else h
+    mu = 1.0 / (alpha + rho)
+    guide = None
+    for k in range(1, iters + 1):
+        q = mu * (alpha * x + rho * (v - u) - grad_f(x))
+        x = _box(q, lo, hi)
+        z = x + u
+        if k <= freeze_after:
+            guide = z
+        v = dsnlm_ref.dsnlm_shifts(z, guide, S, P, hh)["y"]
+        u = u + x - v
+    return x, v, u

@@ -18,12 +18,13 @@ from .api import (  # noqa: F401
     ladmm_gradient,
     ladmm_operator_norm2,
     ladmm_solve,
+    ladmm_solve_backward,
     ladmm_step,
     SROperator,
     SPIOperator,
     LadmmParams,
 )
 
-from .autograd import DSNLMFunction, dsnlm  # noqa: F401,E402
+from .autograd import DSNLMFunction, UnrolledLADMM, dsnlm, unrolled_ladmm  # noqa: F401,E402
 
 __version__ = "0.1.0"

@@ -90,6 +90,10 @@ def _load():
         "ladmm_step": (i, [C.POINTER(LadmmOperator), C.POINTER(LadmmParams), i, pp, vp, vp, vp, vp]),
         "ladmm_solve": (i, [C.POINTER(LadmmOperator), C.POINTER(LadmmParams), vp, vp, vp, vp, vp, vp]),
         "ladmm_apply_forward": (i, [C.POINTER(LadmmOperator), vp, vp, vp]),
+        "ladmm_step_backward": (i, [C.POINTER(LadmmOperator), C.POINTER(LadmmParams), i, vp, vp, vp, vp, vp,
+                                    vp, vp, vp, vp, vp, vp, vp]),
+        "ladmm_solve_backward": (i, [C.POINTER(LadmmOperator), C.POINTER(LadmmParams), vp, vp, vp, vp, vp,
+                                     vp, vp, vp, vp]),
         "ladmm_gradient": (i, [C.POINTER(LadmmOperator), vp, vp, vp]),
         "ladmm_operator_norm2": (i, [C.POINTER(LadmmOperator), i, C.POINTER(f), vp]),
         "dsnlm_tune_set": (i, [i, i, i, i]),
@@ -126,6 +130,7 @@ EXPORTED = [
     "ladmm_gradient", "ladmm_operator_norm2", "dsnlm_last_error", "dsnlm_version",
     "dsnlm_profile_enable", "dsnlm_profile_query", "dsnlm_profile_reset",
     "dsnlm_tune_set", "dsnlm_tune_get", "dsnlm_tune", "dsnlm_peak_probe",
+    "ladmm_step_backward", "ladmm_solve_backward",
 ]
 
 K_PASS_A, K_PASS_B, K_APPLY, K_EPILOGUE, K_BWD_PREP, K_PASS_C, K_PASS_D, K_BWD_TAIL, K_LADMM = range(9)

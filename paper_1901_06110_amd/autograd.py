@@ -49,3 +49,45 @@ def dsnlm(x: torch.Tensor, guide: Optional[torch.Tensor], h, S: int, P: int) -> 
     if not isinstance(h, torch.Tensor):
         h = torch.tensor(float(h), device=x.device)
     return DSNLMFunction.apply(x, guide, h, S, P)
+
+
+class UnrolledLADMM(torch.autograd.Function):
+    """x_K = Algorithm 1 run for params.iters iterations from x0 (v0 = x0,
+    u0 = 0), differentiable in x0, lambda and rho (bandwidth sqrt(lambda/rho),
+    params.h must be <= 0).  The forward keeps per-iteration checkpoints of
+    (x, v, u, z); the backward recomputes each iteration's weights from them."""
+
+    @staticmethod
+    def forward(ctx, x0, lam, rho, op, params):
+        if params.h > 0:
+            raise ValueError("UnrolledLADMM differentiates the coupled bandwidth; set params.h <= 0")
+        p = api.LadmmParams(**{**params.__dict__, "lam": float(lam), "rho": float(rho)})
+        n1, n2 = x0.shape
+        x0 = x0.contiguous()
+        x, v, u = x0.clone(), x0.clone(), torch.zeros_like(x0)
+        ck = torch.empty((p.iters, 4, n1, n2), dtype=torch.float32, device=x0.device)
+        api.ladmm_solve(op, p, x, v, u, checkpoints=ck)
+        ctx.save_for_backward(x0, ck)
+        ctx.op, ctx.p = op, p
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        x0, ck = ctx.saved_tensors
+        p = ctx.p
+        xb = gx.contiguous().clone()
+        vb = torch.zeros_like(xb)
+        ub = torch.zeros_like(xb)
+        zeros = torch.zeros_like(x0)
+        dp = api.ladmm_solve_backward(ctx.op, p, x0, x0, zeros, ck, xb, vb, ub).double()
+        h = (p.lam / p.rho) ** 0.5
+        dlam = dp[1] * h / (2 * p.lam)
+        drho = dp[0] - dp[1] * h / (2 * p.rho)
+        gx0 = xb + vb  # v0 = x0
+        return gx0, dlam.float(), drho.float(), None, None
+
+
+def unrolled_ladmm(x0, lam, rho, op, params):
+    lam = lam if isinstance(lam, torch.Tensor) else torch.tensor(float(lam), device=x0.device)
+    rho = rho if isinstance(rho, torch.Tensor) else torch.tensor(float(rho), device=x0.device)
+    return UnrolledLADMM.apply(x0, lam, rho, op, params)

@@ -482,6 +482,26 @@ int ensure_solver_scratch(dsnlm_weights* w, const OpView& ov, const ladmm_operat
 }
 
 }  // namespace
+
+// out = A^T A x for the super-resolution operator (lr: low-resolution scratch).
+int sr_apply_AtA(const ladmm_operator* op, const float* x, float* lr, float* out, hipStream_t st) {
+    OpView ov;
+    int rc = check_operator(op, false, "sr_apply_AtA", &ov);
+    if (rc) return rc;
+    const int n = op->n1 * op->n2, mlr = ov.g.m1 * ov.g.m2;
+    StepScalars s{};
+    if (op->boundary == 0) {
+        hipLaunchKernelGGL(k_sr_forward<0>, dim3(blocks(mlr)), dim3(256), 0, st, x, nullptr, lr, ov.g, ov.taps);
+        hipLaunchKernelGGL(k_sr_adjoint_step<0>, dim3(blocks(n)), dim3(256), 0, st, lr, out, nullptr, nullptr, nullptr,
+                           ov.g, ov.taps, s, 0);
+    } else {
+        hipLaunchKernelGGL(k_sr_forward<1>, dim3(blocks(mlr)), dim3(256), 0, st, x, nullptr, lr, ov.g, ov.taps);
+        hipLaunchKernelGGL(k_sr_adjoint_step<1>, dim3(blocks(n)), dim3(256), 0, st, lr, out, nullptr, nullptr, nullptr,
+                           ov.g, ov.taps, s, 0);
+    }
+    return check_hip(hipGetLastError(), "A^T A");
+}
+
 }  // namespace dsnlm
 
 using namespace dsnlm;
