@@ -504,24 +504,35 @@ int enqueue_backward(dsnlm_weights* w, const float* x, const float* dy, float* d
         if (rc) return rc;
     }
     if (!dguide && !dh) return DSNLM_OK;
-    DArgs da{};
-    da.z = w->guide;
-    da.aux5 = aux5;
-    da.gz = gz;
-    da.hpart = hpart;
-    da.n1 = n1;
-    da.n2 = n2;
-    da.beta = d.beta;
-    da.kappa = d.kappa;
-    da.tiles_x = tiles_x;
-    {
+    int nd;  // blocks of sweep D (one partial of hbar each)
+    if (S <= 12) {
+        // sweep D on the forward sweep's machinery (32 x 64 s-tiles)
+        d.aux5 = aux5;
+        d.gz = gz;
+        d.hpart = hpart;
+        const int CHn = 32 - 2 * P, CWn = 64 - 2 * P;
+        nd = ((n1 + 2 * P + CHn - 1) / CHn) * ((n2 + 2 * P + CWn - 1) / CWn);
+        rc = check_hip(launch_sweep(kPassD, S, P, d, nullptr, nullptr, 0, st), "backward sweep D");
+        if (rc) return rc;
+    } else {
+        DArgs da{};
+        da.z = w->guide;
+        da.aux5 = aux5;
+        da.gz = gz;
+        da.hpart = hpart;
+        da.n1 = n1;
+        da.n2 = n2;
+        da.beta = d.beta;
+        da.kappa = d.kappa;
+        da.tiles_x = tiles_x;
+        nd = tiles_y * tiles_x;
         ProfScope prof(DSNLM_K_PASS_D, st);
-        rc = check_hip(launch_sweep_d(da, S, P, tiles_y * tiles_x, st), "backward sweep D");
+        rc = check_hip(launch_sweep_d(da, S, P, nd, st), "backward sweep D");
         if (rc) return rc;
     }
     ProfScope prof(DSNLM_K_BWD_TAIL, st);
     if (dguide) hipLaunchKernelGGL(k_fold, dim3(nb), dim3(256), 0, st, gz, dguide, n1, n2, P);
-    if (dh) hipLaunchKernelGGL(k_dh, dim3(1), dim3(256), 0, st, hpart, tiles_y * tiles_x, w->h, dh);
+    if (dh) hipLaunchKernelGGL(k_dh, dim3(1), dim3(256), 0, st, hpart, nd, w->h, dh);
     return check_hip(hipGetLastError(), "backward tail");
 }
 

@@ -66,12 +66,14 @@ struct Geo {
     // V row stride: 4 * odd, for conflict-free float4 reads down rows
     static constexpr int VW0 = ((TWE + 3) / 4) * 4;
     static constexpr int VW = ((VW0 / 4) % 2) ? VW0 : VW0 + 4;
+    static constexpr int BW = TW + 2 * P + 1;         // sweep D: Dbar rows
+    static constexpr int CH = TH - 2 * P, CW = TW - 2 * P;  // sweep D core
     static_assert(TH % R == 0 && TW % L == 0 && L % 4 == 0, "tile shape");
 };
 
 // Floats per pixel of the per-pixel input tile: pass A needs none (pairs that
 // leave the image are masked arithmetically), the other passes stage two.
-constexpr int naux(int mode) { return mode == kPassA ? 0 : 2; }
+constexpr int naux(int mode) { return mode == kPassA ? 0 : (mode == kPassD ? 5 : 2); }
 
 template <int P, int S_CLASS>
 size_t lds_floats(int S, int mode) {
@@ -80,7 +82,12 @@ size_t lds_floats(int S, int mode) {
     const size_t AH = G::TH + 2 * S;
     size_t n = (ZWr * G::ZC + 3) & ~(size_t)3;
     n += (AH * G::AW * naux(mode) + 3) & ~(size_t)3;
-    n += (size_t)2 * G::TH * G::VW;
+    if (mode == kPassD) {
+        n += (size_t)G::TH * G::VW;      // one V buffer (three barriers per shift)
+        n += (size_t)2 * G::TH * G::BW;  // Dbar and its vertical box sums
+    } else {
+        n += (size_t)2 * G::TH * G::VW;
+    }
     return n;
 }
 
@@ -116,8 +123,14 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
         first = (t.flags & 1) != 0;
     } else {
         d = one;
-        ti0 = blockIdx.y * TH;
-        tj0 = blockIdx.x * TW;
+        if constexpr (MODE == kPassD) {
+            // s-tiles overlap by 2P: their cores tile the padded grid [-P, n+P)
+            ti0 = blockIdx.y * G::CH - 2 * P;
+            tj0 = blockIdx.x * G::CW - 2 * P;
+        } else {
+            ti0 = blockIdx.y * TH;
+            tj0 = blockIdx.x * TW;
+        }
         first = blockIdx.x == 0 && blockIdx.y == 0;
     }
     const int n1 = d.n1, n2 = d.n2;
@@ -128,6 +141,9 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
     float* Aux = lds + off;
     off += (AH * AW * NA + 3) & ~3;
     float* Vb = lds + off;
+    constexpr int NVB = (MODE == kPassD) ? 1 : 2;  // V buffers
+    float* Db = Vb + NVB * TH * VW;                // sweep D only
+    float* VDb = Db + TH * G::BW;
 
     // ---- stage the guide tile (halo S+P, mirrored) and the per-pixel inputs
     for (int idx = tid; idx < ZH * ZWr; idx += NT) {
@@ -135,6 +151,18 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
         const int gi = reflect_clamp(ti0 - S - P + r, n1);
         const int gj = reflect_clamp(tj0 - S - P + q, n2);
         Zs[q * ZC + r] = d.z[(size_t)gi * n2 + gj];
+    }
+    if constexpr (NA == 5) {
+        for (int idx = tid; idx < AH * AWr; idx += NT) {
+            const int r = idx / AWr, q = idx - r * AWr;
+            const int gi = ti0 - S + r, gj = tj0 - S + q;
+            const bool in = (unsigned)gi < (unsigned)n1 && (unsigned)gj < (unsigned)n2;
+            float* dst = Aux + 5 * (r * AW + q);
+            const float* src = d.aux5 + 5 * ((size_t)(in ? gi : 0) * n2 + (in ? gj : 0));
+#pragma unroll
+            for (int k = 0; k < 5; ++k) dst[k] = in ? src[k] : 0.f;
+        }
+        for (int idx = tid; idx < 2 * TH * G::BW; idx += NT) Db[idx] = 0.f;  // and VDb
     }
     if constexpr (NA == 2) {
         for (int idx = tid; idx < AH * AWr; idx += NT) {
@@ -191,6 +219,27 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
     const int aux_base = (pi + S) * AW + pj + S;  // own pixel in the per-pixel tile
     const int gi_own = ti0 + pi;
     const int gj_own = tj0 + pj;
+
+    // sweep D: own factors (omegabar, beta, gamma, c, c x), own guide value,
+    // core / in-image flags and the guide-gradient accumulators
+    constexpr int LD = (MODE == kPassD) ? L : 1;
+    float own[LD][5];
+    float zown[LD];
+    bool sin_[LD], core_[LD];
+    float accz[LD];
+    float hacc = 0.f;
+    if constexpr (MODE == kPassD) {
+#pragma unroll
+        for (int k = 0; k < L; ++k) {
+#pragma unroll
+            for (int q = 0; q < 5; ++q) own[k][q] = Aux[5 * (aux_base + k) + q];
+            zown[k] = Zs[(pj + k + S + P) * ZC + pi + S + P];
+            const int gj = gj_own + k;
+            sin_[k] = (unsigned)gi_own < (unsigned)n1 && (unsigned)gj < (unsigned)n2;
+            core_[k] = pi >= P && pi < TH - P && pj + k >= P && pj + k < TW - P;
+            accz[k] = 0.f;
+        }
+    }
 
     // phase 1: vertical sliding box sums of e_d = (z(p) - z(p+d))^2 down the
     // column strips, written to V.  The running sum adds the entering square
@@ -271,6 +320,25 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
                     acc0[k] += ok ? a : 0.f;
                 }
             }
+        } else if constexpr (NA == 5) {
+            // Dbar_{s,d} + Dbar_{s+d,-d} = -kappa a (abar_{s,d} + abar_{s+d,-d})
+            const float kap = d.kappa;
+            const bool rowok = (unsigned)(gi_own + dy) < (unsigned)n1;
+            const float* nb = Aux + 5 * (aux_base + dy * AW + dx);
+#pragma unroll
+            for (int k = 0; k < L; ++k) {
+                const float a = __builtin_amdgcn_exp2f(lg - beta * Dk[k]);
+                const float* r5 = nb + 5 * k;
+                float as = own[k][0] + r5[0];
+                as = fmaf(own[k][1], r5[4], as);
+                as = fmaf(own[k][2], r5[3], as);
+                as = fmaf(r5[1], own[k][4], as);
+                as = fmaf(r5[2], own[k][3], as);
+                const bool ok = sin_[k] && rowok && (unsigned)(gj_own + k + dx) < (unsigned)n2;
+                const float db = ok ? -kap * a * as : 0.f;
+                hacc = core_[k] ? fmaf(db, Dk[k], hacc) : hacc;
+                Db[pi * G::BW + pj + k + P] = db;
+            }
         } else {
 #pragma unroll
             for (int k = 0; k < L; ++k) {
@@ -278,6 +346,49 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
                 acc0[k] = fmaf(a, cv[k].x, acc0[k]);
                 if constexpr (MODE != kPassBBuild) acc1[k] = fmaf(a, cv[k].y, acc1[k]);
             }
+        }
+    };
+
+    // sweep D tail of one shift: box-sum Dbar over the patch and accumulate
+    // 2 (z(p) - z(p+d)) box(Dbar)(p) on the core
+    auto tailD = [&](int dy, int dx) {
+        if constexpr (MODE == kPassD) {
+            constexpr int BW = G::BW;
+            __syncthreads();
+            // phase 3: vertical sliding box sums on the core rows (column strips)
+            {
+                constexpr int R3 = (G::CH + 3) / 4;
+                const int c = tid % TW, strip = tid / TW;
+                const int r0 = P + strip * R3;
+                const int r1 = (r0 + R3 < TH - P) ? r0 + R3 : TH - P;
+                if (r0 < r1) {
+                    float v = Db[(r0 - P) * BW + c + P];
+#pragma unroll
+                    for (int t = 1; t <= 2 * P; ++t) v += Db[(r0 - P + t) * BW + c + P];
+                    VDb[r0 * BW + c + P] = v;
+                    for (int r = r0 + 1; r < r1; ++r) {
+                        v += Db[(r + P) * BW + c + P] - Db[(r - P - 1) * BW + c + P];
+                        VDb[r * BW + c + P] = v;
+                    }
+                }
+            }
+            __syncthreads();
+            // phase 4: horizontal sliding box sums, accumulate on the core
+            {
+                const float* vr = VDb + pi * BW + pj;
+                float hs = vr[0];
+#pragma unroll
+                for (int q = 1; q <= 2 * P; ++q) hs += vr[q];
+                const float* zq = Zs + (pj + S + P + dx) * ZC + pi + S + P + dy;
+#pragma unroll
+                for (int k = 0; k < L; ++k) {
+                    if (k > 0) hs += vr[k + 2 * P] - vr[k - 1];
+                    accz[k] = fmaf(2.f * (zown[k] - zq[k * ZC]), hs, accz[k]);
+                }
+            }
+        } else {
+            (void)dy;
+            (void)dx;
         }
     };
 
@@ -304,7 +415,7 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
 #pragma unroll
                 for (int g = 0; g < GW; ++g) {
                     if (dy0 + g <= S) {
-                        float* V = Vb + (t & 1) * (TH * VW);
+                        float* V = Vb + ((NVB == 2) ? (t & 1) : 0) * (TH * VW);
 #pragma unroll
                         for (int k1 = 0; k1 < G::ROUNDS1; ++k1) {
                             if (tid + k1 * NT < G::NITEM1) {
@@ -327,6 +438,7 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
                         __syncthreads();
                         load2(dy0 + g, dx, V);
                         math2(dy0 + g, dx);
+                        tailD(dy0 + g, dx);
                         ++t;
                     }
                 }
@@ -362,6 +474,27 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
                 ++dy;
             }
         }
+    }
+
+    if constexpr (MODE == kPassD) {
+        const int W2 = n2 + 2 * P;
+#pragma unroll
+        for (int k = 0; k < L; ++k) {
+            const int gj = gj_own + k;
+            if (core_[k] && gi_own >= -P && gi_own < n1 + P && gj >= -P && gj < n2 + P)
+                d.gz[(size_t)(gi_own + P) * W2 + gj + P] = accz[k];
+        }
+        // block partial of sum Dbar D: fixed-order LDS tree (V is free: its
+        // last reads were before the two barriers of the last shift's tail)
+        float* red = Vb;
+        red[tid] = hacc;
+        __syncthreads();
+        for (int w = NT / 2; w > 0; w >>= 1) {
+            if (tid < w) red[tid] += red[tid + w];
+            __syncthreads();
+        }
+        if (tid == 0) d.hpart[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+        return;
     }
 
     // ---- per-pixel epilogue of the pass
@@ -451,7 +584,9 @@ hipError_t launch_var(int S, const ImgDesc& one, const ImgDesc* batch, const Til
     hipError_t e = ensure_attr<P, S_CLASS, MODE, BATCH, PIPE>();
     if (e != hipSuccess) return e;
     dim3 grid = BATCH ? dim3(ntiles)
-                      : dim3((one.n2 + G::TW - 1) / G::TW, (one.n1 + G::TH - 1) / G::TH);
+                      : (MODE == kPassD
+                             ? dim3((one.n2 + 2 * P + G::CW - 1) / G::CW, (one.n1 + 2 * P + G::CH - 1) / G::CH)
+                             : dim3((one.n2 + G::TW - 1) / G::TW, (one.n1 + G::TH - 1) / G::TH));
     HatTable hat = make_hat(S);
     hipLaunchKernelGGL((k_sweep<P, S_CLASS, MODE, BATCH, PIPE>), grid, dim3(G::NT), lds, st, one,
                        batch, tiles, S, hat);
@@ -461,6 +596,10 @@ hipError_t launch_var(int S, const ImgDesc& one, const ImgDesc* batch, const Til
 template <int P, int S_CLASS, int MODE, bool BATCH>
 hipError_t launch_one(int S, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
                       int ntiles, hipStream_t st) {
+    if constexpr (MODE == kPassD) {
+        if (lds_floats<P, S_CLASS>(S, MODE) * sizeof(float) > 160 * 1024) return hipErrorInvalidValue;
+        return launch_var<P, S_CLASS, MODE, BATCH, 2>(S, one, batch, tiles, ntiles, st);
+    }
     switch (sweep_variant(MODE, S, P)) {
         case 1: return launch_var<P, S_CLASS, MODE, BATCH, 1>(S, one, batch, tiles, ntiles, st);
         case 2: return launch_var<P, S_CLASS, MODE, BATCH, 2>(S, one, batch, tiles, ntiles, st);
@@ -481,6 +620,10 @@ hipError_t dispatch_mode(int mode, int S, const ImgDesc& one, const ImgDesc* bat
             case kPassBBuild: return launch_one<P, S_CLASS, kPassBBuild, false>(S, one, batch, tiles, ntiles, st);
             case kApply: return launch_one<P, S_CLASS, kApply, false>(S, one, batch, tiles, ntiles, st);
             case kPassC: return launch_one<P, S_CLASS, kPassC, false>(S, one, batch, tiles, ntiles, st);
+            case kPassD:
+                if constexpr (S_CLASS <= kSmallS)
+                    return launch_one<P, S_CLASS, kPassD, false>(S, one, batch, tiles, ntiles, st);
+                return hipErrorInvalidValue;
             default: break;
         }
     }
@@ -574,6 +717,7 @@ hipError_t launch_sweep(int mode, int S, int P, const ImgDesc& one, const ImgDes
     const int kind = mode == kPassA ? DSNLM_K_PASS_A
                      : (mode == kPassBApply || mode == kPassBBuild) ? DSNLM_K_PASS_B
                      : mode == kApply ? DSNLM_K_APPLY
+                     : mode == kPassD ? DSNLM_K_PASS_D
                                       : DSNLM_K_PASS_C;
     ProfScope prof(kind, st);
     if (batch) return dispatch_p<true>(mode, S, P, one, batch, tiles, ntiles, st);

@@ -31,6 +31,9 @@ struct ImgDesc {
     // backward
     const float* aux_in;   // per-pixel float2 inputs of the backward sweep C
     float* aux_out;        // its per-pixel float2 outputs
+    const float* aux5;     // per-pixel factors of the backward sweep D (5 floats)
+    float* gz;             // sweep D output: gradient on the padded grid
+    float* hpart;          // sweep D output: per-block partial sums for dh
     int n1, n2;
     float beta;            // log2(e) / (2 (2P+1)^2 h^2)
     float kappa;           // 1 / (2 (2P+1)^2 h^2)
@@ -52,6 +55,7 @@ enum SweepMode : int {
     kPassBBuild = 2,   // delta and the key only
     kApply = 3,        // B' only (weights already built)
     kPassC = 4,        // backward: sum a t_r, sum a w_r
+    kPassD = 5,        // backward: guide and bandwidth gradients
 };
 
 // Variant table of the sweeps (tuning.hip).
