@@ -89,25 +89,19 @@ def cpu_baseline(images, S, P, budget_s: float = 20.0):
 
 
 def fwd_bwd_ratio(M, xs, hs, S, P, steps):
-    """Time the forward alone and forward + backward (input, guide and h
-    gradients) over the batch with per-image launches; return the ratio."""
+    """Time the batched forward alone and the batched forward + backward
+    (input, guide and h gradients of every image); return the ratio."""
     import torch
-    ys, handles, ybars = [], [], []
-    for x, h in zip(xs, hs):
-        y, w = M.dsnlm_forward(x, None, S, P, h, keep=True)
-        ys.append(y)
-        handles.append(w)
-        ybars.append(2.0 * (y - x))
-    outs = [(torch.empty_like(x), torch.empty_like(x)) for x in xs]
+    imgs = [(x, x, h) for x, h in zip(xs, hs)]
+    outs = M.dsnlm_forward_batched(imgs, S, P)
+    ybars = [2.0 * (y - x) for x, y in zip(xs, outs)]
 
     def fwd():
-        for x, y, h, w in zip(xs, ys, hs, handles):
-            M.dsnlm_forward(x, None, S, P, h, y=y, weights=w)
+        M.dsnlm_forward_batched(imgs, S, P, outs=outs)
 
     def fwd_bwd():
         fwd()
-        for x, w, yb in zip(xs, handles, ybars):
-            M.dsnlm_apply_backward(w, x, yb)
+        M.dsnlm_backward_batched(ybars)
 
     def timed(fn):
         fn()
@@ -125,7 +119,8 @@ def fwd_bwd_ratio(M, xs, hs, S, P, steps):
     tfb = timed(fwd_bwd)
     return {"fwd_ms": tf, "fwd_bwd_ms": tfb, "ratio": tfb / tf,
             "fwd_bwd_mpx_s": sum(x.numel() for x in xs) / (tfb * 1e-3) / 1e6,
-            "note": "per-image launches, 64 images, S=10, P=3; backward = d/dx, d/dguide, d/dh"}
+            "note": "batched launches, %d images, S=%d, P=%d; backward = d/dx, d/dguide, d/dh"
+                    % (len(xs), S, P)}
 
 
 def ladmm_sr_timing(M, S, P):

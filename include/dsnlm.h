@@ -124,6 +124,19 @@ typedef struct {
  * (they share the workspace). */
 int dsnlm_forward_batched(const dsnlm_image* imgs, int count, int S, int P, void* stream);
 
+/* Vector-Jacobian products of the LAST dsnlm_forward_batched call (same
+ * images, same order; its inputs must be unchanged): per image, dy is the
+ * cotangent of y and dx = W dy, dguide, dh (device scalar) are written; each
+ * output may be NULL.  One launch per backward sweep for the whole batch.
+ * Guide and bandwidth gradients need S <= 12 here. */
+typedef struct {
+    const float* dy;
+    float* dx;
+    float* dguide;
+    float* dh;
+} dsnlm_image_grad;
+int dsnlm_backward_batched(const dsnlm_image_grad* grads, int count, void* stream);
+
 /* ----------------------------------------------------------------------- */
 /* Linearized plug-and-play ADMM (Section 2, Algorithm 1).                   */
 /* Problem: min_x f(x) + lambda g(x), x in C = [lo, hi]^n.  f is defined by  */

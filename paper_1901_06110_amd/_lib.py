@@ -32,6 +32,15 @@ class DsnlmImage(C.Structure):
     ]
 
 
+class DsnlmImageGrad(C.Structure):
+    _fields_ = [
+        ("dy", C.c_void_p),
+        ("dx", C.c_void_p),
+        ("dguide", C.c_void_p),
+        ("dh", C.c_void_p),
+    ]
+
+
 class LadmmOperator(C.Structure):
     _fields_ = [
         ("kind", C.c_int),
@@ -87,6 +96,7 @@ def _load():
         "dsnlm_weights_scalars": (i, [vp, C.POINTER(f), C.POINTER(i), vp]),
         "dsnlm_weights_array": (vp, [vp, i]),
         "dsnlm_forward_batched": (i, [C.POINTER(DsnlmImage), i, i, i, vp]),
+        "dsnlm_backward_batched": (i, [C.POINTER(DsnlmImageGrad), i, vp]),
         "ladmm_step": (i, [C.POINTER(LadmmOperator), C.POINTER(LadmmParams), i, pp, vp, vp, vp, vp]),
         "ladmm_solve": (i, [C.POINTER(LadmmOperator), C.POINTER(LadmmParams), vp, vp, vp, vp, vp, vp]),
         "ladmm_apply_forward": (i, [C.POINTER(LadmmOperator), vp, vp, vp]),
@@ -130,7 +140,7 @@ EXPORTED = [
     "ladmm_gradient", "ladmm_operator_norm2", "dsnlm_last_error", "dsnlm_version",
     "dsnlm_profile_enable", "dsnlm_profile_query", "dsnlm_profile_reset",
     "dsnlm_tune_set", "dsnlm_tune_get", "dsnlm_tune", "dsnlm_peak_probe",
-    "ladmm_step_backward", "ladmm_solve_backward",
+    "ladmm_step_backward", "ladmm_solve_backward", "dsnlm_backward_batched",
 ]
 
 K_PASS_A, K_PASS_B, K_APPLY, K_EPILOGUE, K_BWD_PREP, K_PASS_C, K_PASS_D, K_BWD_TAIL, K_LADMM = range(9)

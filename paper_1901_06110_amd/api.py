@@ -128,20 +128,48 @@ def dsnlm_apply_backward(w: Weights, x: torch.Tensor, dy: torch.Tensor, need_dx:
     return dx, dg, dh
 
 
+_LAST_BATCH: list = []
+
+
 def dsnlm_forward_batched(images: Sequence, S: int, P: int, outs=None):
     """images: sequence of (guide, x, h); returns the list of outputs."""
     n = len(images)
     arr = (_lib.DsnlmImage * max(n, 1))()
-    ys = []
+    ys, keep = [], []
     for k, (g, x, h) in enumerate(images):
         x = _img(x, "x")
         g = x if g is None else _img(g, "guide")
+        keep.append((g, x))
         y = torch.empty_like(x) if outs is None else outs[k]
         ys.append(y)
         arr[k] = _lib.DsnlmImage(g.data_ptr(), x.data_ptr(), y.data_ptr(), x.shape[0], x.shape[1],
                                  float(h))
     _lib.check(_lib.get().dsnlm_forward_batched(arr, n, S, P, _stream()))
+    # the library keeps device pointers to these for dsnlm_backward_batched:
+    # hold the tensors until the next batched forward
+    _LAST_BATCH[:] = keep
     return ys
+
+
+def dsnlm_backward_batched(dys: Sequence, need_dx: bool = True, need_dguide: bool = True,
+                           need_dh: bool = True):
+    """Vector-Jacobian products of the last dsnlm_forward_batched call.
+
+    dys: one cotangent per image of that call, same order.  Its inputs must be
+    unchanged.  Returns a list of (dx, dguide, dh) per image (None where not
+    requested)."""
+    n = len(dys)
+    arr = (_lib.DsnlmImageGrad * max(n, 1))()
+    res = []
+    for k, dy in enumerate(dys):
+        dy = _img(dy, "dy")
+        dx = torch.empty_like(dy) if need_dx else None
+        dg = torch.empty_like(dy) if need_dguide else None
+        dh = torch.empty((1,), dtype=torch.float32, device=dy.device) if need_dh else None
+        res.append((dx, dg, dh))
+        arr[k] = _lib.DsnlmImageGrad(dy.data_ptr(), _p(dx).value, _p(dg).value, _p(dh).value)
+    _lib.check(_lib.get().dsnlm_backward_batched(arr, n, _stream()))
+    return res
 
 
 # --------------------------------------------------------------------------

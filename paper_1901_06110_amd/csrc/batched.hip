@@ -29,6 +29,7 @@ struct BatchWorkspace {
     size_t tiles_cap = 0;
     std::vector<ImgDesc> last_descs;
     std::vector<TileRef> last_tiles;
+    int last_S = -1, last_P = -1;  // of the last forward (for the backward)
 };
 
 BatchWorkspace g_ws;
@@ -147,9 +148,37 @@ extern "C" int dsnlm_forward_batched(const dsnlm_image* imgs, int count, int S, 
         }
     }
     const int nt = (int)tiles.size();
+    g_ws.last_S = S;
+    g_ws.last_P = P;
     ImgDesc none{};
     rc = check_hip(launch_sweep(kPassA, S, P, none, g_ws.descs, g_ws.tiles, nt, st), "batch pass A");
     if (!rc) rc = check_hip(launch_sweep(kPassBApply, S, P, none, g_ws.descs, g_ws.tiles, nt, st), "batch pass B");
     if (!rc) rc = check_hip(launch_epilogue(none, g_ws.descs, g_ws.tiles, nt, S, P, st), "batch epilogue");
     return rc;
+}
+
+extern "C" int dsnlm_backward_batched(const dsnlm_image_grad* grads, int count, void* stream) {
+    if (count < 0 || (count > 0 && !grads)) return fail(DSNLM_EINVAL, "dsnlm_backward_batched: bad arguments");
+    std::lock_guard<std::mutex> lk(g_ws.mu);
+    if (count != (int)g_ws.last_descs.size() || g_ws.last_S < 0)
+        return fail(DSNLM_EINVAL, "dsnlm_backward_batched: count differs from the last dsnlm_forward_batched");
+    if (count == 0) return DSNLM_OK;
+    const int S = g_ws.last_S, P = g_ws.last_P;
+    if (S > 12 && (count > 0))
+        for (int k = 0; k < count; ++k)
+            if (grads[k].dguide || grads[k].dh)
+                return fail(DSNLM_EUNSUPPORTED, "dsnlm_backward_batched: guide/bandwidth gradients need S <= 12");
+    std::vector<BwdImage> ims(count);
+    for (int k = 0; k < count; ++k) {
+        const ImgDesc& f = g_ws.last_descs[k];
+        if (!grads[k].dy) return fail(DSNLM_EINVAL, "dsnlm_backward_batched: null dy in image " + std::to_string(k));
+        const size_t bytes = (size_t)f.n1 * f.n2 * sizeof(float);
+        for (float* o : {grads[k].dx, grads[k].dguide})
+            if (o && (overlaps(o, f.x, bytes) || overlaps(o, f.z, bytes) || overlaps(o, grads[k].dy, bytes)))
+                return fail(DSNLM_EINVAL, "dsnlm_backward_batched: an output overlaps an input in image " +
+                                              std::to_string(k));
+        ims[k] = BwdImage{&g_ws.last_descs[k], grads[k].dy, grads[k].dx, grads[k].dguide, grads[k].dh};
+    }
+    return enqueue_backward_batch(ims.data(), count, S, P, g_ws.tiles, (int)g_ws.last_tiles.size(),
+                                  static_cast<hipStream_t>(stream));
 }

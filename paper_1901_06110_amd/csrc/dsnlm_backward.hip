@@ -21,6 +21,8 @@
 // Sweep D recomputes D_{s,d} for an s-tile, forms Dbar_{s,d} in LDS, box-sums
 // it over the patch, and accumulates zbar for the s-tile's core pixels.
 #include <cmath>
+#include <cstring>
+#include <vector>
 
 #include "internal.h"
 
@@ -50,6 +52,13 @@ struct BwdArgs {
     float* partials;     // per-block partial sums
     float* mbar;         // device scalar
     int n;
+    // batched form only
+    float* gz;           // padded-grid guide gradient
+    float* dguide;       // guide gradient (nullable)
+    float* dh;           // device scalar (nullable)
+    float* hpart;        // sweep-D block partials of this image
+    int n1, n2, P, nd;
+    float h;
 };
 
 // B'bar, the (t, w) pairs, and per-block sums of ybar B'.
@@ -120,6 +129,122 @@ __global__ void __launch_bounds__(256) k_bwd_mid(BwdArgs a) {
     o[2] = cc * (f - xv * bb);
     o[3] = cc;
     o[4] = cc * xv;
+}
+
+
+// ---- segmented forms for a batch: block b of the grid works on image
+// map[b].x, its local block map[b].y ------------------------------------------
+__global__ void __launch_bounds__(256) k_bwd_prep_seg(const BwdArgs* __restrict__ imgs,
+                                                      const int2* __restrict__ map) {
+    const int2 mb = map[blockIdx.x];
+    const BwdArgs a = imgs[mb.x];
+    const int idx = mb.y * 256 + threadIdx.x;
+    const float m = __uint_as_float((unsigned)(*a.key >> 32));
+    float part = 0.f;
+    if (idx < a.n) {
+        const float yb = a.dy[idx];
+        const float bb = yb / m;
+        const float cc = a.c[idx];
+        a.pairs[2 * idx] = cc * bb;
+        a.pairs[2 * idx + 1] = -cc * bb * a.x[idx];
+        part = yb * a.bp[idx];
+    }
+    __shared__ double sh[256];
+    sh[threadIdx.x] = part;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.partials[mb.y] = (float)sh[0];
+}
+
+// one block per image
+__global__ void __launch_bounds__(256) k_bwd_mbar_seg(const BwdArgs* __restrict__ imgs) {
+    const BwdArgs a = imgs[blockIdx.x];
+    const int nblk = (a.n + 255) / 256;
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) acc += a.partials[b];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const unsigned long long key = *a.key;
+        const float m = __uint_as_float((unsigned)(key >> 32));
+        const int sstar = (int)(~(unsigned)(key & 0xffffffffu));
+        const float mb = (float)(-sh[0] / ((double)m * m));
+        *a.mbar = mb;
+        a.pairs[2 * sstar + 1] += a.c[sstar] * mb;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_bwd_mid_seg(const BwdArgs* __restrict__ imgs,
+                                                     const int2* __restrict__ map) {
+    const int2 mb = map[blockIdx.x];
+    const BwdArgs a = imgs[mb.x];
+    const int idx = mb.y * 256 + threadIdx.x;
+    if (idx >= a.n) return;
+    const unsigned long long key = *a.key;
+    const float m = __uint_as_float((unsigned)(key >> 32));
+    const int sstar = (int)(~(unsigned)(key & 0xffffffffu));
+    const float f = idx == sstar ? *a.mbar : 0.f;
+    const float yb = a.dy[idx];
+    const float bb = yb / m;
+    const float cc = a.c[idx];
+    const float dl = a.delta[idx];
+    const float xv = a.x[idx];
+    const float U = a.cw[2 * idx];
+    const float Wc = a.cw[2 * idx + 1];
+    if (a.dx) a.dx[idx] = yb - dl * bb + cc * U;
+    const float cbar = bb * a.bp[idx] / cc + f * dl / cc + xv * U + Wc;
+    float* o = a.aux5 + 5 * (size_t)idx;
+    o[0] = -0.5f * cbar * cc * cc * cc;
+    o[1] = cc * bb;
+    o[2] = cc * (f - xv * bb);
+    o[3] = cc;
+    o[4] = cc * xv;
+}
+
+__global__ void __launch_bounds__(256) k_fold_seg(const BwdArgs* __restrict__ imgs, const int2* __restrict__ map) {
+    const int2 mb = map[blockIdx.x];
+    const BwdArgs a = imgs[mb.x];
+    const int idx = mb.y * 256 + threadIdx.x;
+    if (idx >= a.n || !a.dguide) return;
+    const int n1 = a.n1, n2 = a.n2, P = a.P;
+    const int i = idx / n2, j = idx - i * n2;
+    int pi[3], pj[3];
+    int ci = 0, cj = 0;
+    pi[ci++] = i;
+    if (i <= P - 1) pi[ci++] = -1 - i;
+    if (i >= n1 - P) pi[ci++] = 2 * n1 - 1 - i;
+    pj[cj++] = j;
+    if (j <= P - 1) pj[cj++] = -1 - j;
+    if (j >= n2 - P) pj[cj++] = 2 * n2 - 1 - j;
+    const int W2 = n2 + 2 * P;
+    float acc = 0.f;
+    for (int x = 0; x < ci; ++x)
+        for (int y = 0; y < cj; ++y) acc += a.gz[(size_t)(pi[x] + P) * W2 + pj[y] + P];
+    a.dguide[idx] = acc;
+}
+
+// one block per image: dh = -(1/h) sum of its sweep-D partials
+__global__ void __launch_bounds__(256) k_dh_seg(const BwdArgs* __restrict__ imgs) {
+    const BwdArgs a = imgs[blockIdx.x];
+    if (!a.dh) return;
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < a.nd; b += 256) acc += a.hpart[b];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *a.dh = (float)(-sh[0] / a.h);
 }
 
 // ---- sweep D -----------------------------------------------------------
@@ -534,6 +659,156 @@ int enqueue_backward(dsnlm_weights* w, const float* x, const float* dy, float* d
     if (dguide) hipLaunchKernelGGL(k_fold, dim3(nb), dim3(256), 0, st, gz, dguide, n1, n2, P);
     if (dh) hipLaunchKernelGGL(k_dh, dim3(1), dim3(256), 0, st, hpart, nd, w->h, dh);
     return check_hip(hipGetLastError(), "backward tail");
+}
+
+namespace {
+
+// Grow-only workspace of the batched backward.
+struct BwdBatchWs {
+    float* arrays = nullptr;
+    size_t arrays_cap = 0;
+    BwdArgs* args = nullptr;
+    size_t args_cap = 0;
+    ImgDesc* descs = nullptr;
+    size_t descs_cap = 0;
+    int2* map = nullptr;
+    size_t map_cap = 0;
+    TileRef* dtiles = nullptr;
+    size_t dtiles_cap = 0;
+    std::vector<BwdArgs> h_args;
+    std::vector<ImgDesc> h_descs;
+    std::vector<int2> h_map;
+    std::vector<TileRef> h_dtiles;
+};
+BwdBatchWs g_bws;
+
+template <class T>
+hipError_t grow_b(T** p, size_t* cap, size_t need) {
+    if (need <= *cap) return hipSuccess;
+    if (*p) {
+        hipError_t e = hipFree(*p);
+        if (e != hipSuccess) return e;
+        *p = nullptr;
+    }
+    const size_t n = need + need / 4 + 16;
+    hipError_t e = hipMalloc(p, n * sizeof(T));
+    *cap = e == hipSuccess ? n : 0;
+    return e;
+}
+
+template <class T>
+int upload_if_changed(T* dev, std::vector<T>& keep, const std::vector<T>& now, hipStream_t st, const char* what) {
+    if (keep.size() == now.size() && !now.empty() &&
+        std::memcmp(keep.data(), now.data(), now.size() * sizeof(T)) == 0)
+        return DSNLM_OK;
+    keep = now;
+    if (keep.empty()) return DSNLM_OK;
+    const int rc =
+        check_hip(hipMemcpyAsync(dev, keep.data(), keep.size() * sizeof(T), hipMemcpyHostToDevice, st), what);
+    if (rc) keep.clear();  // force a fresh upload next time
+    return rc;
+}
+
+}  // namespace
+
+int enqueue_backward_batch(const BwdImage* ims, int count, int S, int P, const TileRef* fwd_tiles, int nfwd_tiles,
+                           hipStream_t st) {
+    const int CHn = 32 - 2 * P, CWn = 64 - 2 * P;
+    // workspace layout per image: pairs 2n | cw 2n | aux5 5n | gz | partials nb | hpart nd | mbar
+    size_t total = 0;
+    std::vector<size_t> base(count);
+    std::vector<int> nd(count), nb(count);
+    for (int k = 0; k < count; ++k) {
+        const ImgDesc& f = *ims[k].fwd;
+        const size_t n = (size_t)f.n1 * f.n2;
+        nb[k] = (int)((n + 255) / 256);
+        nd[k] = ((f.n1 + 2 * P + CHn - 1) / CHn) * ((f.n2 + 2 * P + CWn - 1) / CWn);
+        base[k] = total;
+        total += 9 * n + (size_t)(f.n1 + 2 * P) * (f.n2 + 2 * P) + nb[k] + nd[k] + 4;
+    }
+    int rc = check_hip(grow_b(&g_bws.arrays, &g_bws.arrays_cap, total), "batched backward workspace");
+    if (!rc) rc = check_hip(grow_b(&g_bws.args, &g_bws.args_cap, (size_t)count), "batched backward args");
+    if (!rc) rc = check_hip(grow_b(&g_bws.descs, &g_bws.descs_cap, (size_t)count), "batched backward descriptors");
+    if (rc) return rc;
+    std::vector<BwdArgs> args(count);
+    std::vector<ImgDesc> descs(count);
+    std::vector<int2> map;
+    std::vector<TileRef> dtiles;
+    for (int k = 0; k < count; ++k) {
+        const ImgDesc& f = *ims[k].fwd;
+        const size_t n = (size_t)f.n1 * f.n2;
+        float* b = g_bws.arrays + base[k];
+        BwdArgs a{};
+        a.x = f.x;
+        a.dy = ims[k].dy;
+        a.c = f.c;
+        a.delta = f.delta;
+        a.bp = f.bp;
+        a.key = f.key;
+        a.pairs = b;
+        a.cw = b + 2 * n;
+        a.aux5 = b + 4 * n;
+        a.gz = b + 9 * n;
+        a.partials = a.gz + (size_t)(f.n1 + 2 * P) * (f.n2 + 2 * P);
+        a.hpart = a.partials + nb[k];
+        a.mbar = a.hpart + nd[k];
+        a.n = (int)n;
+        a.dx = ims[k].dx;
+        a.dguide = ims[k].dguide;
+        a.dh = ims[k].dh;
+        a.n1 = f.n1;
+        a.n2 = f.n2;
+        a.P = P;
+        a.nd = nd[k];
+        a.h = f.h;
+        args[k] = a;
+        ImgDesc d = f;
+        d.aux_in = a.pairs;
+        d.aux_out = a.cw;
+        d.aux5 = a.aux5;
+        d.gz = a.gz;
+        d.hpart = a.hpart;
+        d.tile_base = (int)dtiles.size();
+        descs[k] = d;
+        for (int b2 = 0; b2 < nb[k]; ++b2) map.push_back(make_int2(k, b2));
+        const int tyn = (f.n1 + 2 * P + CHn - 1) / CHn, txn = (f.n2 + 2 * P + CWn - 1) / CWn;
+        for (int ty = 0; ty < tyn; ++ty)
+            for (int tx = 0; tx < txn; ++tx) dtiles.push_back(TileRef{k, ty * CHn - 2 * P, tx * CWn - 2 * P, 0});
+    }
+    rc = check_hip(grow_b(&g_bws.map, &g_bws.map_cap, map.size()), "batched backward map");
+    if (!rc) rc = check_hip(grow_b(&g_bws.dtiles, &g_bws.dtiles_cap, dtiles.size()), "batched backward tiles");
+    if (!rc) rc = upload_if_changed(g_bws.args, g_bws.h_args, args, st, "upload backward args");
+    if (!rc) rc = upload_if_changed(g_bws.descs, g_bws.h_descs, descs, st, "upload backward descriptors");
+    if (!rc) rc = upload_if_changed(g_bws.map, g_bws.h_map, map, st, "upload backward map");
+    if (!rc) rc = upload_if_changed(g_bws.dtiles, g_bws.h_dtiles, dtiles, st, "upload backward tiles");
+    if (rc) return rc;
+    const int nmap = (int)map.size();
+    {
+        ProfScope prof(DSNLM_K_BWD_PREP, st);
+        hipLaunchKernelGGL(k_bwd_prep_seg, dim3(nmap), dim3(256), 0, st, g_bws.args, g_bws.map);
+        hipLaunchKernelGGL(k_bwd_mbar_seg, dim3(count), dim3(256), 0, st, g_bws.args);
+        rc = check_hip(hipGetLastError(), "batched backward prep");
+        if (rc) return rc;
+    }
+    ImgDesc none{};
+    rc = check_hip(launch_sweep(kPassC, S, P, none, g_bws.descs, fwd_tiles, nfwd_tiles, st), "batched sweep C");
+    if (rc) return rc;
+    {
+        ProfScope prof(DSNLM_K_BWD_PREP, st);
+        hipLaunchKernelGGL(k_bwd_mid_seg, dim3(nmap), dim3(256), 0, st, g_bws.args, g_bws.map);
+        rc = check_hip(hipGetLastError(), "batched backward mid");
+        if (rc) return rc;
+    }
+    bool need_d = false;
+    for (int k = 0; k < count; ++k) need_d = need_d || ims[k].dguide || ims[k].dh;
+    if (!need_d) return DSNLM_OK;
+    rc = check_hip(launch_sweep(kPassD, S, P, none, g_bws.descs, g_bws.dtiles, (int)dtiles.size(), st),
+                   "batched sweep D");
+    if (rc) return rc;
+    ProfScope prof(DSNLM_K_BWD_TAIL, st);
+    hipLaunchKernelGGL(k_fold_seg, dim3(nmap), dim3(256), 0, st, g_bws.args, g_bws.map);
+    hipLaunchKernelGGL(k_dh_seg, dim3(count), dim3(256), 0, st, g_bws.args);
+    return check_hip(hipGetLastError(), "batched backward tail");
 }
 
 }  // namespace dsnlm

@@ -493,7 +493,10 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
             if (tid < w) red[tid] += red[tid + w];
             __syncthreads();
         }
-        if (tid == 0) d.hpart[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+        if (tid == 0) {
+            const int hidx = BATCH ? (int)blockIdx.x - d.tile_base : (int)(blockIdx.y * gridDim.x + blockIdx.x);
+            d.hpart[hidx] = red[0];
+        }
         return;
     }
 
@@ -613,17 +616,17 @@ hipError_t dispatch_mode(int mode, int S, const ImgDesc& one, const ImgDesc* bat
     switch (mode) {
         case kPassA: return launch_one<P, S_CLASS, kPassA, BATCH>(S, one, batch, tiles, ntiles, st);
         case kPassBApply: return launch_one<P, S_CLASS, kPassBApply, BATCH>(S, one, batch, tiles, ntiles, st);
+        case kPassC: return launch_one<P, S_CLASS, kPassC, BATCH>(S, one, batch, tiles, ntiles, st);
+        case kPassD:
+            if constexpr (S_CLASS <= kSmallS)
+                return launch_one<P, S_CLASS, kPassD, BATCH>(S, one, batch, tiles, ntiles, st);
+            return hipErrorInvalidValue;
         default: break;
     }
     if constexpr (!BATCH) {
         switch (mode) {
             case kPassBBuild: return launch_one<P, S_CLASS, kPassBBuild, false>(S, one, batch, tiles, ntiles, st);
             case kApply: return launch_one<P, S_CLASS, kApply, false>(S, one, batch, tiles, ntiles, st);
-            case kPassC: return launch_one<P, S_CLASS, kPassC, false>(S, one, batch, tiles, ntiles, st);
-            case kPassD:
-                if constexpr (S_CLASS <= kSmallS)
-                    return launch_one<P, S_CLASS, kPassD, false>(S, one, batch, tiles, ntiles, st);
-                return hipErrorInvalidValue;
             default: break;
         }
     }

@@ -101,6 +101,17 @@ class ProfScope {
     hipEvent_t ev_;
 };
 
+// Batched backward (dsnlm_backward.hip) over the state a batched forward left.
+struct BwdImage {
+    const ImgDesc* fwd;     // forward descriptor of the image (z, x, c, delta, B', key, sizes)
+    const float* dy;
+    float* dx;              // nullable
+    float* dguide;          // nullable
+    float* dh;              // nullable (device scalar)
+};
+int enqueue_backward_batch(const BwdImage* ims, int count, int S, int P, const TileRef* fwd_tiles,
+                           int nfwd_tiles, hipStream_t st);
+
 // Error state.
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);

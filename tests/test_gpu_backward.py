@@ -111,3 +111,57 @@ def test_backward_c3_batch_shape_runs_and_is_deterministic():
         for u, v in zip(a, b):
             assert torch.isfinite(u).all()
             assert torch.equal(u, v)
+
+
+@pytest.mark.parametrize("S,P", [(7, 3), (4, 1), (10, 2)])
+def test_batched_backward_matches_fp64_autograd(S, P):
+    """One batched forward and backward over images of uneven sizes (several
+    tiles and ragged tails): every image's gradients against the FP64
+    autograd reference, and against the single-image backward."""
+    M = _M()
+    shapes = [(32, 32, 0.1), (29, 71, 0.08), (70, 45, 0.12), (12, 12, 0.15)]
+    imgs, refs = [], []
+    for k, (n1, n2, h) in enumerate(shapes):
+        clean, x, z = _case(n1, n2, 900 + 7 * k)
+        imgs.append((clean, x, z, h))
+    print(f"batched backward S={S} P={P} shapes={shapes}", flush=True)
+    # the forward's inputs must stay alive and unchanged until the backward
+    dev = [(_t(z), _t(x), h) for _, x, z, h in imgs]
+    ys = M.dsnlm_forward_batched(dev, S, P)
+    ybars = []
+    for (clean, x, z, h), y in zip(imgs, ys):
+        ybar = 2.0 * (y.cpu().numpy().astype(np.float64) - clean)
+        ybars.append(ybar)
+        ref = G.autograd_grads(x, z, S, P, h, ybar)
+        d = np.sort(ref["delta"].ravel())
+        assert d[-1] - d[-2] >= 1e-4 * d[-1], "tie in the maximum row sum"
+        refs.append(ref)
+    out = M.dsnlm_backward_batched([_t(yb) for yb in ybars])
+    torch.cuda.synchronize()
+    for (clean, x, z, h), ybar, ref, (dx, dg, dh) in zip(imgs, ybars, refs, out):
+        assert _rel(dx.cpu().numpy(), ref["dx"]) <= 1e-4
+        assert _rel(dg.cpu().numpy(), ref["dz"]) <= 1e-3
+        assert abs(float(dh.cpu()) - ref["dh"]) <= 1e-3 * abs(ref["dh"])
+        _, w = M.dsnlm_forward(_t(x), _t(z), S, P, h, keep=True)
+        dx1, dg1, dh1 = M.dsnlm_apply_backward(w, _t(x), _t(ybar))
+        torch.cuda.synchronize()
+        assert _rel(dx.cpu().numpy(), dx1.cpu().numpy()) <= 1e-5
+        assert _rel(dg.cpu().numpy(), dg1.cpu().numpy()) <= 1e-4
+
+
+def test_batched_backward_input_gradient_only_and_errors():
+    M = _M()
+    S, P = 5, 2
+    data = [_case(40, 37, 950), _case(17, 66, 951)]
+    dev = [(_t(z), _t(x), 0.1) for _, x, z in data]
+    ys = M.dsnlm_forward_batched(dev, S, P)
+    ybars = [np.random.default_rng(k).standard_normal(y.shape) for k, y in enumerate(ys)]
+    out = M.dsnlm_backward_batched([_t(yb) for yb in ybars], need_dguide=False, need_dh=False)
+    torch.cuda.synchronize()
+    for (_, x, z), yb, (dx, dg, dh) in zip(data, ybars, out):
+        assert dg is None and dh is None
+        Wd = R.dense_weights(z, S, P, 0.1)["W"]
+        ref = (Wd @ yb.ravel()).reshape(yb.shape)
+        assert _rel(dx.cpu().numpy(), ref) <= 1e-4
+    with pytest.raises(M.api._lib.DsnlmError):
+        M.dsnlm_backward_batched([_t(ybars[0])])
