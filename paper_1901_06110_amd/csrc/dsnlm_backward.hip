@@ -20,6 +20,7 @@
 //   dguide = fold of zbar through the mirror padding.
 // Sweep D recomputes D_{s,d} for an s-tile, forms Dbar_{s,d} in LDS, box-sums
 // it over the patch, and accumulates zbar for the s-tile's core pixels.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -47,11 +48,13 @@ struct BwdArgs {
     const unsigned long long* key;  // (m, s*)
     float* pairs;        // [2n] t, w  (input of sweep C)
     float* cw;           // [2n] U, Wc (output of sweep C)
-    float* aux5;         // [5n] omegabar, beta, gamma, c, c x
+    float* aux5;         // sweep-D factors: [5n] omegabar, beta, gamma, c, c x (aux4 == 0)
+                         // or padded float4 (omegabar, c, B'bar, x) (aux4 == 1)
     float* dx;           // W ybar (nullable)
     float* partials;     // per-block partial sums
     float* mbar;         // device scalar
     int n;
+    int aux4;
     // batched form only
     float* gz;           // padded-grid guide gradient
     float* dguide;       // guide gradient (nullable)
@@ -60,6 +63,20 @@ struct BwdArgs {
     int n1, n2, P, nd;
     float h;
 };
+
+__device__ __forceinline__ void write_sweep_d_factors(const BwdArgs& a, int idx, float obar, float cc,
+                                                      float bb, float xv, float f) {
+    if (a.aux4) {
+        reinterpret_cast<float4*>(a.aux5)[kAux4Lead + idx] = make_float4(obar, cc, bb, xv);
+    } else {
+        float* o = a.aux5 + 5 * (size_t)idx;
+        o[0] = obar;
+        o[1] = cc * bb;
+        o[2] = cc * (f - xv * bb);
+        o[3] = cc;
+        o[4] = cc * xv;
+    }
+}
 
 // B'bar, the (t, w) pairs, and per-block sums of ybar B'.
 __global__ void __launch_bounds__(256) k_bwd_prep(BwdArgs a) {
@@ -123,12 +140,7 @@ __global__ void __launch_bounds__(256) k_bwd_mid(BwdArgs a) {
     if (a.dx) a.dx[idx] = yb - dl * bb + cc * U;
     const float cbar = bb * a.bp[idx] / cc + f * dl / cc + xv * U + Wc;
     const float obar = -0.5f * cbar * cc * cc * cc;
-    float* o = a.aux5 + 5 * (size_t)idx;
-    o[0] = obar;
-    o[1] = cc * bb;
-    o[2] = cc * (f - xv * bb);
-    o[3] = cc;
-    o[4] = cc * xv;
+    write_sweep_d_factors(a, idx, obar, cc, bb, xv, f);
 }
 
 
@@ -201,12 +213,7 @@ __global__ void __launch_bounds__(256) k_bwd_mid_seg(const BwdArgs* __restrict__
     const float Wc = a.cw[2 * idx + 1];
     if (a.dx) a.dx[idx] = yb - dl * bb + cc * U;
     const float cbar = bb * a.bp[idx] / cc + f * dl / cc + xv * U + Wc;
-    float* o = a.aux5 + 5 * (size_t)idx;
-    o[0] = -0.5f * cbar * cc * cc * cc;
-    o[1] = cc * bb;
-    o[2] = cc * (f - xv * bb);
-    o[3] = cc;
-    o[4] = cc * xv;
+    write_sweep_d_factors(a, idx, -0.5f * cbar * cc * cc * cc, cc, bb, xv, f);
 }
 
 __global__ void __launch_bounds__(256) k_fold_seg(const BwdArgs* __restrict__ imgs, const int2* __restrict__ map) {
@@ -577,7 +584,8 @@ size_t backward_scratch_floats(int n1, int n2, int S, int P) {
     const size_t n = (size_t)n1 * n2;
     const int CH = 32 - 2 * P, CW = 32 - 2 * P;
     const size_t tiles = (size_t)((n1 + 2 * P + CH - 1) / CH) * ((n2 + 2 * P + CW - 1) / CW);
-    return 2 * n + 2 * n + 5 * n + (size_t)(n1 + 2 * P) * (n2 + 2 * P) + blocks256(n) + tiles + 8;
+    return 2 * n + 2 * n + std::max(5 * n, aux4_floats(n)) + (size_t)(n1 + 2 * P) * (n2 + 2 * P) +
+           blocks256(n) + tiles + 8;
 }
 
 int enqueue_backward(dsnlm_weights* w, const float* x, const float* dy, float* dx, float* dguide, float* dh,
@@ -587,7 +595,7 @@ int enqueue_backward(dsnlm_weights* w, const float* x, const float* dy, float* d
     float* pairs = scratch;
     float* cw = pairs + 2 * n;
     float* aux5 = cw + 2 * n;
-    float* gz = aux5 + 5 * n;
+    float* gz = aux5 + std::max(5 * n, aux4_floats(n));
     float* partials = gz + (size_t)(n1 + 2 * P) * (n2 + 2 * P);
     const int nb = blocks256(n);
     const int CH = 32 - 2 * P, CW = 32 - 2 * P;
@@ -605,6 +613,7 @@ int enqueue_backward(dsnlm_weights* w, const float* x, const float* dy, float* d
     a.pairs = pairs;
     a.cw = cw;
     a.aux5 = aux5;
+    a.aux4 = S <= 12;
     a.dx = dx;
     a.partials = partials;
     a.mbar = mbar;
@@ -633,6 +642,7 @@ int enqueue_backward(dsnlm_weights* w, const float* x, const float* dy, float* d
     if (S <= 12) {
         // sweep D on the forward sweep's machinery (32 x 64 s-tiles)
         d.aux5 = aux5;
+        d.mbar = mbar;
         d.gz = gz;
         d.hpart = hpart;
         const int CHn = 32 - 2 * P, CWn = 64 - 2 * P;
@@ -714,7 +724,7 @@ int upload_if_changed(T* dev, std::vector<T>& keep, const std::vector<T>& now, h
 int enqueue_backward_batch(const BwdImage* ims, int count, int S, int P, const TileRef* fwd_tiles, int nfwd_tiles,
                            hipStream_t st) {
     const int CHn = 32 - 2 * P, CWn = 64 - 2 * P;
-    // workspace layout per image: pairs 2n | cw 2n | aux5 5n | gz | partials nb | hpart nd | mbar
+    // workspace layout per image: pairs 2n | cw 2n | sweep-D factors | gz | partials nb | hpart nd | mbar
     size_t total = 0;
     std::vector<size_t> base(count);
     std::vector<int> nd(count), nb(count);
@@ -723,8 +733,9 @@ int enqueue_backward_batch(const BwdImage* ims, int count, int S, int P, const T
         const size_t n = (size_t)f.n1 * f.n2;
         nb[k] = (int)((n + 255) / 256);
         nd[k] = ((f.n1 + 2 * P + CHn - 1) / CHn) * ((f.n2 + 2 * P + CWn - 1) / CWn);
-        base[k] = total;
-        total += 9 * n + (size_t)(f.n1 + 2 * P) * (f.n2 + 2 * P) + nb[k] + nd[k] + 4;
+        base[k] = total;  // 256-byte aligned: the factors are read as float4
+        total += 4 * n + aux4_floats(n) + (size_t)(f.n1 + 2 * P) * (f.n2 + 2 * P) + nb[k] + nd[k] + 4;
+        total = (total + 63) & ~(size_t)63;
     }
     int rc = check_hip(grow_b(&g_bws.arrays, &g_bws.arrays_cap, total), "batched backward workspace");
     if (!rc) rc = check_hip(grow_b(&g_bws.args, &g_bws.args_cap, (size_t)count), "batched backward args");
@@ -748,7 +759,8 @@ int enqueue_backward_batch(const BwdImage* ims, int count, int S, int P, const T
         a.pairs = b;
         a.cw = b + 2 * n;
         a.aux5 = b + 4 * n;
-        a.gz = b + 9 * n;
+        a.aux4 = 1;
+        a.gz = b + 4 * n + aux4_floats(n);
         a.partials = a.gz + (size_t)(f.n1 + 2 * P) * (f.n2 + 2 * P);
         a.hpart = a.partials + nb[k];
         a.mbar = a.hpart + nd[k];
@@ -766,6 +778,7 @@ int enqueue_backward_batch(const BwdImage* ims, int count, int S, int P, const T
         d.aux_in = a.pairs;
         d.aux_out = a.cw;
         d.aux5 = a.aux5;
+        d.mbar = a.mbar;
         d.gz = a.gz;
         d.hpart = a.hpart;
         d.tile_base = (int)dtiles.size();

@@ -44,12 +44,12 @@ __device__ __forceinline__ int reflect_clamp(int k, int n) {
 // Tile geometry.  S_CLASS is the largest search half-width the instance
 // serves; it fixes the LDS row strides at compile time so every LDS access in
 // the shift loop is a base register plus an immediate offset.
-template <int P, int S_CLASS>
+template <int P, int S_CLASS, int L_ = 8>
 struct Geo {
     static constexpr int TH = 32, TW = 64;   // output tile
     static constexpr int R = 8;              // phase-1 strip height
-    static constexpr int L = 8;              // phase-2 segment length
-    static constexpr int NT = TH * (TW / L);  // 256 threads
+    static constexpr int L = L_;             // phase-2 segment length
+    static constexpr int NT = TH * (TW / L);  // threads: 256 (L = 8) or 512 (L = 4)
     static constexpr int TWE = TW + 2 * P;   // tile widened by the patch
     static constexpr int NITEM1 = TWE * (TH / R);
     static constexpr int ROUNDS1 = (NITEM1 + NT - 1) / NT;
@@ -71,9 +71,15 @@ struct Geo {
     static_assert(TH % R == 0 && TW % L == 0 && L % 4 == 0, "tile shape");
 };
 
-// Floats per pixel of the per-pixel input tile: pass A needs none (pairs that
-// leave the image are masked arithmetically), the other passes stage two.
-constexpr int naux(int mode) { return mode == kPassA ? 0 : (mode == kPassD ? 5 : 2); }
+// Sweep D carries many more live values per output (its own factors, the
+// partner factors, the guide-gradient accumulators), so it gives each thread
+// 4 outputs instead of 8 and runs 512 threads per tile.
+template <int P, int S_CLASS, int MODE>
+using GeoOf = Geo<P, S_CLASS, MODE == kPassD ? 4 : 8>;
+
+// per-pixel floats staged in LDS: none for pass A (its partners only mask) and
+// sweep D (it reads partner factors straight from memory), two otherwise
+constexpr int naux(int mode) { return (mode == kPassA || mode == kPassD) ? 0 : 2; }
 
 template <int P, int S_CLASS>
 size_t lds_floats(int S, int mode) {
@@ -100,11 +106,14 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
     return v;
 }
 
+// Sweep D: 512 threads, and registers capped at 128 so that two tiles share a
+// CU (its LDS would allow three).
 template <int P, int S_CLASS, int MODE, bool BATCH, int PIPE>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(MODE == kPassD ? 512 : 256)
+    __attribute__((amdgpu_waves_per_eu(MODE == kPassD ? 4 : 1)))
 k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__ tiles, int S,
         HatTable hat) {
-    using G = Geo<P, S_CLASS>;
+    using G = GeoOf<P, S_CLASS, MODE>;
     constexpr int NT = G::NT, TH = G::TH, TW = G::TW, R = G::R, L = G::L;
     constexpr int ZC = G::ZC, AW = G::AW, VW = G::VW;
     constexpr int NA = naux(MODE);
@@ -152,16 +161,7 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
         const int gj = reflect_clamp(tj0 - S - P + q, n2);
         Zs[q * ZC + r] = d.z[(size_t)gi * n2 + gj];
     }
-    if constexpr (NA == 5) {
-        for (int idx = tid; idx < AH * AWr; idx += NT) {
-            const int r = idx / AWr, q = idx - r * AWr;
-            const int gi = ti0 - S + r, gj = tj0 - S + q;
-            const bool in = (unsigned)gi < (unsigned)n1 && (unsigned)gj < (unsigned)n2;
-            float* dst = Aux + 5 * (r * AW + q);
-            const float* src = d.aux5 + 5 * ((size_t)(in ? gi : 0) * n2 + (in ? gj : 0));
-#pragma unroll
-            for (int k = 0; k < 5; ++k) dst[k] = in ? src[k] : 0.f;
-        }
+    if constexpr (MODE == kPassD) {
         for (int idx = tid; idx < 2 * TH * G::BW; idx += NT) Db[idx] = 0.f;  // and VDb
     }
     if constexpr (NA == 2) {
@@ -220,23 +220,49 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
     const int gi_own = ti0 + pi;
     const int gj_own = tj0 + pj;
 
-    // sweep D: own factors (omegabar, beta, gamma, c, c x), own guide value,
-    // core / in-image flags and the guide-gradient accumulators
+    // sweep D: own factors (omegabar and c scaled by -kappa, B'bar, x), own
+    // guide value, core / in-image flags and the guide-gradient accumulators.
+    // Partner factors are read from memory per shift through a buffer
+    // resource; its range check returns zeros past the image's array, and
+    // pairs with a partner outside the image are masked anyway.
     constexpr int LD = (MODE == kPassD) ? L : 1;
-    float own[LD][5];
+    float ow[LD], oc[LD], ob[LD], ox[LD];
     float zown[LD];
     bool sin_[LD], core_[LD];
     float accz[LD];
     float hacc = 0.f;
+    float nk = 0.f;                 // -kappa
+    float mb = 0.f;                 // mbar, routed to the argmax pixel s*
+    int si = -1, sj = -1;           // s*
+    bool fnear = false;             // can a pair of this tile touch s*?
+    int roff = 0;                   // byte offset of this thread's run at shift 0
+    const float4* rbase = nullptr;  // buffer base and size (bytes) for the partner reads
+    int rbytes = 0;
     if constexpr (MODE == kPassD) {
+        nk = -d.kappa;
+        const unsigned long long key = *d.key;
+        const int sstar = (int)(~(unsigned)(key & 0xffffffffu));
+        si = sstar / n2;
+        sj = sstar - si * n2;
+        mb = *d.mbar;
+        fnear = si >= ti0 - S && si < ti0 + TH + S && sj >= tj0 - S && sj < tj0 + TW + S;
+        const int row0 = ti0 - S > 0 ? ti0 - S : 0;
+        const float4* img4 = reinterpret_cast<const float4*>(d.aux5) + kAux4Lead;
+        rbase = img4 + (size_t)row0 * n2 - kAux4Lead;
+        const size_t recs = ((size_t)(n1 - row0) * n2 + kAux4Lead + kAux4Trail) * 16;
+        rbytes = (int)(recs < 0x7ffffff0u ? recs : 0x7ffffff0u);
+        roff = ((gi_own - row0) * n2 + gj_own + kAux4Lead) * 16;
 #pragma unroll
         for (int k = 0; k < L; ++k) {
-#pragma unroll
-            for (int q = 0; q < 5; ++q) own[k][q] = Aux[5 * (aux_base + k) + q];
             zown[k] = Zs[(pj + k + S + P) * ZC + pi + S + P];
             const int gj = gj_own + k;
             sin_[k] = (unsigned)gi_own < (unsigned)n1 && (unsigned)gj < (unsigned)n2;
             core_[k] = pi >= P && pi < TH - P && pj + k >= P && pj + k < TW - P;
+            const float4 o = sin_[k] ? img4[(size_t)gi_own * n2 + gj] : make_float4(0.f, 0.f, 0.f, 0.f);
+            ow[k] = nk * o.x;
+            oc[k] = nk * o.y;
+            ob[k] = o.z;
+            ox[k] = o.w;
             accz[k] = 0.f;
         }
     }
@@ -273,9 +299,13 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
     // phase 2 is split so its LDS reads can be issued before the next
     // shift's phase 1: load() fetches V (and the per-pixel inputs), math()
     // forms D by horizontal sliding sums and a = exp2(log2 Lambda - beta D).
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float4*>(rbase), (short)0, rbytes, 0x00020000);
     constexpr int NV = ((L + 2 * P + 3) / 4) * 4;
     float vv[NV];
     float2 cv[L];
+    constexpr int LR = (MODE == kPassD) ? L : 1;
+    float4 rv[LR];
     auto load2 = [&](int dy, int dx, const float* V) {
         const float* vr = V + pi * VW + pj;
 #pragma unroll
@@ -292,6 +322,21 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
             for (int k = 0; k < L; ++k) cv[k] = ap[k];
         }
     };
+    auto loadr = [&](int dy, int dx) {
+        if constexpr (MODE == kPassD) {
+            const int o = roff + (dy * n2 + dx) * 16;
+            // keep these loads at this point of the schedule: hoisting them
+            // into earlier shifts only raises register pressure
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int k = 0; k < L; ++k)
+                rv[k] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, o + 16 * k, 0, 0));
+            __builtin_amdgcn_sched_barrier(0);
+        } else {
+            (void)dy;
+            (void)dx;
+        }
+    };
     auto math2 = [&](int dy, int dx) {
         const float lg = hat.lg[dy + S] + hat.lg[dx + S];
         float hs = vv[0];
@@ -304,7 +349,7 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
             hs += vv[k + 2 * P] - vv[k - 1];
             Dk[k] = hs;
         }
-        if constexpr (NA == 0) {
+        if constexpr (MODE == kPassA) {
             // the whole tile keeps its partners inside the image for this shift?
             const bool inside = ti0 + dy >= 0 && ti0 + TH - 1 + dy < n1 && tj0 + dx >= 0 &&
                                 tj0 + TW - 1 + dx < n2;
@@ -320,24 +365,38 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
                     acc0[k] += ok ? a : 0.f;
                 }
             }
-        } else if constexpr (NA == 5) {
-            // Dbar_{s,d} + Dbar_{s+d,-d} = -kappa a (abar_{s,d} + abar_{s+d,-d})
-            const float kap = d.kappa;
+        } else if constexpr (MODE == kPassD) {
+            // -kappa (abar_{s,d} + abar_{s+d,-d}) with r = s + d:
+            //   -kappa (omegabar_s + omegabar_r)
+            //   - kappa c_s c_r ((B'bar_s - B'bar_r)(x_r - x_s) + f_s + f_r)
             const bool rowok = (unsigned)(gi_own + dy) < (unsigned)n1;
-            const float* nb = Aux + 5 * (aux_base + dy * AW + dx);
-#pragma unroll
-            for (int k = 0; k < L; ++k) {
+            auto pair = [&](int k, float as, float q) {
                 const float a = __builtin_amdgcn_exp2f(lg - beta * Dk[k]);
-                const float* r5 = nb + 5 * k;
-                float as = own[k][0] + r5[0];
-                as = fmaf(own[k][1], r5[4], as);
-                as = fmaf(own[k][2], r5[3], as);
-                as = fmaf(r5[1], own[k][4], as);
-                as = fmaf(r5[2], own[k][3], as);
                 const bool ok = sin_[k] && rowok && (unsigned)(gj_own + k + dx) < (unsigned)n2;
-                const float db = ok ? -kap * a * as : 0.f;
+                const float db = ok ? a * as : 0.f;
                 hacc = core_[k] ? fmaf(db, Dk[k], hacc) : hacc;
                 Db[pi * G::BW + pj + k + P] = db;
+                (void)q;
+            };
+            if (!fnear) {
+#pragma unroll
+                for (int k = 0; k < L; ++k) {
+                    const float4 r = rv[k];
+                    const float q = oc[k] * r.y;
+                    pair(k, fmaf(q, (ob[k] - r.z) * (r.w - ox[k]), fmaf(nk, r.x, ow[k])), q);
+                }
+            } else {
+                // the f terms live on s* alone
+                const bool rs = gi_own + dy == si, ss = gi_own == si;
+#pragma unroll
+                for (int k = 0; k < L; ++k) {
+                    const float4 r = rv[k];
+                    const float q = oc[k] * r.y;
+                    const float fr = (rs && gj_own + k + dx == sj) ? mb : 0.f;
+                    const float fs = (ss && gj_own + k == sj) ? mb : 0.f;
+                    const float e = fmaf(ob[k] - r.z, r.w - ox[k], fs + fr);
+                    pair(k, fmaf(q, e, fmaf(nk, r.x, ow[k])), q);
+                }
             }
         } else {
 #pragma unroll
@@ -349,42 +408,42 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
         }
     };
 
-    // sweep D tail of one shift: box-sum Dbar over the patch and accumulate
-    // 2 (z(p) - z(p+d)) box(Dbar)(p) on the core
-    auto tailD = [&](int dy, int dx) {
+    // sweep D after D-bar of a shift is in LDS: box-sum it over the patch
+    // (phase 3 vertical on the core rows, column strips; phase 4 horizontal)
+    // and accumulate 2 (z(p) - z(p+d)) box(Dbar)(p) on the core.  Phase 3 of
+    // shift t shares a barrier interval with phase 1 of shift t+1, and phase 4
+    // of shift t with phase 2 of shift t+1, so a shift costs two barriers.
+    auto phase3 = [&]() {
         if constexpr (MODE == kPassD) {
             constexpr int BW = G::BW;
-            __syncthreads();
-            // phase 3: vertical sliding box sums on the core rows (column strips)
-            {
-                constexpr int R3 = (G::CH + 3) / 4;
-                const int c = tid % TW, strip = tid / TW;
-                const int r0 = P + strip * R3;
-                const int r1 = (r0 + R3 < TH - P) ? r0 + R3 : TH - P;
-                if (r0 < r1) {
-                    float v = Db[(r0 - P) * BW + c + P];
+            constexpr int R3 = (G::CH + 3) / 4;
+            const int c = tid % TW, strip = tid / TW;
+            const int r0 = P + strip * R3;
+            const int r1 = (r0 + R3 < TH - P) ? r0 + R3 : TH - P;
+            if (r0 < r1) {
+                float v = Db[(r0 - P) * BW + c + P];
 #pragma unroll
-                    for (int t = 1; t <= 2 * P; ++t) v += Db[(r0 - P + t) * BW + c + P];
-                    VDb[r0 * BW + c + P] = v;
-                    for (int r = r0 + 1; r < r1; ++r) {
-                        v += Db[(r + P) * BW + c + P] - Db[(r - P - 1) * BW + c + P];
-                        VDb[r * BW + c + P] = v;
-                    }
+                for (int t = 1; t <= 2 * P; ++t) v += Db[(r0 - P + t) * BW + c + P];
+                VDb[r0 * BW + c + P] = v;
+                for (int r = r0 + 1; r < r1; ++r) {
+                    v += Db[(r + P) * BW + c + P] - Db[(r - P - 1) * BW + c + P];
+                    VDb[r * BW + c + P] = v;
                 }
             }
-            __syncthreads();
-            // phase 4: horizontal sliding box sums, accumulate on the core
-            {
-                const float* vr = VDb + pi * BW + pj;
-                float hs = vr[0];
+        }
+    };
+    auto phase4 = [&](int dy, int dx) {
+        if constexpr (MODE == kPassD) {
+            constexpr int BW = G::BW;
+            const float* vr = VDb + pi * BW + pj;
+            float hs = vr[0];
 #pragma unroll
-                for (int q = 1; q <= 2 * P; ++q) hs += vr[q];
-                const float* zq = Zs + (pj + S + P + dx) * ZC + pi + S + P + dy;
+            for (int q = 1; q <= 2 * P; ++q) hs += vr[q];
+            const float* zq = Zs + (pj + S + P + dx) * ZC + pi + S + P + dy;
 #pragma unroll
-                for (int k = 0; k < L; ++k) {
-                    if (k > 0) hs += vr[k + 2 * P] - vr[k - 1];
-                    accz[k] = fmaf(2.f * (zown[k] - zq[k * ZC]), hs, accz[k]);
-                }
+            for (int k = 0; k < L; ++k) {
+                if (k > 0) hs += vr[k + 2 * P] - vr[k - 1];
+                accz[k] = fmaf(2.f * (zown[k] - zq[k * ZC]), hs, accz[k]);
             }
         } else {
             (void)dy;
@@ -403,6 +462,7 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
         constexpr int GW = G::GWIN;
         constexpr int NW = NE + GW - 1;
         int t = 0;
+        int pdy = 0, pdx = 0;  // previous shift (sweep D)
         for (dx = -S; dx <= S; ++dx) {
             for (int dy0 = -S; dy0 <= S; dy0 += GW) {
                 float win[G::ROUNDS1][NW];
@@ -435,14 +495,30 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
                                 }
                             }
                         }
+                        if constexpr (MODE == kPassD) {
+                            loadr(dy0 + g, dx);  // in flight over phases 3 and 4
+                            if (t > 0) phase3();
+                        }
                         __syncthreads();
+                        if constexpr (MODE == kPassD) {
+                            if (t > 0) phase4(pdy, pdx);
+                        }
                         load2(dy0 + g, dx, V);
                         math2(dy0 + g, dx);
-                        tailD(dy0 + g, dx);
+                        if constexpr (MODE == kPassD) {
+                            __syncthreads();
+                            pdy = dy0 + g;
+                            pdx = dx;
+                        }
                         ++t;
                     }
                 }
             }
+        }
+        if constexpr (MODE == kPassD) {  // drain the last shift
+            phase3();
+            __syncthreads();
+            phase4(pdy, pdx);
         }
     } else if constexpr (PIPE == 1) {
         // software pipeline: phase 1 of shift t+1 and phase 2 of shift t share
@@ -485,7 +561,7 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
                 d.gz[(size_t)(gi_own + P) * W2 + gj + P] = accz[k];
         }
         // block partial of sum Dbar D: fixed-order LDS tree (V is free: its
-        // last reads were before the two barriers of the last shift's tail)
+        // last reads, in the last shift's phase 2, precede two barriers)
         float* red = Vb;
         red[tid] = hacc;
         __syncthreads();
@@ -582,7 +658,7 @@ hipError_t ensure_attr() {
 template <int P, int S_CLASS, int MODE, bool BATCH, int PIPE>
 hipError_t launch_var(int S, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
                       int ntiles, hipStream_t st) {
-    using G = Geo<P, S_CLASS>;
+    using G = GeoOf<P, S_CLASS, MODE>;
     const size_t lds = lds_floats<P, S_CLASS>(S, MODE) * sizeof(float);
     hipError_t e = ensure_attr<P, S_CLASS, MODE, BATCH, PIPE>();
     if (e != hipSuccess) return e;
@@ -602,11 +678,12 @@ hipError_t launch_one(int S, const ImgDesc& one, const ImgDesc* batch, const Til
     if constexpr (MODE == kPassD) {
         if (lds_floats<P, S_CLASS>(S, MODE) * sizeof(float) > 160 * 1024) return hipErrorInvalidValue;
         return launch_var<P, S_CLASS, MODE, BATCH, 2>(S, one, batch, tiles, ntiles, st);
-    }
-    switch (sweep_variant(MODE, S, P)) {
-        case 1: return launch_var<P, S_CLASS, MODE, BATCH, 1>(S, one, batch, tiles, ntiles, st);
-        case 2: return launch_var<P, S_CLASS, MODE, BATCH, 2>(S, one, batch, tiles, ntiles, st);
-        default: return launch_var<P, S_CLASS, MODE, BATCH, 0>(S, one, batch, tiles, ntiles, st);
+    } else {
+        switch (sweep_variant(MODE, S, P)) {
+            case 1: return launch_var<P, S_CLASS, MODE, BATCH, 1>(S, one, batch, tiles, ntiles, st);
+            case 2: return launch_var<P, S_CLASS, MODE, BATCH, 2>(S, one, batch, tiles, ntiles, st);
+            default: return launch_var<P, S_CLASS, MODE, BATCH, 0>(S, one, batch, tiles, ntiles, st);
+        }
     }
 }
 

@@ -31,7 +31,9 @@ struct ImgDesc {
     // backward
     const float* aux_in;   // per-pixel float2 inputs of the backward sweep C
     float* aux_out;        // its per-pixel float2 outputs
-    const float* aux5;     // per-pixel factors of the backward sweep D (5 floats)
+    const float* aux5;     // per-pixel factors of the backward sweep D: float4
+                           // (omegabar, c, B'bar, x) per pixel
+    const float* mbar;     // device scalar mbar of the backward (sweep D)
     float* gz;             // sweep D output: gradient on the padded grid
     float* hpart;          // sweep D output: per-block partial sums for dh
     int n1, n2;
@@ -40,6 +42,13 @@ struct ImgDesc {
     float h;
     int tile_base;         // first entry of this image in a batch tile list
 };
+
+// Per-pixel float4 factors of sweep D are stored with this many zero-cost pad
+// pixels before and after each image, so that a thread's run of partners
+// never leaves the allocation (partners outside the image are masked).
+constexpr int kAux4Lead = 32;
+constexpr int kAux4Trail = 128;
+inline size_t aux4_floats(size_t n) { return 4 * (n + kAux4Lead + kAux4Trail); }
 
 // One tile of a batch: image index and tile origin.
 struct TileRef {
