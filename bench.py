@@ -31,12 +31,15 @@ if ROOT not in sys.path:
 # is the fallback when the probe is unavailable).
 VALU_LANE_OPS_PER_S = 256 * 64 * 2.4e9
 EXP_SLOTS_FALLBACK = 4.0
-# Algorithmic FP32 VALU ops per (pixel, in-window shift), transcendental apart:
+# The sweeps evaluate each unordered pair {s, s + d} once (half window, the
+# weight is symmetric) and add it to both pixels.  Algorithmic FP32 VALU ops
+# per evaluated pair, the transcendental apart:
 #   weight: diff 1 + square 1 + separable sliding box 4 + exponent 1 (+ 1 exp)
-#   pass A adds 1 (accumulate omega); pass B adds 2 (two FMAs)
-VALU_PASS_A = 8
-VALU_PASS_B = 9
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sweep_batched64_S10P3.md")
+#   pass A adds 2 (omega at s and at s + d); pass B adds 4 (two FMAs at each)
+VALU_PASS_A = 9
+VALU_PASS_B = 11
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_half_b_batched64_S10P3.md")
+TRAFFIC_SOURCE = os.path.join(ROOT, "paper_1901_06110_amd", "csrc", "dsnlm_half.hip")
 
 
 def measured_traffic(kind: str):
@@ -45,18 +48,19 @@ def measured_traffic(kind: str):
     import hashlib
     try:
         text = open(TRAFFIC_FILE).read()
-        src = open(os.path.join(ROOT, "paper_1901_06110_amd", "csrc", "dsnlm_sweep.hip"), "rb").read()
+        src = open(TRAFFIC_SOURCE, "rb").read()
     except OSError:
         return None
     vals = dict(l.split(": ", 1) for l in text.splitlines() if ": " in l and not l.startswith(("|", "#")))
-    if vals.get("source_sha256_dsnlm_sweep.hip", "").strip() != hashlib.sha256(src).hexdigest():
+    if vals.get("source_sha256_dsnlm_half.hip", "").strip() != hashlib.sha256(src).hexdigest():
         return None
     v = vals.get(f"traffic_bytes_per_launch_{kind}")
     return float(v) if v else None
 
 
 def window_pairs(n1: int, n2: int, S: int) -> int:
-    """Number of (pixel, shift) pairs with both pixels in the image."""
+    """Number of ordered (pixel, shift) pairs with both pixels in the image
+    (d = 0 included); the unordered pairs with d != 0 are (this - n1 n2) / 2."""
     def axis(n):
         tot = 0
         for i in range(n):
@@ -232,7 +236,7 @@ def main():
     import ctypes as C
     tot = {}
     for name, kind in [("pass_a", _lib.K_PASS_A), ("pass_b", _lib.K_PASS_B),
-                       ("epilogue", _lib.K_EPILOGUE)]:
+                       ("prep_and_gather", _lib.K_HALF_AUX), ("epilogue", _lib.K_EPILOGUE)]:
         t = C.c_double()
         n = C.c_int()
         lib.dsnlm_profile_query(kind, C.byref(t), C.byref(n))
@@ -253,7 +257,8 @@ def main():
     pb_avg_ms = pb_ms / max(pb_n, 1)
     ops_pair_b = VALU_PASS_B + exp_slots
     ops_pair_a = VALU_PASS_A + exp_slots
-    ops_per_launch = ops_pair_b * pairs / launches_per_step
+    half_pairs = (pairs - total_px) / 2  # pairs the sweeps evaluate
+    ops_per_launch = ops_pair_b * half_pairs / launches_per_step
     achieved = ops_per_launch / (pb_avg_ms * 1e-3) / 1e12
     peak = VALU_LANE_OPS_PER_S / 1e12
 
@@ -283,7 +288,7 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "k_sweep pass B (step-S2 row sums, B', max m)",
+            "kernel": "k_half pass B (half-window step-S2 sums at both pixels of each pair)",
             "achieved": achieved,
             "peak": peak,
             "unit": "Tops/s",
@@ -292,7 +297,7 @@ def main():
             "traffic": measured_traffic("pass_b"),
             "ops_per_pair": ops_pair_b,
             "exp_slots": exp_slots,
-            "pairs_per_launch": pairs / launches_per_step,
+            "pairs_evaluated_per_launch": half_pairs / launches_per_step,
             "avg_launch_ms": pb_avg_ms,
         },
         "kernel_ms_per_step": {k: v[0] / prof_steps for k, v in tot.items()},
@@ -300,7 +305,7 @@ def main():
         "fwd_bwd_over_fwd": fb["ratio"] if fb else None,
         "fwd_bwd": fb,
         "ladmm_sr_512": lad,
-        "forward_roofline_frac": (ops_pair_a + ops_pair_b) * pairs / (ms * 1e-3) / VALU_LANE_OPS_PER_S,
+        "forward_roofline_frac": (ops_pair_a + ops_pair_b) * half_pairs / (ms * 1e-3) / VALU_LANE_OPS_PER_S,
         "wall_s_timed": wall,
     }
     if not args.no_cpu:

@@ -254,7 +254,8 @@ typedef enum {
     DSNLM_K_PASS_D = 6,     /* backward sweep: guide and bandwidth sums     */
     DSNLM_K_BWD_TAIL = 7,   /* backward: fold and final reductions          */
     DSNLM_K_LADMM = 8,      /* forward-model, gradient and update kernels   */
-    DSNLM_K_COUNT = 9
+    DSNLM_K_HALF_AUX = 9,   /* half-window sweeps: factor prep and gather   */
+    DSNLM_K_COUNT = 10
 } dsnlm_kernel_kind;
 
 int dsnlm_profile_enable(int on);

@@ -143,7 +143,7 @@ EXPORTED = [
     "ladmm_step_backward", "ladmm_solve_backward", "dsnlm_backward_batched",
 ]
 
-K_PASS_A, K_PASS_B, K_APPLY, K_EPILOGUE, K_BWD_PREP, K_PASS_C, K_PASS_D, K_BWD_TAIL, K_LADMM = range(9)
+K_PASS_A, K_PASS_B, K_APPLY, K_EPILOGUE, K_BWD_PREP, K_PASS_C, K_PASS_D, K_BWD_TAIL, K_LADMM, K_HALF_AUX = range(10)
 
 
 def check(code: int) -> None:

@@ -54,6 +54,8 @@ ImgDesc base_desc(const dsnlm_weights* w) {
     d.delta = w->delta;
     d.bp = w->bp;
     d.key = w->key;
+    d.part = w->part;
+    d.pf = w->part ? half_pf(w->part, w->n1, w->n2, w->S) : nullptr;
     d.n1 = w->n1;
     d.n2 = w->n2;
     const double np = 2.0 * w->P + 1.0;
@@ -87,6 +89,15 @@ int prepare_handle(int n1, int n2, int S, int P, float h, dsnlm_weights** out) {
         }
         *out = w;
     }
+    const size_t need = half_part_floats(n1, n2, S);
+    if (w->part_cap < need) {
+        (void)hipFree(w->part);
+        w->part = nullptr;
+        w->part_cap = 0;
+        int rc = check_hip(hipMalloc(&w->part, need * sizeof(float)), "hipMalloc partial buffer");
+        if (rc) return rc;
+        w->part_cap = need;
+    }
     w->S = S;
     w->P = P;
     w->h = h;
@@ -113,6 +124,7 @@ void dsnlm_weights_destroy(dsnlm_weights* w) {
     (void)hipFree(w->key);
     (void)hipFree(w->scratch);
     (void)hipFree(w->bscratch);
+    (void)hipFree(w->part);
     delete w;
 }
 

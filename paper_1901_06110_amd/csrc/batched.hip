@@ -27,6 +27,8 @@ struct BatchWorkspace {
     size_t descs_cap = 0;
     TileRef* tiles = nullptr;
     size_t tiles_cap = 0;
+    float* part = nullptr;    // partial buffers of the half-window sweeps
+    size_t part_cap = 0;
     std::vector<ImgDesc> last_descs;
     std::vector<TileRef> last_tiles;
     int last_S = -1, last_P = -1;  // of the last forward (for the backward)
@@ -94,7 +96,11 @@ extern "C" int dsnlm_forward_batched(const dsnlm_image* imgs, int count, int S, 
 
     std::vector<ImgDesc> descs(count);
     std::vector<TileRef> tiles;
-    size_t off = 0;
+    size_t part_total = 0;
+    for (int k = 0; k < count; ++k) part_total += half_part_floats(imgs[k].n1, imgs[k].n2, S);
+    rc = check_hip(grow(&g_ws.part, &g_ws.part_cap, part_total), "batch partial buffers");
+    if (rc) return rc;
+    size_t off = 0, part_off = 0;
     const double log2e = 1.4426950408889634;
     for (int k = 0; k < count; ++k) {
         const dsnlm_image& im = imgs[k];
@@ -107,6 +113,9 @@ extern "C" int dsnlm_forward_batched(const dsnlm_image* imgs, int count, int S, 
         d.delta = g_ws.arrays + total + off;
         d.bp = g_ws.arrays + 2 * total + off;
         d.key = g_ws.keys + k;
+        d.part = g_ws.part + part_off;
+        d.pf = half_pf(d.part, im.n1, im.n2, S);
+        part_off += half_part_floats(im.n1, im.n2, S);
         d.n1 = im.n1;
         d.n2 = im.n2;
         const double np = 2.0 * P + 1.0;
@@ -151,6 +160,7 @@ extern "C" int dsnlm_forward_batched(const dsnlm_image* imgs, int count, int S, 
     g_ws.last_S = S;
     g_ws.last_P = P;
     ImgDesc none{};
+    none.part = g_ws.part;  // every descriptor carries a partial buffer
     rc = check_hip(launch_sweep(kPassA, S, P, none, g_ws.descs, g_ws.tiles, nt, st), "batch pass A");
     if (!rc) rc = check_hip(launch_sweep(kPassBApply, S, P, none, g_ws.descs, g_ws.tiles, nt, st), "batch pass B");
     if (!rc) rc = check_hip(launch_epilogue(none, g_ws.descs, g_ws.tiles, nt, S, P, st), "batch epilogue");

@@ -584,15 +584,15 @@ size_t backward_scratch_floats(int n1, int n2, int S, int P) {
     const size_t n = (size_t)n1 * n2;
     const int CH = 32 - 2 * P, CW = 32 - 2 * P;
     const size_t tiles = (size_t)((n1 + 2 * P + CH - 1) / CH) * ((n2 + 2 * P + CW - 1) / CW);
-    return 2 * n + 2 * n + std::max(5 * n, aux4_floats(n)) + (size_t)(n1 + 2 * P) * (n2 + 2 * P) +
-           blocks256(n) + tiles + 8;
+    return 2 * (size_t)kFacLead + 2 * n + 2 * n + std::max(5 * n, aux4_floats(n)) +
+           (size_t)(n1 + 2 * P) * (n2 + 2 * P) + blocks256(n) + tiles + 8;
 }
 
 int enqueue_backward(dsnlm_weights* w, const float* x, const float* dy, float* dx, float* dguide, float* dh,
                      float* scratch, hipStream_t st) {
     const int n1 = w->n1, n2 = w->n2, S = w->S, P = w->P;
     const size_t n = (size_t)n1 * n2;
-    float* pairs = scratch;
+    float* pairs = scratch + 2 * kFacLead;  // read by the half-window sweep C as partner factors
     float* cw = pairs + 2 * n;
     float* aux5 = cw + 2 * n;
     float* gz = aux5 + std::max(5 * n, aux4_floats(n));
@@ -734,7 +734,8 @@ int enqueue_backward_batch(const BwdImage* ims, int count, int S, int P, const T
         nb[k] = (int)((n + 255) / 256);
         nd[k] = ((f.n1 + 2 * P + CHn - 1) / CHn) * ((f.n2 + 2 * P + CWn - 1) / CWn);
         base[k] = total;  // 256-byte aligned: the factors are read as float4
-        total += 4 * n + aux4_floats(n) + (size_t)(f.n1 + 2 * P) * (f.n2 + 2 * P) + nb[k] + nd[k] + 4;
+        total += 2 * (size_t)kFacLead + 4 * n + aux4_floats(n) + (size_t)(f.n1 + 2 * P) * (f.n2 + 2 * P) +
+                 nb[k] + nd[k] + 4;
         total = (total + 63) & ~(size_t)63;
     }
     int rc = check_hip(grow_b(&g_bws.arrays, &g_bws.arrays_cap, total), "batched backward workspace");
@@ -748,7 +749,7 @@ int enqueue_backward_batch(const BwdImage* ims, int count, int S, int P, const T
     for (int k = 0; k < count; ++k) {
         const ImgDesc& f = *ims[k].fwd;
         const size_t n = (size_t)f.n1 * f.n2;
-        float* b = g_bws.arrays + base[k];
+        float* b = g_bws.arrays + base[k] + 2 * kFacLead;  // lead pad before the (t, w) pairs
         BwdArgs a{};
         a.x = f.x;
         a.dy = ims[k].dy;
@@ -804,6 +805,7 @@ int enqueue_backward_batch(const BwdImage* ims, int count, int S, int P, const T
         if (rc) return rc;
     }
     ImgDesc none{};
+    none.part = descs[0].part;  // non-null: the forward's descriptors carry partial buffers
     rc = check_hip(launch_sweep(kPassC, S, P, none, g_bws.descs, fwd_tiles, nfwd_tiles, st), "batched sweep C");
     if (rc) return rc;
     {

@@ -1,0 +1,566 @@
+// Half-window form of the accumulating sweeps (pass A, the pass-B family and
+// the backward sweep C) on gfx950.
+//
+// The kernel weight of a pair is symmetric, a_{s,s+d} = a_{s+d,s}: the hat
+// Lambda_d is even in d and D_{s,d} = D_{s+d,-d} (Section 3, the patch
+// distance and eq. for a).  So every unordered pair {s, r = s + d} is
+// evaluated once, for the shifts of a half window H = {dy > 0} u {dy = 0,
+// dx > 0}; d = 0 (a = 1) is added analytically.  Each sweep sums, for every
+// pixel, a times a per-pixel factor of the partner:
+//
+//   pass A       sum_r a                       (omega)
+//   pass B, apply sum_r a c_r, sum_r a c_r x_r  (delta, B')
+//   sweep C      sum_r a t_r, sum_r a w_r      (backward)
+//
+// A tile adds a * factor(r) to its own pixel s in registers and a * factor(s)
+// to the partner r in an LDS accumulator that spans the tile's partner region
+// (S rows below, S columns either side).  Partner factors are read per shift
+// from a per-pixel float2 array in memory (range-checked buffer loads), which
+// keeps the LDS at two tiles per CU.  The region is written to a
+// per-tile partial buffer, and a gather kernel adds for every pixel the
+// regions of the (at most six) tiles covering it, in a fixed order, then the
+// d = 0 term, and finishes the pass exactly as the full-window sweep does.
+// The sums are the same as the full window's, up to the order of the FP32
+// additions.
+#include <cmath>
+
+#include "internal.h"
+
+namespace dsnlm {
+
+namespace {
+
+template <int P, int S_CLASS>
+struct HGeo {
+    static constexpr int TH = 32, TW = 64;   // s-tile (the forward tiling)
+    static constexpr int R = 8;              // phase-1 strip height
+    static constexpr int L = 4;              // outputs per thread
+    static constexpr int NT = TH * (TW / L);  // 512 threads
+    static constexpr int TWE = TW + 2 * P;
+    static constexpr int NITEM1 = TWE * (TH / R);
+    static constexpr int GWIN = 7;
+    // guide tile, column-major: rows ti0-P .. ti0+TH+S+P (+ window slack)
+    static constexpr int ZC0 = TH + S_CLASS + 2 * P + GWIN - 1;
+    static constexpr int ZC = ZC0 | 1;
+    // partner region: rows ti0 .. ti0+TH+S, columns tj0-S .. tj0+TW+S
+    static constexpr int AW = (TW + 2 * S_CLASS) | 1;
+    static constexpr int VW0 = ((TWE + 3) / 4) * 4;
+    static constexpr int VW = ((VW0 / 4) % 2) ? VW0 : VW0 + 4;
+    static_assert(NITEM1 <= NT, "one phase-1 item per thread");
+};
+
+// floats per partner-region entry in LDS: the sum of a (pass A) or the two
+// factor-weighted sums (the others)
+constexpr int half_nc(int mode) { return mode == kPassA ? 1 : 2; }
+// channels of the partial buffer
+constexpr int half_np(int mode) { return mode == kPassA ? 1 : 2; }
+
+template <int P, int S_CLASS>
+size_t half_lds_floats(int S, int mode) {
+    using G = HGeo<P, S_CLASS>;
+    const size_t ZWr = G::TW + 2 * (S + P);
+    size_t n = (ZWr * G::ZC + 3) & ~(size_t)3;
+    n += (size_t)2 * G::TH * G::VW;
+    n += (size_t)(G::TH + S) * G::AW * half_nc(mode);
+    return n;
+}
+
+__device__ __forceinline__ int reflect_h(int k, int n) {
+    if (k < 0) k = -k - 1;
+    if (k >= n) k = 2 * n - 1 - k;
+    k = k < 0 ? 0 : k;
+    k = k >= n ? n - 1 : k;
+    return k;
+}
+
+// the tile's index within its image and the image's tile columns
+__device__ __forceinline__ int local_tile(int ti0, int tj0, int n2, int TH, int TW) {
+    const int ntx = (n2 + TW - 1) / TW;
+    return (ti0 / TH) * ntx + tj0 / TW;
+}
+
+template <int P, int S_CLASS, int MODE, bool BATCH>
+__global__ void __launch_bounds__(512)
+k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__ tiles, int S,
+       HatTable hat) {
+    using G = HGeo<P, S_CLASS>;
+    constexpr int NT = G::NT, TH = G::TH, TW = G::TW, R = G::R, L = G::L;
+    constexpr int ZC = G::ZC, AW = G::AW, VW = G::VW;
+    constexpr int NC = half_nc(MODE);
+    constexpr int NE = R + 2 * P;
+    extern __shared__ __align__(16) float lds[];
+    const int tid = threadIdx.x;
+
+    ImgDesc d;
+    int ti0, tj0;
+    bool first;
+    if constexpr (BATCH) {
+        const TileRef t = tiles[blockIdx.x];
+        d = batch[t.img];
+        ti0 = t.ti0;
+        tj0 = t.tj0;
+        first = (t.flags & 1) != 0;
+    } else {
+        d = one;
+        ti0 = blockIdx.y * TH;
+        tj0 = blockIdx.x * TW;
+        first = blockIdx.x == 0 && blockIdx.y == 0;
+    }
+    const int n1 = d.n1, n2 = d.n2;
+    const int ZH = TH + S + 2 * P, ZWr = TW + 2 * (S + P);
+    const int AH = TH + S, AWr = TW + 2 * S;
+    float* Zs = lds;
+    int off = (ZWr * ZC + 3) & ~3;
+    float* Vb = lds + off;
+    off += 2 * TH * VW;
+    float* Acc = lds + off;  // partner region, NC floats per entry
+
+    // ---- staging: guide rows ti0-P .. ti0+TH+S+P (mirrored), partner region
+    for (int idx = tid; idx < ZH * ZWr; idx += NT) {
+        const int r = idx / ZWr, q = idx - r * ZWr;
+        const int gi = reflect_h(ti0 - P + r, n1);
+        const int gj = reflect_h(tj0 - S - P + q, n2);
+        Zs[q * ZC + r] = d.z[(size_t)gi * n2 + gj];
+    }
+    for (int idx = tid; idx < AH * AWr * NC; idx += NT) {
+        const int r = idx / (AWr * NC), q = idx - r * (AWr * NC);
+        Acc[r * AW * NC + q] = 0.f;
+    }
+    if constexpr (MODE == kPassA) {
+        if (first && tid == 0) *d.key = 0ull;  // the pass-B gather takes the max after this
+    }
+    __syncthreads();
+
+    // ---- phase-1 item: one column strip of R rows (threads past NITEM1 idle)
+    const bool has1 = tid < G::NITEM1;
+    const int it = has1 ? tid : 0;
+    const int strip = it / G::TWE;
+    const int c1 = it - strip * G::TWE;
+    const int zoff = (c1 + S) * ZC + strip * R;
+    const int voff = strip * R * VW + c1;
+    float ref[NE];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) ref[q] = Zs[zoff + q];
+
+    const int pi = tid % TH;
+    const int pj = (tid / TH) * L;
+    const int own = pi * AW + pj + S;  // own pixel in the partner region
+    float acc0[L], acc1[L], f0[L], f1[L];
+    // per-pixel partner factors: (t, w) of the backward, else (c, c x) made
+    // by the preparation kernel
+    const float2* fac = reinterpret_cast<const float2*>(MODE == kPassC ? d.aux_in : d.pf);
+    const size_t fbytes = ((size_t)n1 * n2 + kFacLead) * 8;
+    const __amdgpu_buffer_rsrc_t frs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float2*>(NC == 2 ? fac - kFacLead : nullptr), (short)0,
+        NC == 2 ? (int)(fbytes < 0x7ffffff0u ? fbytes : 0x7ffffff0u) : 0, 0x00020000);
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        acc0[k] = 0.f;
+        acc1[k] = 0.f;
+        f0[k] = 0.f;
+        f1[k] = 0.f;
+        if constexpr (NC == 2) {
+            const int gi = ti0 + pi, gj = tj0 + pj + k;
+            if (gi < n1 && gj < n2) {
+                const float2 v = fac[(size_t)gi * n2 + gj];
+                f0[k] = v.x;
+                f1[k] = v.y;
+            }
+        }
+    }
+    const float beta = d.beta;
+    const int gi_own = ti0 + pi, gj_own = tj0 + pj;
+    const bool s_in = ti0 + TH <= n1 && tj0 + TW <= n2;
+
+    constexpr int NV = ((L + 2 * P + 3) / 4) * 4;
+    constexpr int GW = G::GWIN;
+    constexpr int NW = NE + GW - 1;
+    int t = 0;
+    for (int dx = -S; dx <= S; ++dx) {
+        const int dylo = dx > 0 ? 0 : 1;  // the half window
+        for (int dy0 = dylo; dy0 <= S; dy0 += GW) {
+            float win[NW];
+            {
+                const float* zq = Zs + zoff + dx * ZC + dy0;
+#pragma unroll
+                for (int q = 0; q < NW; ++q) win[q] = zq[q];
+            }
+#pragma unroll
+            for (int g = 0; g < GW; ++g) {
+                const int dy = dy0 + g;
+                if (dy <= S) {
+                    float* V = Vb + (t & 1) * (TH * VW);
+                    // partner factors of this shift, in flight over phase 1;
+                    // outside the array the range check returns zeros (those
+                    // pairs are masked)
+                    float2 rf[NC == 2 ? L : 1];
+                    if constexpr (NC == 2) {
+                        const int o = ((gi_own + dy) * n2 + gj_own + dx + kFacLead) * 8;  // >= 0
+#pragma unroll
+                        for (int k = 0; k < L; ++k)
+                            rf[k] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(frs, o + 8 * k, 0, 0));
+                    }
+                    // phase 1: vertical sliding box of (z(p) - z(p+d))^2
+                    if (has1) {
+                        float tq[NE];
+#pragma unroll
+                        for (int q = 0; q < NE; ++q) tq[q] = ref[q] - win[g + q];
+                        float v = tq[0] * tq[0];
+#pragma unroll
+                        for (int q = 1; q <= 2 * P; ++q) v = fmaf(tq[q], tq[q], v);
+                        float* vo = V + voff;
+                        vo[0] = v;
+#pragma unroll
+                        for (int q = 1; q < R; ++q) {
+                            v = fmaf(tq[q + 2 * P], tq[q + 2 * P], v);
+                            v = fmaf(-tq[q - 1], tq[q - 1], v);
+                            vo[q * VW] = v;
+                        }
+                    }
+                    __syncthreads();
+                    // phase 2: horizontal sliding box, weights, both-sided sums
+                    float vv[NV];
+                    {
+                        const float* vr = V + pi * VW + pj;
+#pragma unroll
+                        for (int q = 0; q < NV / 4; ++q) {
+                            const float4 t4 = reinterpret_cast<const float4*>(vr)[q];
+                            vv[4 * q + 0] = t4.x;
+                            vv[4 * q + 1] = t4.y;
+                            vv[4 * q + 2] = t4.z;
+                            vv[4 * q + 3] = t4.w;
+                        }
+                    }
+                    const float lg = hat.lg[dy + S] + hat.lg[dx + S];
+                    float hs = vv[0];
+#pragma unroll
+                    for (int q = 1; q <= 2 * P; ++q) hs += vv[q];
+                    float a[L];
+                    a[0] = __builtin_amdgcn_exp2f(lg - beta * hs);
+#pragma unroll
+                    for (int k = 1; k < L; ++k) {
+                        hs += vv[k + 2 * P] - vv[k - 1];
+                        a[k] = __builtin_amdgcn_exp2f(lg - beta * hs);
+                    }
+                    const bool inside = s_in && ti0 + TH - 1 + dy < n1 && tj0 + dx >= 0 &&
+                                        tj0 + TW - 1 + dx < n2;
+                    if (!inside) {
+                        const bool rowok = gi_own < n1 && gi_own + dy < n1;
+#pragma unroll
+                        for (int k = 0; k < L; ++k) {
+                            const int gj = gj_own + k;
+                            const bool ok = rowok && gj < n2 && (unsigned)(gj + dx) < (unsigned)n2;
+                            a[k] = ok ? a[k] : 0.f;
+                        }
+                    }
+                    const int pr = own + dy * AW + dx;  // partner entry of output 0
+                    if constexpr (NC == 1) {
+#pragma unroll
+                        for (int k = 0; k < L; ++k) {
+                            acc0[k] += a[k];
+                            Acc[pr + k] += a[k];
+                        }
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < L; ++k) {
+                            const float2 v = rf[k];
+                            acc0[k] = fmaf(a[k], v.x, acc0[k]);
+                            acc1[k] = fmaf(a[k], v.y, acc1[k]);
+                            float2* e = reinterpret_cast<float2*>(Acc) + pr + k;
+                            const float2 u = *e;
+                            *e = make_float2(fmaf(a[k], f0[k], u.x), fmaf(a[k], f1[k], u.y));
+                        }
+                    }
+                    ++t;
+                }
+            }
+        }
+    }
+    // the last shift's partner updates are complete after this barrier; then
+    // the own-pixel sums join the region (each thread owns its entries)
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        if constexpr (NC == 1) {
+            Acc[own + k] += acc0[k];
+        } else {
+            float2* e = reinterpret_cast<float2*>(Acc) + own + k;
+            const float2 v = *e;
+            *e = make_float2(v.x + acc0[k], v.y + acc1[k]);
+        }
+    }
+    __syncthreads();
+    const size_t reg = (size_t)AH * AWr;
+    const int lt = local_tile(ti0, tj0, n2, TH, TW);
+    float* part = d.part + (size_t)lt * reg * half_np(MODE);
+    for (int idx = tid; idx < AH * AWr; idx += NT) {
+        const int r = idx / AWr, q = idx - r * AWr;
+        if constexpr (NC == 1) {
+            part[idx] = Acc[r * AW + q];
+        } else {
+            reinterpret_cast<float2*>(part)[idx] = reinterpret_cast<const float2*>(Acc)[r * AW + q];
+        }
+    }
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64_h(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// One block per s-tile: every pixel of the tile sums the partial regions of
+// the tiles covering it (own, left, right, above, above-left, above-right),
+// adds the d = 0 term and finishes the pass.
+template <int MODE, bool BATCH>
+__global__ void __launch_bounds__(256)
+k_half_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__ tiles, int S) {
+    constexpr int TH = 32, TW = 64;
+    constexpr int NP = half_np(MODE);
+    ImgDesc d;
+    int ti0, tj0;
+    if constexpr (BATCH) {
+        const TileRef t = tiles[blockIdx.x];
+        d = batch[t.img];
+        ti0 = t.ti0;
+        tj0 = t.tj0;
+    } else {
+        d = one;
+        ti0 = blockIdx.y * TH;
+        tj0 = blockIdx.x * TW;
+    }
+    const int n1 = d.n1, n2 = d.n2;
+    const int AWr = TW + 2 * S;
+    const size_t reg = (size_t)(TH + S) * AWr;
+    const int ntx = (n2 + TW - 1) / TW;
+    const int lt = (ti0 / TH) * ntx + tj0 / TW;
+    const int tx = tj0 / TW;
+    unsigned long long best = 0ull;
+    for (int e = threadIdx.x; e < TH * TW; e += 256) {
+        const int li = e / TW, lj = e - li * TW;
+        const int gi = ti0 + li, gj = tj0 + lj;
+        if (gi >= n1 || gj >= n2) continue;
+        float s0 = 0.f, s1 = 0.f;
+        auto add = [&](int tile, int r, int q) {
+            const size_t o = (size_t)tile * reg + (size_t)r * AWr + q;
+            if constexpr (NP == 1) {
+                s0 += d.part[o];
+            } else {
+                const float2 v = reinterpret_cast<const float2*>(d.part)[o];
+                s0 += v.x;
+                s1 += v.y;
+            }
+        };
+        const bool left = tx > 0 && lj < S, right = tx + 1 < ntx && lj >= TW - S;
+        add(lt, li, lj + S);
+        if (left) add(lt - 1, li, lj + TW + S);
+        if (right) add(lt + 1, li, lj - TW + S);
+        if (ti0 > 0 && li < S) {
+            const int up = lt - ntx;
+            add(up, li + TH, lj + S);
+            if (left) add(up - 1, li + TH, lj + TW + S);
+            if (right) add(up + 1, li + TH, lj - TW + S);
+        }
+        const size_t p = (size_t)gi * n2 + gj;
+        if constexpr (MODE == kPassA) {
+            d.c[p] = 1.0f / sqrtf(s0 + 1.0f);  // omega includes a_{s,s} = 1
+        } else if constexpr (MODE == kPassC) {
+            const float2 tw = reinterpret_cast<const float2*>(d.aux_in)[p];
+            reinterpret_cast<float2*>(d.aux_out)[p] = make_float2(s0 + tw.x, s1 + tw.y);
+        } else {
+            const float cs = d.c[p];
+            s0 += cs;  // d = 0: a = 1, partner factor c_s
+            if constexpr (MODE == kPassBApply || MODE == kApply) {
+                const float xs = d.x[p];
+                s1 += cs * xs;
+                d.bp[p] = cs * (s1 - xs * s0);
+            }
+            if constexpr (MODE == kPassBApply || MODE == kPassBBuild) {
+                const float dl = cs * s0;
+                d.delta[p] = dl;
+                const unsigned long long kk =
+                    ((unsigned long long)__float_as_uint(dl) << 32) | (unsigned long long)(~(unsigned)p);
+                best = kk > best ? kk : best;
+            }
+        }
+    }
+    if constexpr (MODE == kPassBApply || MODE == kPassBBuild) {
+        best = wave_max_u64_h(best);
+        if ((threadIdx.x & 63) == 0 && best != 0ull) atomicMax(d.key, best);
+    }
+}
+
+// Partner factors (c, c x) of the pass-B family for the half-window sweep
+// (one block per s-tile, the sweep's own tiling).
+template <int MODE, bool BATCH>
+__global__ void __launch_bounds__(256)
+k_half_prep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__ tiles) {
+    constexpr int TH = 32, TW = 64;
+    ImgDesc d;
+    int ti0, tj0;
+    if constexpr (BATCH) {
+        const TileRef t = tiles[blockIdx.x];
+        d = batch[t.img];
+        ti0 = t.ti0;
+        tj0 = t.tj0;
+    } else {
+        d = one;
+        ti0 = blockIdx.y * TH;
+        tj0 = blockIdx.x * TW;
+    }
+    for (int e = threadIdx.x; e < TH * TW; e += 256) {
+        const int gi = ti0 + e / TW, gj = tj0 + e % TW;
+        if (gi >= d.n1 || gj >= d.n2) continue;
+        const size_t p = (size_t)gi * d.n2 + gj;
+        const float cc = d.c[p];
+        reinterpret_cast<float2*>(d.pf)[p] = make_float2(cc, MODE == kPassBBuild ? 0.f : cc * d.x[p]);
+    }
+}
+
+template <int P, int S_CLASS, int MODE, bool BATCH>
+hipError_t half_attr() {
+    static bool attr_set = false;  // per instance
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_half<P, S_CLASS, MODE, BATCH>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    return hipSuccess;
+}
+
+template <int P, int S_CLASS>
+hipError_t half_attr_all() {
+    hipError_t e = half_attr<P, S_CLASS, kPassA, false>();
+    if (e == hipSuccess) e = half_attr<P, S_CLASS, kPassBApply, false>();
+    if (e == hipSuccess) e = half_attr<P, S_CLASS, kPassBBuild, false>();
+    if (e == hipSuccess) e = half_attr<P, S_CLASS, kApply, false>();
+    if (e == hipSuccess) e = half_attr<P, S_CLASS, kPassC, false>();
+    return e;
+}
+
+template <int P>
+hipError_t half_prepare_p(int S) {
+    return S <= 12 ? half_attr_all<P, 12>() : half_attr_all<P, kMaxS>();
+}
+
+template <int P, int S_CLASS, int MODE, bool BATCH>
+hipError_t launch_half_one(int S, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles, int ntiles,
+                           hipStream_t st) {
+    using G = HGeo<P, S_CLASS>;
+    const size_t lds = half_lds_floats<P, S_CLASS>(S, MODE) * sizeof(float);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    hipError_t ea = half_attr<P, S_CLASS, MODE, BATCH>();
+    if (ea != hipSuccess) return ea;
+    const dim3 grid = BATCH ? dim3(ntiles) : dim3((one.n2 + G::TW - 1) / G::TW, (one.n1 + G::TH - 1) / G::TH);
+    const HatTable hat = make_hat(S);
+    if constexpr (MODE == kPassBApply || MODE == kPassBBuild || MODE == kApply) {
+        ProfScope prof(DSNLM_K_HALF_AUX, st);
+        hipLaunchKernelGGL((k_half_prep<MODE, BATCH>), grid, dim3(256), 0, st, one, batch, tiles);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    {
+        constexpr int kind = MODE == kPassA ? DSNLM_K_PASS_A
+                             : (MODE == kPassBApply || MODE == kPassBBuild) ? DSNLM_K_PASS_B
+                             : MODE == kApply ? DSNLM_K_APPLY
+                                              : DSNLM_K_PASS_C;
+        ProfScope prof(kind, st);
+        hipLaunchKernelGGL((k_half<P, S_CLASS, MODE, BATCH>), grid, dim3(G::NT), lds, st, one, batch, tiles, S,
+                           hat);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    ProfScope prof(DSNLM_K_HALF_AUX, st);
+    hipLaunchKernelGGL((k_half_gather<MODE, BATCH>), grid, dim3(256), 0, st, one, batch, tiles, S);
+    return hipGetLastError();
+}
+
+template <int P, int S_CLASS, bool BATCH>
+hipError_t half_mode(int mode, int S, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
+                     int ntiles, hipStream_t st) {
+    switch (mode) {
+        case kPassA: return launch_half_one<P, S_CLASS, kPassA, BATCH>(S, one, batch, tiles, ntiles, st);
+        case kPassBApply: return launch_half_one<P, S_CLASS, kPassBApply, BATCH>(S, one, batch, tiles, ntiles, st);
+        case kPassBBuild: return launch_half_one<P, S_CLASS, kPassBBuild, BATCH>(S, one, batch, tiles, ntiles, st);
+        case kApply: return launch_half_one<P, S_CLASS, kApply, BATCH>(S, one, batch, tiles, ntiles, st);
+        case kPassC: return launch_half_one<P, S_CLASS, kPassC, BATCH>(S, one, batch, tiles, ntiles, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int P, bool BATCH>
+hipError_t half_s(int mode, int S, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles, int ntiles,
+                  hipStream_t st) {
+    if (S <= 12) return half_mode<P, 12, BATCH>(mode, S, one, batch, tiles, ntiles, st);
+    return half_mode<P, kMaxS, BATCH>(mode, S, one, batch, tiles, ntiles, st);
+}
+
+template <bool BATCH>
+hipError_t half_p(int mode, int S, int P, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
+                  int ntiles, hipStream_t st) {
+    switch (P) {
+        case 0: return half_s<0, BATCH>(mode, S, one, batch, tiles, ntiles, st);
+        case 1: return half_s<1, BATCH>(mode, S, one, batch, tiles, ntiles, st);
+        case 2: return half_s<2, BATCH>(mode, S, one, batch, tiles, ntiles, st);
+        case 3: return half_s<3, BATCH>(mode, S, one, batch, tiles, ntiles, st);
+        case 4: return half_s<4, BATCH>(mode, S, one, batch, tiles, ntiles, st);
+        case 5: return half_s<5, BATCH>(mode, S, one, batch, tiles, ntiles, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+size_t half_part_floats(int n1, int n2, int S) {
+    const size_t tiles = (size_t)((n1 + 31) / 32) * ((n2 + 63) / 64);
+    const size_t regions = tiles * (size_t)(32 + S) * (64 + 2 * S) * 2;
+    return ((regions + 63) & ~(size_t)63) + 2 * ((size_t)n1 * n2 + kFacLead) + 64;
+}
+
+float* half_pf(float* part, int n1, int n2, int S) {
+    const size_t tiles = (size_t)((n1 + 31) / 32) * ((n2 + 63) / 64);
+    const size_t regions = tiles * (size_t)(32 + S) * (64 + 2 * S) * 2;
+    return part + ((regions + 63) & ~(size_t)63) + 2 * kFacLead;
+}
+
+bool half_lds_fits(int S, int P, int mode) {
+    size_t f = 0;
+    switch (P) {
+        case 0: f = S <= 12 ? half_lds_floats<0, 12>(S, mode) : half_lds_floats<0, kMaxS>(S, mode); break;
+        case 1: f = S <= 12 ? half_lds_floats<1, 12>(S, mode) : half_lds_floats<1, kMaxS>(S, mode); break;
+        case 2: f = S <= 12 ? half_lds_floats<2, 12>(S, mode) : half_lds_floats<2, kMaxS>(S, mode); break;
+        case 3: f = S <= 12 ? half_lds_floats<3, 12>(S, mode) : half_lds_floats<3, kMaxS>(S, mode); break;
+        case 4: f = S <= 12 ? half_lds_floats<4, 12>(S, mode) : half_lds_floats<4, kMaxS>(S, mode); break;
+        case 5: f = S <= 12 ? half_lds_floats<5, 12>(S, mode) : half_lds_floats<5, kMaxS>(S, mode); break;
+        default: return false;
+    }
+    return f * sizeof(float) <= 160 * 1024;
+}
+
+bool half_mode_ok(int mode) {
+    return mode == kPassA || mode == kPassBApply || mode == kPassBBuild || mode == kApply || mode == kPassC;
+}
+
+hipError_t prepare_half(int S, int P) {
+    switch (P) {
+        case 0: return half_prepare_p<0>(S);
+        case 1: return half_prepare_p<1>(S);
+        case 2: return half_prepare_p<2>(S);
+        case 3: return half_prepare_p<3>(S);
+        case 4: return half_prepare_p<4>(S);
+        case 5: return half_prepare_p<5>(S);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_half(int mode, int S, int P, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
+                       int ntiles, hipStream_t st) {
+    if (batch) return half_p<true>(mode, S, P, one, batch, tiles, ntiles, st);
+    return half_p<false>(mode, S, P, one, batch, tiles, ntiles, st);
+}
+
+}  // namespace dsnlm

@@ -228,9 +228,8 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
     constexpr int LD = (MODE == kPassD) ? L : 1;
     float ow[LD], oc[LD], ob[LD], ox[LD];
     float zown[LD];
-    bool sin_[LD], core_[LD];
-    float accz[LD];
-    float hacc = 0.f;
+    float accz[LD], hk[LD];
+    bool s_in = false;              // every s of the tile inside the image
     float nk = 0.f;                 // -kappa
     float mb = 0.f;                 // mbar, routed to the argmax pixel s*
     int si = -1, sj = -1;           // s*
@@ -256,15 +255,16 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
         for (int k = 0; k < L; ++k) {
             zown[k] = Zs[(pj + k + S + P) * ZC + pi + S + P];
             const int gj = gj_own + k;
-            sin_[k] = (unsigned)gi_own < (unsigned)n1 && (unsigned)gj < (unsigned)n2;
-            core_[k] = pi >= P && pi < TH - P && pj + k >= P && pj + k < TW - P;
-            const float4 o = sin_[k] ? img4[(size_t)gi_own * n2 + gj] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const bool in = (unsigned)gi_own < (unsigned)n1 && (unsigned)gj < (unsigned)n2;
+            const float4 o = in ? img4[(size_t)gi_own * n2 + gj] : make_float4(0.f, 0.f, 0.f, 0.f);
             ow[k] = nk * o.x;
             oc[k] = nk * o.y;
             ob[k] = o.z;
             ox[k] = o.w;
             accz[k] = 0.f;
+            hk[k] = 0.f;
         }
+        s_in = ti0 >= 0 && ti0 + TH <= n1 && tj0 >= 0 && tj0 + TW <= n2;
     }
 
     // phase 1: vertical sliding box sums of e_d = (z(p) - z(p+d))^2 down the
@@ -369,33 +369,32 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
             // -kappa (abar_{s,d} + abar_{s+d,-d}) with r = s + d:
             //   -kappa (omegabar_s + omegabar_r)
             //   - kappa c_s c_r ((B'bar_s - B'bar_r)(x_r - x_s) + f_s + f_r)
-            const bool rowok = (unsigned)(gi_own + dy) < (unsigned)n1;
-            auto pair = [&](int k, float as, float q) {
-                const float a = __builtin_amdgcn_exp2f(lg - beta * Dk[k]);
-                const bool ok = sin_[k] && rowok && (unsigned)(gj_own + k + dx) < (unsigned)n2;
-                const float db = ok ? a * as : 0.f;
-                hacc = core_[k] ? fmaf(db, Dk[k], hacc) : hacc;
-                Db[pi * G::BW + pj + k + P] = db;
-                (void)q;
+            auto abar = [&](int k) {
+                const float4 r = rv[k];
+                return fmaf(oc[k] * r.y, (ob[k] - r.z) * (r.w - ox[k]), fmaf(nk, r.x, ow[k]));
             };
-            if (!fnear) {
+            const bool inside = s_in && ti0 + dy >= 0 && ti0 + TH - 1 + dy < n1 && tj0 + dx >= 0 &&
+                                tj0 + TW - 1 + dx < n2;
+            if (inside && !fnear) {
+                // every s of the tile and every partner is in the image
 #pragma unroll
-                for (int k = 0; k < L; ++k) {
-                    const float4 r = rv[k];
-                    const float q = oc[k] * r.y;
-                    pair(k, fmaf(q, (ob[k] - r.z) * (r.w - ox[k]), fmaf(nk, r.x, ow[k])), q);
-                }
+                for (int k = 0; k < L; ++k)
+                    Db[pi * G::BW + pj + k + P] = __builtin_amdgcn_exp2f(lg - beta * Dk[k]) * abar(k);
             } else {
-                // the f terms live on s* alone
+                const bool rowok = (unsigned)(gi_own + dy) < (unsigned)n1 && (unsigned)gi_own < (unsigned)n1;
                 const bool rs = gi_own + dy == si, ss = gi_own == si;
 #pragma unroll
                 for (int k = 0; k < L; ++k) {
-                    const float4 r = rv[k];
-                    const float q = oc[k] * r.y;
-                    const float fr = (rs && gj_own + k + dx == sj) ? mb : 0.f;
-                    const float fs = (ss && gj_own + k == sj) ? mb : 0.f;
-                    const float e = fmaf(ob[k] - r.z, r.w - ox[k], fs + fr);
-                    pair(k, fmaf(q, e, fmaf(nk, r.x, ow[k])), q);
+                    float as = abar(k);
+                    if (fnear) {  // the f terms live on s* alone
+                        const float fr = (rs && gj_own + k + dx == sj) ? mb : 0.f;
+                        const float fs = (ss && gj_own + k == sj) ? mb : 0.f;
+                        as = fmaf(oc[k] * rv[k].y, fs + fr, as);
+                    }
+                    const float a = __builtin_amdgcn_exp2f(lg - beta * Dk[k]);
+                    const bool ok = rowok && (unsigned)(gj_own + k + dx) < (unsigned)n2 &&
+                                    (unsigned)(gj_own + k) < (unsigned)n2;
+                    Db[pi * G::BW + pj + k + P] = ok ? a * as : 0.f;
                 }
             }
         } else {
@@ -443,7 +442,12 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
 #pragma unroll
             for (int k = 0; k < L; ++k) {
                 if (k > 0) hs += vr[k + 2 * P] - vr[k - 1];
-                accz[k] = fmaf(2.f * (zown[k] - zq[k * ZC]), hs, accz[k]);
+                // zbar += 2 dz G (the 2 is applied at the end); the bandwidth
+                // sum needs sum_s Dbar D = sum_q e_d(q) G(q), e_d = dz^2
+                const float dz = zown[k] - zq[k * ZC];
+                const float t = dz * hs;
+                accz[k] += t;
+                hk[k] = fmaf(dz, t, hk[k]);
             }
         } else {
             (void)dy;
@@ -554,12 +558,17 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
 
     if constexpr (MODE == kPassD) {
         const int W2 = n2 + 2 * P;
+        // the core: the s-tile less P on each side (cores tile the padded grid)
+        auto core = [&](int k) { return pi >= P && pi < TH - P && pj + k >= P && pj + k < TW - P; };
 #pragma unroll
         for (int k = 0; k < L; ++k) {
             const int gj = gj_own + k;
-            if (core_[k] && gi_own >= -P && gi_own < n1 + P && gj >= -P && gj < n2 + P)
-                d.gz[(size_t)(gi_own + P) * W2 + gj + P] = accz[k];
+            if (core(k) && gi_own >= -P && gi_own < n1 + P && gj >= -P && gj < n2 + P)
+                d.gz[(size_t)(gi_own + P) * W2 + gj + P] = 2.f * accz[k];
         }
+        float hacc = 0.f;
+#pragma unroll
+        for (int k = 0; k < L; ++k) hacc += core(k) ? hk[k] : 0.f;
         // block partial of sum Dbar D: fixed-order LDS tree (V is free: its
         // last reads, in the last shift's phase 2, precede two barriers)
         float* red = Vb;
@@ -680,9 +689,9 @@ hipError_t launch_one(int S, const ImgDesc& one, const ImgDesc* batch, const Til
         return launch_var<P, S_CLASS, MODE, BATCH, 2>(S, one, batch, tiles, ntiles, st);
     } else {
         switch (sweep_variant(MODE, S, P)) {
+            case 0: return launch_var<P, S_CLASS, MODE, BATCH, 0>(S, one, batch, tiles, ntiles, st);
             case 1: return launch_var<P, S_CLASS, MODE, BATCH, 1>(S, one, batch, tiles, ntiles, st);
-            case 2: return launch_var<P, S_CLASS, MODE, BATCH, 2>(S, one, batch, tiles, ntiles, st);
-            default: return launch_var<P, S_CLASS, MODE, BATCH, 0>(S, one, batch, tiles, ntiles, st);
+            default: return launch_var<P, S_CLASS, MODE, BATCH, 2>(S, one, batch, tiles, ntiles, st);
         }
     }
 }
@@ -766,6 +775,8 @@ HatTable make_hat(int S) {
 }
 
 hipError_t prepare_sweeps(int S, int P) {
+    hipError_t e = prepare_half(S, P);
+    if (e != hipSuccess) return e;
     switch (P) {
         case 0: return prepare_p<0>(S);
         case 1: return prepare_p<1>(S);
@@ -799,6 +810,8 @@ hipError_t launch_sweep(int mode, int S, int P, const ImgDesc& one, const ImgDes
                      : mode == kApply ? DSNLM_K_APPLY
                      : mode == kPassD ? DSNLM_K_PASS_D
                                       : DSNLM_K_PASS_C;
+    if (one.part && half_mode_ok(mode) && sweep_variant(mode, S, P) == kHalfVariant && half_lds_fits(S, P, mode))
+        return launch_half(mode, S, P, one, batch, tiles, ntiles, st);  // times its kernels itself
     ProfScope prof(kind, st);
     if (batch) return dispatch_p<true>(mode, S, P, one, batch, tiles, ntiles, st);
     return dispatch_p<false>(mode, S, P, one, batch, tiles, ntiles, st);

@@ -36,6 +36,9 @@ struct ImgDesc {
     const float* mbar;     // device scalar mbar of the backward (sweep D)
     float* gz;             // sweep D output: gradient on the padded grid
     float* hpart;          // sweep D output: per-block partial sums for dh
+    float* part;           // half-window sweeps: per-tile partner-region partial sums
+    float* pf;             // half-window sweeps: per-pixel float2 partner factors
+                           // (kFacLead readable float2 entries precede index 0)
     int n1, n2;
     float beta;            // log2(e) / (2 (2P+1)^2 h^2)
     float kappa;           // 1 / (2 (2P+1)^2 h^2)
@@ -68,7 +71,10 @@ enum SweepMode : int {
 };
 
 // Variant table of the sweeps (tuning.hip).
-constexpr int kSweepVariants = 3;
+// 0 plain, 1 software-pipelined, 2 grouped register window (full window);
+// 3 half window (accumulating sweeps only; needs ImgDesc::part)
+constexpr int kSweepVariants = 4;
+constexpr int kHalfVariant = 3;
 int sweep_variant(int mode, int S, int P);
 void set_sweep_variant(int kind, int S, int P, int v);
 void save_tuning();
@@ -87,6 +93,24 @@ hipError_t launch_sweep(int mode, int S, int P, const ImgDesc& one, const ImgDes
                         const TileRef* tiles, int ntiles, hipStream_t st);
 hipError_t launch_epilogue(const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
                            int ntiles, int S, int P, hipStream_t st);
+
+// Half-window sweeps (dsnlm_half.hip).  Floats of the partial buffer of an
+// n1 x n2 image; whether the LDS of a mode fits; the launcher (sweep +
+// gather).  launch_sweep routes a mode here when variant 3 is selected and a
+// partial buffer is given (for a batch launch: one.part non-null means every
+// descriptor carries one).
+// Float2 arrays read by the half-window sweeps as partner factors (the
+// backward's (t, w) pairs and the forward's (c, c x)) are allocated with this
+// many entries before index 0, so a run of partners never starts before the
+// allocation.
+constexpr int kFacLead = 32;
+size_t half_part_floats(int n1, int n2, int S);  // partial buffer + (c, c x) array
+float* half_pf(float* part, int n1, int n2, int S);  // the (c, c x) array inside it
+bool half_lds_fits(int S, int P, int mode);
+bool half_mode_ok(int mode);
+hipError_t launch_half(int mode, int S, int P, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
+                       int ntiles, hipStream_t st);
+hipError_t prepare_half(int S, int P);
 
 // Backward launchers (dsnlm_backward.hip).
 // Backward (dsnlm_backward.hip): LDS bytes of sweep D and the largest S it
@@ -142,5 +166,7 @@ struct dsnlm_weights {
     float* zbuf;       // denoiser input x + u inside the solver (in scratch)
     float* bscratch;   // backward scratch (grow-only), freed with the handle
     size_t bscratch_cap;
+    float* part;       // partial buffer of the half-window sweeps (grow-only)
+    size_t part_cap;
     bool applied;      // bp holds B' of the last apply
 };

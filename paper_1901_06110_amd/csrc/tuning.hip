@@ -37,11 +37,12 @@ int kind_of(int mode) {
 void load_cache_locked() {
     if (g_loaded) return;
     g_loaded = true;
-    // default: the grouped register-window schedule (variant 2), the fastest
-    // on gfx950 for every kind measured
+    // default: the half-window sweeps (variant 3), the fastest on gfx950
+    // for every kind measured (the full-window grouped schedule, variant 2,
+    // serves callers without a partial buffer)
     for (auto& a : g_table)
         for (auto& b : a)
-            for (int& c : b) c = 2;
+            for (int& c : b) c = kHalfVariant;
     const char* path = std::getenv("DSNLM_TUNE_CACHE");
     if (!path) return;
     FILE* f = std::fopen(path, "r");
@@ -123,7 +124,7 @@ extern "C" int dsnlm_tune(const float* guide, int n1, int n2, int S, int P, floa
     if (rc) return rc;
     const size_t n = (size_t)n1 * n2;
     float* scratch = nullptr;  // y and the backward per-pixel pair array
-    rc = check_hip(hipMalloc(&scratch, 5 * n * sizeof(float)), "dsnlm_tune scratch");
+    rc = check_hip(hipMalloc(&scratch, (5 * n + 2 * kFacLead) * sizeof(float)), "dsnlm_tune scratch");
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (!rc) rc = check_hip(hipEventCreate(&e0), "event");
     if (!rc) rc = check_hip(hipEventCreate(&e1), "event");
@@ -131,13 +132,13 @@ extern "C" int dsnlm_tune(const float* guide, int n1, int n2, int S, int P, floa
     ImgDesc d = base_desc(w);
     d.x = w->guide;
     d.y = scratch;
-    d.aux_in = scratch + n;       // timing only: the values are irrelevant
-    d.aux_out = scratch + 3 * n;
+    d.aux_in = scratch + n + 2 * kFacLead;  // timing only: the values are irrelevant
+    d.aux_out = scratch + 3 * n + 2 * kFacLead;
     // build once so c, delta and m hold meaningful values
     if (!rc) rc = check_hip(launch_sweep(kPassA, S, P, d, nullptr, nullptr, 0, st), "tune build");
     if (!rc) rc = check_hip(launch_sweep(kPassBApply, S, P, d, nullptr, nullptr, 0, st), "tune build");
-    if (!rc) rc = check_hip(hipMemcpyAsync(scratch + n, w->c, n * sizeof(float), hipMemcpyDeviceToDevice, st), "copy");
-    if (!rc) rc = check_hip(hipMemcpyAsync(scratch + 2 * n, w->c, n * sizeof(float), hipMemcpyDeviceToDevice, st), "copy");
+    if (!rc) rc = check_hip(hipMemcpyAsync(scratch + n + 2 * kFacLead, w->c, n * sizeof(float), hipMemcpyDeviceToDevice, st), "copy");
+    if (!rc) rc = check_hip(hipMemcpyAsync(scratch + 2 * n + 2 * kFacLead, w->c, n * sizeof(float), hipMemcpyDeviceToDevice, st), "copy");
     const int modes[4] = {kPassA, kPassBApply, kApply, kPassC};
     for (int k = 0; k < 4 && !rc; ++k) {
         float best = 1e30f;
