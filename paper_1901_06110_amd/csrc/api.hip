@@ -55,7 +55,7 @@ ImgDesc base_desc(const dsnlm_weights* w) {
     d.bp = w->bp;
     d.key = w->key;
     d.part = w->part;
-    d.pf = w->part ? half_pf(w->part, w->n1, w->n2, w->S) : nullptr;
+    d.zpad = w->part ? half_zpad(w->part, w->n1, w->n2, w->S) : nullptr;
     d.n1 = w->n1;
     d.n2 = w->n2;
     const double np = 2.0 * w->P + 1.0;
@@ -89,7 +89,7 @@ int prepare_handle(int n1, int n2, int S, int P, float h, dsnlm_weights** out) {
         }
         *out = w;
     }
-    const size_t need = half_part_floats(n1, n2, S);
+    const size_t need = half_part_floats(n1, n2, S, P);
     if (w->part_cap < need) {
         (void)hipFree(w->part);
         w->part = nullptr;

@@ -97,7 +97,7 @@ extern "C" int dsnlm_forward_batched(const dsnlm_image* imgs, int count, int S, 
     std::vector<ImgDesc> descs(count);
     std::vector<TileRef> tiles;
     size_t part_total = 0;
-    for (int k = 0; k < count; ++k) part_total += half_part_floats(imgs[k].n1, imgs[k].n2, S);
+    for (int k = 0; k < count; ++k) part_total += half_part_floats(imgs[k].n1, imgs[k].n2, S, P);
     rc = check_hip(grow(&g_ws.part, &g_ws.part_cap, part_total), "batch partial buffers");
     if (rc) return rc;
     size_t off = 0, part_off = 0;
@@ -114,8 +114,8 @@ extern "C" int dsnlm_forward_batched(const dsnlm_image* imgs, int count, int S, 
         d.bp = g_ws.arrays + 2 * total + off;
         d.key = g_ws.keys + k;
         d.part = g_ws.part + part_off;
-        d.pf = half_pf(d.part, im.n1, im.n2, S);
-        part_off += half_part_floats(im.n1, im.n2, S);
+        d.zpad = half_zpad(d.part, im.n1, im.n2, S);
+        part_off += half_part_floats(im.n1, im.n2, S, P);
         d.n1 = im.n1;
         d.n2 = im.n2;
         const double np = 2.0 * P + 1.0;

@@ -14,9 +14,9 @@
 //
 // A tile adds a * factor(r) to its own pixel s in registers and a * factor(s)
 // to the partner r in an LDS accumulator that spans the tile's partner region
-// (S rows below, S columns either side).  Partner factors are read per shift
-// from a per-pixel float2 array in memory (range-checked buffer loads), which
-// keeps the LDS at two tiles per CU.  The region is written to a
+// (S rows below, S columns either side), next to the partner factors.  The
+// guide is read from a mirrored copy in memory (made before pass A) rather
+// than staged in LDS, which keeps the LDS at two tiles per CU.  The region is written to a
 // per-tile partial buffer, and a gather kernel adds for every pixel the
 // regions of the (at most six) tiles covering it, in a fixed order, then the
 // d = 0 term, and finishes the pass exactly as the full-window sweep does.
@@ -39,30 +39,23 @@ struct HGeo {
     static constexpr int TWE = TW + 2 * P;
     static constexpr int NITEM1 = TWE * (TH / R);
     static constexpr int GWIN = 7;
-    // guide tile, column-major: rows ti0-P .. ti0+TH+S+P (+ window slack)
-    static constexpr int ZC0 = TH + S_CLASS + 2 * P + GWIN - 1;
-    static constexpr int ZC = ZC0 | 1;
-    // partner region: rows ti0 .. ti0+TH+S, columns tj0-S .. tj0+TW+S
+    // partner region: rows ti0 .. ti0+TH+S, columns tj0-S .. tj0+TW+S (odd stride)
     static constexpr int AW = (TW + 2 * S_CLASS) | 1;
     static constexpr int VW0 = ((TWE + 3) / 4) * 4;
     static constexpr int VW = ((VW0 / 4) % 2) ? VW0 : VW0 + 4;
     static_assert(NITEM1 <= NT, "one phase-1 item per thread");
 };
 
-// floats per partner-region entry in LDS: the sum of a (pass A) or the two
-// factor-weighted sums (the others)
-constexpr int half_nc(int mode) { return mode == kPassA ? 1 : 2; }
+// floats per partner-region entry in LDS: the sum of a (pass A), or the
+// partner factors and the two factor-weighted sums (the others)
+constexpr int half_nc(int mode) { return mode == kPassA ? 1 : 4; }
 // channels of the partial buffer
 constexpr int half_np(int mode) { return mode == kPassA ? 1 : 2; }
 
 template <int P, int S_CLASS>
 size_t half_lds_floats(int S, int mode) {
     using G = HGeo<P, S_CLASS>;
-    const size_t ZWr = G::TW + 2 * (S + P);
-    size_t n = (ZWr * G::ZC + 3) & ~(size_t)3;
-    n += (size_t)2 * G::TH * G::VW;
-    n += (size_t)(G::TH + S) * G::AW * half_nc(mode);
-    return n;
+    return (size_t)2 * G::TH * G::VW + (size_t)(G::TH + S) * G::AW * half_nc(mode);
 }
 
 __device__ __forceinline__ int reflect_h(int k, int n) {
@@ -73,10 +66,42 @@ __device__ __forceinline__ int reflect_h(int k, int n) {
     return k;
 }
 
-// the tile's index within its image and the image's tile columns
+// the tile's index within its image
 __device__ __forceinline__ int local_tile(int ti0, int tj0, int n2, int TH, int TW) {
     const int ntx = (n2 + TW - 1) / TW;
     return (ti0 / TH) * ntx + tj0 / TW;
+}
+
+// The guide mirrored into a margin of m = S + P on every side, so that the
+// sweeps read any patch pixel without index reflection.  One block per
+// s-tile writes the tile's rows and columns, plus the margins beside it when
+// the tile is on the image border.
+template <bool BATCH>
+__global__ void __launch_bounds__(256)
+k_half_pad(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__ tiles, int m) {
+    constexpr int TH = 32, TW = 64;
+    ImgDesc d;
+    int ti0, tj0;
+    if constexpr (BATCH) {
+        const TileRef t = tiles[blockIdx.x];
+        d = batch[t.img];
+        ti0 = t.ti0;
+        tj0 = t.tj0;
+    } else {
+        d = one;
+        ti0 = blockIdx.y * TH;
+        tj0 = blockIdx.x * TW;
+    }
+    const int n1 = d.n1, n2 = d.n2, W2 = n2 + 2 * m;
+    const int i0 = ti0 == 0 ? -m : ti0;
+    const int i1 = ti0 + TH >= n1 ? n1 + m : ti0 + TH;
+    const int j0 = tj0 == 0 ? -m : tj0;
+    const int j1 = tj0 + TW >= n2 ? n2 + m : tj0 + TW;
+    const int w = j1 - j0;
+    for (int e = threadIdx.x; e < (i1 - i0) * w; e += 256) {
+        const int i = i0 + e / w, j = j0 + e % w;
+        d.zpad[(size_t)(i + m) * W2 + j + m] = d.z[(size_t)reflect_h(i, n1) * n2 + reflect_h(j, n2)];
+    }
 }
 
 template <int P, int S_CLASS, int MODE, bool BATCH>
@@ -85,7 +110,7 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
        HatTable hat) {
     using G = HGeo<P, S_CLASS>;
     constexpr int NT = G::NT, TH = G::TH, TW = G::TW, R = G::R, L = G::L;
-    constexpr int ZC = G::ZC, AW = G::AW, VW = G::VW;
+    constexpr int AW = G::AW, VW = G::VW;
     constexpr int NC = half_nc(MODE);
     constexpr int NE = R + 2 * P;
     extern __shared__ __align__(16) float lds[];
@@ -107,65 +132,75 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
         first = blockIdx.x == 0 && blockIdx.y == 0;
     }
     const int n1 = d.n1, n2 = d.n2;
-    const int ZH = TH + S + 2 * P, ZWr = TW + 2 * (S + P);
     const int AH = TH + S, AWr = TW + 2 * S;
-    float* Zs = lds;
-    int off = (ZWr * ZC + 3) & ~3;
-    float* Vb = lds + off;
-    off += 2 * TH * VW;
-    float* Acc = lds + off;  // partner region, NC floats per entry
+    float* Vb = lds;
+    float* Acc = lds + 2 * TH * VW;  // partner region, NC floats per entry
 
-    // ---- staging: guide rows ti0-P .. ti0+TH+S+P (mirrored), partner region
-    for (int idx = tid; idx < ZH * ZWr; idx += NT) {
-        const int r = idx / ZWr, q = idx - r * ZWr;
-        const int gi = reflect_h(ti0 - P + r, n1);
-        const int gj = reflect_h(tj0 - S - P + q, n2);
-        Zs[q * ZC + r] = d.z[(size_t)gi * n2 + gj];
-    }
-    for (int idx = tid; idx < AH * AWr * NC; idx += NT) {
-        const int r = idx / (AWr * NC), q = idx - r * (AWr * NC);
-        Acc[r * AW * NC + q] = 0.f;
+    // ---- the partner region: factors (c, c x) or (t, w) and zeroed sums
+    for (int idx = tid; idx < AH * AWr; idx += NT) {
+        const int r = idx / AWr, q = idx - r * AWr;
+        if constexpr (NC == 1) {
+            Acc[r * AW + q] = 0.f;
+        } else {
+            const int gi = ti0 + r, gj = tj0 - S + q;
+            const bool in = (unsigned)gi < (unsigned)n1 && (unsigned)gj < (unsigned)n2;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (in) {
+                const size_t p = (size_t)gi * n2 + gj;
+                if constexpr (MODE == kPassC) {
+                    const float2 tw = reinterpret_cast<const float2*>(d.aux_in)[p];
+                    v.x = tw.x;
+                    v.y = tw.y;
+                } else {
+                    const float cc = d.c[p];
+                    v.x = cc;
+                    v.y = (MODE == kPassBBuild) ? 0.f : cc * d.x[p];
+                }
+            }
+            reinterpret_cast<float4*>(Acc)[r * AW + q] = v;
+        }
     }
     if constexpr (MODE == kPassA) {
         if (first && tid == 0) *d.key = 0ull;  // the pass-B gather takes the max after this
     }
-    __syncthreads();
 
-    // ---- phase-1 item: one column strip of R rows (threads past NITEM1 idle)
+    // ---- phase-1 item: one column strip of R rows (threads past NITEM1 idle).
+    // The guide comes from its mirrored copy in memory; lanes walk along
+    // columns, so each load of a wave reads one contiguous row segment.  The
+    // range check returns zeros past the copy (only masked outputs see them).
+    const int m = S + P, W2 = n2 + 2 * m;
     const bool has1 = tid < G::NITEM1;
     const int it = has1 ? tid : 0;
     const int strip = it / G::TWE;
     const int c1 = it - strip * G::TWE;
-    const int zoff = (c1 + S) * ZC + strip * R;
+    // mirrored copy: pixel (i, j) at (i + m) * W2 + j + m; the strip's first
+    // reference pixel is (ti0 - P + strip R, tj0 - P + c1)
+    const int zbase = (ti0 + S + strip * R) * W2 + tj0 + S + c1;
+    const size_t zbytes = (size_t)(n1 + 2 * m) * W2 * 4;
+    const __amdgpu_buffer_rsrc_t zrs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(d.zpad), (short)0, (int)(zbytes < 0x7ffffff0u ? zbytes : 0x7ffffff0u), 0x00020000);
+    auto zload = [&](int off) { return __builtin_amdgcn_raw_buffer_load_b32(zrs, off * 4, 0, 0); };
     const int voff = strip * R * VW + c1;
     float ref[NE];
 #pragma unroll
-    for (int q = 0; q < NE; ++q) ref[q] = Zs[zoff + q];
+    for (int q = 0; q < NE; ++q) ref[q] = __builtin_bit_cast(float, zload(zbase + q * W2));
 
     const int pi = tid % TH;
     const int pj = (tid / TH) * L;
     const int own = pi * AW + pj + S;  // own pixel in the partner region
+    __syncthreads();
     float acc0[L], acc1[L], f0[L], f1[L];
-    // per-pixel partner factors: (t, w) of the backward, else (c, c x) made
-    // by the preparation kernel
-    const float2* fac = reinterpret_cast<const float2*>(MODE == kPassC ? d.aux_in : d.pf);
-    const size_t fbytes = ((size_t)n1 * n2 + kFacLead) * 8;
-    const __amdgpu_buffer_rsrc_t frs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<float2*>(NC == 2 ? fac - kFacLead : nullptr), (short)0,
-        NC == 2 ? (int)(fbytes < 0x7ffffff0u ? fbytes : 0x7ffffff0u) : 0, 0x00020000);
 #pragma unroll
     for (int k = 0; k < L; ++k) {
         acc0[k] = 0.f;
         acc1[k] = 0.f;
-        f0[k] = 0.f;
-        f1[k] = 0.f;
-        if constexpr (NC == 2) {
-            const int gi = ti0 + pi, gj = tj0 + pj + k;
-            if (gi < n1 && gj < n2) {
-                const float2 v = fac[(size_t)gi * n2 + gj];
-                f0[k] = v.x;
-                f1[k] = v.y;
-            }
+        if constexpr (NC == 4) {
+            const float4 v = reinterpret_cast<const float4*>(Acc)[own + k];
+            f0[k] = v.x;
+            f1[k] = v.y;
+        } else {
+            f0[k] = 0.f;
+            f1[k] = 0.f;
         }
     }
     const float beta = d.beta;
@@ -181,25 +216,15 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
         for (int dy0 = dylo; dy0 <= S; dy0 += GW) {
             float win[NW];
             {
-                const float* zq = Zs + zoff + dx * ZC + dy0;
+                const int zw = zbase + dy0 * W2 + dx;
 #pragma unroll
-                for (int q = 0; q < NW; ++q) win[q] = zq[q];
+                for (int q = 0; q < NW; ++q) win[q] = __builtin_bit_cast(float, zload(zw + q * W2));
             }
 #pragma unroll
             for (int g = 0; g < GW; ++g) {
                 const int dy = dy0 + g;
                 if (dy <= S) {
                     float* V = Vb + (t & 1) * (TH * VW);
-                    // partner factors of this shift, in flight over phase 1;
-                    // outside the array the range check returns zeros (those
-                    // pairs are masked)
-                    float2 rf[NC == 2 ? L : 1];
-                    if constexpr (NC == 2) {
-                        const int o = ((gi_own + dy) * n2 + gj_own + dx + kFacLead) * 8;  // >= 0
-#pragma unroll
-                        for (int k = 0; k < L; ++k)
-                            rf[k] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(frs, o + 8 * k, 0, 0));
-                    }
                     // phase 1: vertical sliding box of (z(p) - z(p+d))^2
                     if (has1) {
                         float tq[NE];
@@ -263,12 +288,12 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
                     } else {
 #pragma unroll
                         for (int k = 0; k < L; ++k) {
-                            const float2 v = rf[k];
+                            float4* e = reinterpret_cast<float4*>(Acc) + pr + k;
+                            const float4 v = *e;
                             acc0[k] = fmaf(a[k], v.x, acc0[k]);
                             acc1[k] = fmaf(a[k], v.y, acc1[k]);
-                            float2* e = reinterpret_cast<float2*>(Acc) + pr + k;
-                            const float2 u = *e;
-                            *e = make_float2(fmaf(a[k], f0[k], u.x), fmaf(a[k], f1[k], u.y));
+                            reinterpret_cast<float2*>(e)[1] =
+                                make_float2(fmaf(a[k], f0[k], v.z), fmaf(a[k], f1[k], v.w));
                         }
                     }
                     ++t;
@@ -284,7 +309,7 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
         if constexpr (NC == 1) {
             Acc[own + k] += acc0[k];
         } else {
-            float2* e = reinterpret_cast<float2*>(Acc) + own + k;
+            float2* e = reinterpret_cast<float2*>(reinterpret_cast<float4*>(Acc) + own + k) + 1;
             const float2 v = *e;
             *e = make_float2(v.x + acc0[k], v.y + acc1[k]);
         }
@@ -298,7 +323,8 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
         if constexpr (NC == 1) {
             part[idx] = Acc[r * AW + q];
         } else {
-            reinterpret_cast<float2*>(part)[idx] = reinterpret_cast<const float2*>(Acc)[r * AW + q];
+            const float4 v = reinterpret_cast<const float4*>(Acc)[r * AW + q];
+            reinterpret_cast<float2*>(part)[idx] = make_float2(v.z, v.w);
         }
     }
 }
@@ -393,33 +419,6 @@ k_half_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __r
     }
 }
 
-// Partner factors (c, c x) of the pass-B family for the half-window sweep
-// (one block per s-tile, the sweep's own tiling).
-template <int MODE, bool BATCH>
-__global__ void __launch_bounds__(256)
-k_half_prep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__ tiles) {
-    constexpr int TH = 32, TW = 64;
-    ImgDesc d;
-    int ti0, tj0;
-    if constexpr (BATCH) {
-        const TileRef t = tiles[blockIdx.x];
-        d = batch[t.img];
-        ti0 = t.ti0;
-        tj0 = t.tj0;
-    } else {
-        d = one;
-        ti0 = blockIdx.y * TH;
-        tj0 = blockIdx.x * TW;
-    }
-    for (int e = threadIdx.x; e < TH * TW; e += 256) {
-        const int gi = ti0 + e / TW, gj = tj0 + e % TW;
-        if (gi >= d.n1 || gj >= d.n2) continue;
-        const size_t p = (size_t)gi * d.n2 + gj;
-        const float cc = d.c[p];
-        reinterpret_cast<float2*>(d.pf)[p] = make_float2(cc, MODE == kPassBBuild ? 0.f : cc * d.x[p]);
-    }
-}
-
 template <int P, int S_CLASS, int MODE, bool BATCH>
 hipError_t half_attr() {
     static bool attr_set = false;  // per instance
@@ -457,9 +456,9 @@ hipError_t launch_half_one(int S, const ImgDesc& one, const ImgDesc* batch, cons
     if (ea != hipSuccess) return ea;
     const dim3 grid = BATCH ? dim3(ntiles) : dim3((one.n2 + G::TW - 1) / G::TW, (one.n1 + G::TH - 1) / G::TH);
     const HatTable hat = make_hat(S);
-    if constexpr (MODE == kPassBApply || MODE == kPassBBuild || MODE == kApply) {
+    if constexpr (MODE == kPassA) {  // the mirrored guide copy read by every half sweep
         ProfScope prof(DSNLM_K_HALF_AUX, st);
-        hipLaunchKernelGGL((k_half_prep<MODE, BATCH>), grid, dim3(256), 0, st, one, batch, tiles);
+        hipLaunchKernelGGL((k_half_pad<BATCH>), grid, dim3(256), 0, st, one, batch, tiles, S + P);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -515,16 +514,17 @@ hipError_t half_p(int mode, int S, int P, const ImgDesc& one, const ImgDesc* bat
 
 }  // namespace
 
-size_t half_part_floats(int n1, int n2, int S) {
+size_t half_part_floats(int n1, int n2, int S, int P) {
     const size_t tiles = (size_t)((n1 + 31) / 32) * ((n2 + 63) / 64);
     const size_t regions = tiles * (size_t)(32 + S) * (64 + 2 * S) * 2;
-    return ((regions + 63) & ~(size_t)63) + 2 * ((size_t)n1 * n2 + kFacLead) + 64;
+    const size_t m = (size_t)S + P;
+    return ((regions + 63) & ~(size_t)63) + (n1 + 2 * m) * (n2 + 2 * m) + 64;
 }
 
-float* half_pf(float* part, int n1, int n2, int S) {
+float* half_zpad(float* part, int n1, int n2, int S) {
     const size_t tiles = (size_t)((n1 + 31) / 32) * ((n2 + 63) / 64);
     const size_t regions = tiles * (size_t)(32 + S) * (64 + 2 * S) * 2;
-    return part + ((regions + 63) & ~(size_t)63) + 2 * kFacLead;
+    return part + ((regions + 63) & ~(size_t)63);
 }
 
 bool half_lds_fits(int S, int P, int mode) {

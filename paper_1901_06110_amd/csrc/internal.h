@@ -37,8 +37,7 @@ struct ImgDesc {
     float* gz;             // sweep D output: gradient on the padded grid
     float* hpart;          // sweep D output: per-block partial sums for dh
     float* part;           // half-window sweeps: per-tile partner-region partial sums
-    float* pf;             // half-window sweeps: per-pixel float2 partner factors
-                           // (kFacLead readable float2 entries precede index 0)
+    float* zpad;           // half-window sweeps: the guide mirrored into a margin of S + P
     int n1, n2;
     float beta;            // log2(e) / (2 (2P+1)^2 h^2)
     float kappa;           // 1 / (2 (2P+1)^2 h^2)
@@ -99,13 +98,10 @@ hipError_t launch_epilogue(const ImgDesc& one, const ImgDesc* batch, const TileR
 // gather).  launch_sweep routes a mode here when variant 3 is selected and a
 // partial buffer is given (for a batch launch: one.part non-null means every
 // descriptor carries one).
-// Float2 arrays read by the half-window sweeps as partner factors (the
-// backward's (t, w) pairs and the forward's (c, c x)) are allocated with this
-// many entries before index 0, so a run of partners never starts before the
-// allocation.
+// Lead pad (float2 entries) before the backward's (t, w) pair array.
 constexpr int kFacLead = 32;
-size_t half_part_floats(int n1, int n2, int S);  // partial buffer + (c, c x) array
-float* half_pf(float* part, int n1, int n2, int S);  // the (c, c x) array inside it
+size_t half_part_floats(int n1, int n2, int S, int P);  // partial regions + mirrored guide
+float* half_zpad(float* part, int n1, int n2, int S);   // the mirrored guide inside it
 bool half_lds_fits(int S, int P, int mode);
 bool half_mode_ok(int mode);
 hipError_t launch_half(int mode, int S, int P, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
