@@ -30,7 +30,7 @@ namespace dsnlm {
 
 namespace {
 
-template <int P, int S_CLASS>
+template <int P, int S_CLASS, int GW_ = 11>
 struct HGeo {
     static constexpr int TH = 32, TW = 64;   // s-tile (the forward tiling)
     static constexpr int R = 8;              // phase-1 strip height
@@ -38,7 +38,7 @@ struct HGeo {
     static constexpr int NT = TH * (TW / L);  // 512 threads
     static constexpr int TWE = TW + 2 * P;
     static constexpr int NITEM1 = TWE * (TH / R);
-    static constexpr int GWIN = 7;
+    static constexpr int GWIN = GW_;   // shifts per register window (one dx, consecutive dy)
     // partner region: rows ti0 .. ti0+TH+S, columns tj0-S .. tj0+TW+S (odd stride)
     static constexpr int AW = (TW + 2 * S_CLASS) | 1;
     static constexpr int VW0 = ((TWE + 3) / 4) * 4;
@@ -104,11 +104,15 @@ k_half_pad(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __rest
     }
 }
 
+// Pass A carries fewer live values: its registers are capped so that three
+// tiles share a CU (its LDS allows it).
 template <int P, int S_CLASS, int MODE, bool BATCH>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MODE == kPassA && P < 5 ? 6 : 1)))
 k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__ tiles, int S,
        HatTable hat) {
-    using G = HGeo<P, S_CLASS>;
+    // window length by measurement on gfx950 (pass A: 15, the others: 11; at
+    // S = 10 either covers every dy of a dx in one group)
+    using G = HGeo<P, S_CLASS, MODE == kPassA ? 15 : 11>;
     constexpr int NT = G::NT, TH = G::TH, TW = G::TW, R = G::R, L = G::L;
     constexpr int AW = G::AW, VW = G::VW;
     constexpr int NC = half_nc(MODE);
