@@ -580,12 +580,11 @@ bool overlaps(const void* a, const void* b, size_t bytes);
 
 // Scratch (floats) needed by dsnlm_apply_backward for an n1 x n2 image.
 size_t backward_scratch_floats(int n1, int n2, int S, int P) {
-    (void)S;
     const size_t n = (size_t)n1 * n2;
     const int CH = 32 - 2 * P, CW = 32 - 2 * P;
     const size_t tiles = (size_t)((n1 + 2 * P + CH - 1) / CH) * ((n2 + 2 * P + CW - 1) / CW);
     return 2 * (size_t)kFacLead + 2 * n + 2 * n + std::max(5 * n, aux4_floats(n)) +
-           (size_t)(n1 + 2 * P) * (n2 + 2 * P) + blocks256(n) + tiles + 8;
+           (size_t)(n1 + 2 * P) * (n2 + 2 * P) + blocks256(n) + tiles + 8 + sweep_d_part_floats(n1, n2, S, P);
 }
 
 int enqueue_backward(dsnlm_weights* w, const float* x, const float* dy, float* dx, float* dguide, float* dh,
@@ -602,6 +601,7 @@ int enqueue_backward(dsnlm_weights* w, const float* x, const float* dy, float* d
     const int tiles_y = (n1 + 2 * P + CH - 1) / CH, tiles_x = (n2 + 2 * P + CW - 1) / CW;
     float* hpart = partials + nb;
     float* mbar = hpart + (size_t)tiles_y * tiles_x;
+    float* dpart = mbar + 8;  // sweep-D partial regions
 
     BwdArgs a{};
     a.x = x;
@@ -645,9 +645,11 @@ int enqueue_backward(dsnlm_weights* w, const float* x, const float* dy, float* d
         d.mbar = mbar;
         d.gz = gz;
         d.hpart = hpart;
+        d.dpart = dpart;
         const int CHn = 32 - 2 * P, CWn = 64 - 2 * P;
         nd = ((n1 + 2 * P + CHn - 1) / CHn) * ((n2 + 2 * P + CWn - 1) / CWn);
         rc = check_hip(launch_sweep(kPassD, S, P, d, nullptr, nullptr, 0, st), "backward sweep D");
+        if (!rc) rc = check_hip(launch_d_gather(S, P, d, nullptr, nullptr, 0, st), "backward sweep D gather");
         if (rc) return rc;
     } else {
         DArgs da{};
@@ -735,7 +737,7 @@ int enqueue_backward_batch(const BwdImage* ims, int count, int S, int P, const T
         nd[k] = ((f.n1 + 2 * P + CHn - 1) / CHn) * ((f.n2 + 2 * P + CWn - 1) / CWn);
         base[k] = total;  // 256-byte aligned: the factors are read as float4
         total += 2 * (size_t)kFacLead + 4 * n + aux4_floats(n) + (size_t)(f.n1 + 2 * P) * (f.n2 + 2 * P) +
-                 nb[k] + nd[k] + 4;
+                 nb[k] + nd[k] + 4 + sweep_d_part_floats(f.n1, f.n2, S, P);
         total = (total + 63) & ~(size_t)63;
     }
     int rc = check_hip(grow_b(&g_bws.arrays, &g_bws.arrays_cap, total), "batched backward workspace");
@@ -765,6 +767,7 @@ int enqueue_backward_batch(const BwdImage* ims, int count, int S, int P, const T
         a.partials = a.gz + (size_t)(f.n1 + 2 * P) * (f.n2 + 2 * P);
         a.hpart = a.partials + nb[k];
         a.mbar = a.hpart + nd[k];
+        float* dpart = a.mbar + 4;
         a.n = (int)n;
         a.dx = ims[k].dx;
         a.dguide = ims[k].dguide;
@@ -782,6 +785,7 @@ int enqueue_backward_batch(const BwdImage* ims, int count, int S, int P, const T
         d.mbar = a.mbar;
         d.gz = a.gz;
         d.hpart = a.hpart;
+        d.dpart = dpart;
         d.tile_base = (int)dtiles.size();
         descs[k] = d;
         for (int b2 = 0; b2 < nb[k]; ++b2) map.push_back(make_int2(k, b2));
@@ -819,6 +823,9 @@ int enqueue_backward_batch(const BwdImage* ims, int count, int S, int P, const T
     if (!need_d) return DSNLM_OK;
     rc = check_hip(launch_sweep(kPassD, S, P, none, g_bws.descs, g_bws.dtiles, (int)dtiles.size(), st),
                    "batched sweep D");
+    if (!rc)
+        rc = check_hip(launch_d_gather(S, P, none, g_bws.descs, g_bws.dtiles, (int)dtiles.size(), st),
+                       "batched sweep D gather");
     if (rc) return rc;
     ProfScope prof(DSNLM_K_BWD_TAIL, st);
     hipLaunchKernelGGL(k_fold_seg, dim3(nmap), dim3(256), 0, st, g_bws.args, g_bws.map);

@@ -68,6 +68,8 @@ struct Geo {
     static constexpr int VW = ((VW0 / 4) % 2) ? VW0 : VW0 + 4;
     static constexpr int BW = TW + 2 * P + 1;         // sweep D: Dbar rows
     static constexpr int CH = TH - 2 * P, CW = TW - 2 * P;  // sweep D core
+    // sweep D partner region of the core: CH + S rows, CW + 2S columns
+    static constexpr int RWc = (CW + 2 * S_CLASS) | 1;
     static_assert(TH % R == 0 && TW % L == 0 && L % 4 == 0, "tile shape");
 };
 
@@ -89,8 +91,9 @@ size_t lds_floats(int S, int mode) {
     size_t n = (ZWr * G::ZC + 3) & ~(size_t)3;
     n += (AH * G::AW * naux(mode) + 3) & ~(size_t)3;
     if (mode == kPassD) {
-        n += (size_t)G::TH * G::VW;      // one V buffer (three barriers per shift)
-        n += (size_t)2 * G::TH * G::BW;  // Dbar and its vertical box sums
+        n += (size_t)G::TH * G::VW;               // one V buffer
+        n += (size_t)2 * G::TH * G::BW;           // Dbar and its vertical box sums
+        n += (size_t)(G::CH + S) * G::RWc;        // partner region of the core
     } else {
         n += (size_t)2 * G::TH * G::VW;
     }
@@ -153,6 +156,7 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
     constexpr int NVB = (MODE == kPassD) ? 1 : 2;  // V buffers
     float* Db = Vb + NVB * TH * VW;                // sweep D only
     float* VDb = Db + TH * G::BW;
+    float* Rg = VDb + TH * G::BW;                  // sweep D partner region (stride RWc)
 
     // ---- stage the guide tile (halo S+P, mirrored) and the per-pixel inputs
     for (int idx = tid; idx < ZH * ZWr; idx += NT) {
@@ -162,7 +166,8 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
         Zs[q * ZC + r] = d.z[(size_t)gi * n2 + gj];
     }
     if constexpr (MODE == kPassD) {
-        for (int idx = tid; idx < 2 * TH * G::BW; idx += NT) Db[idx] = 0.f;  // and VDb
+        // Dbar, its box sums and the partner region start at zero
+        for (int idx = tid; idx < 2 * TH * G::BW + (G::CH + S) * G::RWc; idx += NT) Db[idx] = 0.f;
     }
     if constexpr (NA == 2) {
         for (int idx = tid; idx < AH * AWr; idx += NT) {
@@ -439,15 +444,20 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
 #pragma unroll
             for (int q = 1; q <= 2 * P; ++q) hs += vr[q];
             const float* zq = Zs + (pj + S + P + dx) * ZC + pi + S + P + dy;
+            // partner-region entry of output 0 moved by d (core coordinates)
+            float* rq = Rg + (pi - P + dy) * G::RWc + pj - P + dx + S;
+            const bool crow = pi >= P && pi < TH - P;
 #pragma unroll
             for (int k = 0; k < L; ++k) {
                 if (k > 0) hs += vr[k + 2 * P] - vr[k - 1];
-                // zbar += 2 dz G (the 2 is applied at the end); the bandwidth
-                // sum needs sum_s Dbar D = sum_q e_d(q) G(q), e_d = dz^2
+                // T = dz G: zbar(q) += 2T and, for the mirrored pair, zbar(q+d)
+                // -= 2T (the 2 is applied by the gather); the bandwidth sum
+                // needs sum_s Dbar D = sum_q e_d(q) G(q), e_d = dz^2
                 const float dz = zown[k] - zq[k * ZC];
                 const float t = dz * hs;
                 accz[k] += t;
                 hk[k] = fmaf(dz, t, hk[k]);
+                if (crow && pj + k >= P && pj + k < TW - P) rq[k] -= t;
             }
         } else {
             (void)dy;
@@ -468,7 +478,8 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
         int t = 0;
         int pdy = 0, pdx = 0;  // previous shift (sweep D)
         for (dx = -S; dx <= S; ++dx) {
-            for (int dy0 = -S; dy0 <= S; dy0 += GW) {
+            // sweep D visits the half window (its pairs are symmetric)
+            for (int dy0 = (MODE == kPassD ? (dx > 0 ? 0 : 1) : -S); dy0 <= S; dy0 += GW) {
                 float win[G::ROUNDS1][NW];
 #pragma unroll
                 for (int k1 = 0; k1 < G::ROUNDS1; ++k1) {
@@ -557,31 +568,34 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
     }
 
     if constexpr (MODE == kPassD) {
-        const int W2 = n2 + 2 * P;
         // the core: the s-tile less P on each side (cores tile the padded grid)
         auto core = [&](int k) { return pi >= P && pi < TH - P && pj + k >= P && pj + k < TW - P; };
+        __syncthreads();  // every scatter of the last shift is in the region
 #pragma unroll
-        for (int k = 0; k < L; ++k) {
-            const int gj = gj_own + k;
-            if (core(k) && gi_own >= -P && gi_own < n1 + P && gj >= -P && gj < n2 + P)
-                d.gz[(size_t)(gi_own + P) * W2 + gj + P] = 2.f * accz[k];
-        }
+        for (int k = 0; k < L; ++k)
+            if (core(k)) Rg[(pi - P) * G::RWc + pj + k - P + S] += accz[k];
         float hacc = 0.f;
 #pragma unroll
         for (int k = 0; k < L; ++k) hacc += core(k) ? hk[k] : 0.f;
-        // block partial of sum Dbar D: fixed-order LDS tree (V is free: its
-        // last reads, in the last shift's phase 2, precede two barriers)
+        __syncthreads();
+        const int tile = BATCH ? (int)blockIdx.x - d.tile_base : (int)(blockIdx.y * gridDim.x + blockIdx.x);
+        const int RH = G::CH + S, RWr = G::CW + 2 * S;
+        float* part = d.dpart + (size_t)tile * RH * RWr;
+        for (int idx = tid; idx < RH * RWr; idx += NT) {
+            const int r = idx / RWr, q = idx - r * RWr;
+            part[idx] = Rg[r * G::RWc + q];
+        }
+        // block partial of sum Dbar D over the half window, doubled for the
+        // mirrored pairs: fixed-order LDS tree (V is free: its last reads, in
+        // the last shift's phase 2, precede the barriers above)
         float* red = Vb;
-        red[tid] = hacc;
+        red[tid] = 2.f * hacc;
         __syncthreads();
         for (int w = NT / 2; w > 0; w >>= 1) {
             if (tid < w) red[tid] += red[tid + w];
             __syncthreads();
         }
-        if (tid == 0) {
-            const int hidx = BATCH ? (int)blockIdx.x - d.tile_base : (int)(blockIdx.y * gridDim.x + blockIdx.x);
-            d.hpart[hidx] = red[0];
-        }
+        if (tid == 0) d.hpart[tile] = red[0];
         return;
     }
 
@@ -815,6 +829,70 @@ hipError_t launch_sweep(int mode, int S, int P, const ImgDesc& one, const ImgDes
     ProfScope prof(kind, st);
     if (batch) return dispatch_p<true>(mode, S, P, one, batch, tiles, ntiles, st);
     return dispatch_p<false>(mode, S, P, one, batch, tiles, ntiles, st);
+}
+
+// Sweep D gather: every padded-grid pixel q of a tile's core sums the partial
+// regions of the (at most six) tiles covering it in a fixed order (own, left,
+// right, above, above-left, above-right) and gz(q) = 2 x the sum.
+template <bool BATCH>
+__global__ void __launch_bounds__(256)
+k_d_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__ tiles, int S, int P,
+           int CH, int CW) {
+    ImgDesc d;
+    int ti0, tj0, tile;
+    if constexpr (BATCH) {
+        const TileRef t = tiles[blockIdx.x];
+        d = batch[t.img];
+        ti0 = t.ti0;
+        tj0 = t.tj0;
+        tile = (int)blockIdx.x - d.tile_base;
+    } else {
+        d = one;
+        ti0 = blockIdx.y * CH - 2 * P;
+        tj0 = blockIdx.x * CW - 2 * P;
+        tile = blockIdx.y * gridDim.x + blockIdx.x;
+    }
+    const int n1 = d.n1, n2 = d.n2, W2 = n2 + 2 * P;
+    const int tx_n = (n2 + 2 * P + CW - 1) / CW;
+    const int ty = (ti0 + 2 * P) / CH, tx = (tj0 + 2 * P) / CW;
+    const int RH = CH + S, RWr = CW + 2 * S;
+    const size_t reg = (size_t)RH * RWr;
+    for (int e = threadIdx.x; e < CH * CW; e += 256) {
+        const int li = e / CW, lj = e - li * CW;
+        const int qi = ti0 + P + li, qj = tj0 + P + lj;  // padded-grid position
+        if (qi >= n1 + P || qj >= n2 + P) continue;
+        auto at = [&](int t, int r, int q) { return d.dpart[(size_t)t * reg + (size_t)r * RWr + q]; };
+        const bool left = tx > 0 && lj < S, right = tx + 1 < tx_n && lj >= CW - S;
+        float acc = at(tile, li, lj + S);
+        if (left) acc += at(tile - 1, li, lj + CW + S);
+        if (right) acc += at(tile + 1, li, lj - CW + S);
+        if (ty > 0 && li < S) {
+            const int up = tile - tx_n;
+            acc += at(up, li + CH, lj + S);
+            if (left) acc += at(up - 1, li + CH, lj + CW + S);
+            if (right) acc += at(up + 1, li + CH, lj - CW + S);
+        }
+        d.gz[(size_t)(qi + P) * W2 + qj + P] = 2.f * acc;
+    }
+}
+
+size_t sweep_d_part_floats(int n1, int n2, int S, int P) {
+    const int CH = 32 - 2 * P, CW = 64 - 2 * P;
+    const size_t nd = (size_t)((n1 + 2 * P + CH - 1) / CH) * ((n2 + 2 * P + CW - 1) / CW);
+    return nd * (size_t)(CH + S) * (CW + 2 * S);
+}
+
+hipError_t launch_d_gather(int S, int P, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
+                           int ntiles, hipStream_t st) {
+    const int CH = 32 - 2 * P, CW = 64 - 2 * P;
+    ProfScope prof(DSNLM_K_BWD_TAIL, st);
+    if (batch) {
+        hipLaunchKernelGGL((k_d_gather<true>), dim3(ntiles), dim3(256), 0, st, one, batch, tiles, S, P, CH, CW);
+    } else {
+        const dim3 grid((one.n2 + 2 * P + CW - 1) / CW, (one.n1 + 2 * P + CH - 1) / CH);
+        hipLaunchKernelGGL((k_d_gather<false>), grid, dim3(256), 0, st, one, batch, tiles, S, P, CH, CW);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_epilogue(const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,

@@ -35,6 +35,7 @@ struct ImgDesc {
                            // (omegabar, c, B'bar, x) per pixel
     const float* mbar;     // device scalar mbar of the backward (sweep D)
     float* gz;             // sweep D output: gradient on the padded grid
+    float* dpart;          // sweep D: per-tile partner-region partial sums
     float* hpart;          // sweep D output: per-block partial sums for dh
     float* part;           // half-window sweeps: per-tile partner-region partial sums
     float* zpad;           // half-window sweeps: the guide mirrored into a margin of S + P
@@ -107,6 +108,13 @@ bool half_mode_ok(int mode);
 hipError_t launch_half(int mode, int S, int P, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
                        int ntiles, hipStream_t st);
 hipError_t prepare_half(int S, int P);
+
+// Sweep D (S <= 12) runs over the half window and writes per-tile partial
+// regions; the gather turns them into the padded-grid gradient gz.  Floats
+// of the partial buffer of an n1 x n2 image, and the gather launcher.
+size_t sweep_d_part_floats(int n1, int n2, int S, int P);
+hipError_t launch_d_gather(int S, int P, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
+                           int ntiles, hipStream_t st);
 
 // Backward launchers (dsnlm_backward.hip).
 // Backward (dsnlm_backward.hip): LDS bytes of sweep D and the largest S it
