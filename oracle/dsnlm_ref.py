@@ -299,3 +299,47 @@ def dsnlm_shifts(x, z, S: int, P: int, h, want: str = "y") -> dict:
         hs[i0:i1, j0:j1] += w
     out["y"] = acc + (1.0 - hs) * xt
     return out
+
+
+# ---------------------------------------------------------------------------
+# Plain NLM (eq. NLM): the row-stochastic filter DSG-NLM is built from.
+# ---------------------------------------------------------------------------
+def nlm_dense(x, z, S: int, P: int, h: float) -> np.ndarray:
+    """y = K x with K = diag(1 / sum_r k_{s,r}) [k_{s,r}]: eq. NLM written as a
+    matrix (kernel of the guide z, no hat, window cut at the border; tiny
+    images only)."""
+    x = np.asarray(x, dtype=np.float64)
+    K = dense_weights(z, S, P, h)["K"]
+    Kn = K / K.sum(1, keepdims=True)
+    return (Kn @ x.ravel()).reshape(x.shape)
+
+
+def nlm_shifts(x, z, S: int, P: int, h: float) -> np.ndarray:
+    """eq. NLM with the pixel loop vectorised and a Python loop over the
+    (2S+1)^2 window shifts, patch distances summed directly (torch FP64):
+    y_s = sum_r k_{s,r} x_r / sum_r k_{s,r}."""
+    xt = _as_t(x)
+    zt = _as_t(z)
+    n1, n2 = zt.shape
+    check_args(n1, n2, S, P, float(h))
+    Np = 2 * P + 1
+    zp = zt[torch.as_tensor(sym_index(n1, P))][:, torch.as_tensor(sym_index(n2, P))]
+    kappa = 1.0 / (2.0 * Np * Np * float(h) ** 2)
+    num = torch.zeros((n1, n2), dtype=torch.float64)
+    den = torch.zeros((n1, n2), dtype=torch.float64)
+    for dy in range(-S, S + 1):
+        for dx in range(-S, S + 1):
+            i0, i1 = _shift_ranges(n1, dy)
+            j0, j1 = _shift_ranges(n2, dx)
+            if i0 >= i1 or j0 >= j1:
+                continue
+            D = torch.zeros((i1 - i0, j1 - j0), dtype=torch.float64)
+            for ty in range(Np):
+                for tx in range(Np):
+                    a = zp[i0 + ty:i1 + ty, j0 + tx:j1 + tx]
+                    b = zp[i0 + dy + ty:i1 + dy + ty, j0 + dx + tx:j1 + dx + tx]
+                    D = D + (a - b) ** 2
+            k = torch.exp(-kappa * D)
+            num[i0:i1, j0:j1] += k * xt[i0 + dy:i1 + dy, j0 + dx:j1 + dx]
+            den[i0:i1, j0:j1] += k
+    return (num / den).numpy()

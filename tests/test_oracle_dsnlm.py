@@ -167,3 +167,42 @@ def test_argument_domain():
         R.check_args(4, 4, 1, 1, float("nan"))
     with pytest.raises(ValueError):
         R.dsnlm_shifts(z, z, 1, 1, -1.0)
+
+
+# ---- plain NLM (eq. NLM) -------------------------------------------------
+def test_nlm_two_routes_agree_and_rows_are_stochastic():
+    _, z = synth.piecewise_smooth(7, 9, 61, 0.05)
+    _, x = synth.piecewise_smooth(7, 9, 62, 0.05)
+    S, P, h = 2, 1, 0.1
+    y1 = R.nlm_dense(x, z, S, P, h)
+    y2 = R.nlm_shifts(x, z, S, P, h)
+    assert np.abs(y1 - y2).max() <= 1e-13
+    K = R.dense_weights(z, S, P, h)["K"]
+    Kn = K / K.sum(1, keepdims=True)
+    assert np.abs(Kn.sum(1) - 1).max() <= 1e-14
+    assert np.abs(R.nlm_dense(np.full((7, 9), 0.3), z, S, P, h) - 0.3).max() <= 1e-14
+    assert y1.min() >= x.min() - 1e-15 and y1.max() <= x.max() + 1e-15
+
+
+def test_nlm_large_bandwidth_is_the_window_mean():
+    """h -> infinity: k = 1 on the (border-cut) window, so y_s is the plain mean
+    of x over Omega_s, a box filter computed here with numpy slicing."""
+    _, x = synth.piecewise_smooth(8, 11, 63, 0.05)
+    x = x.astype(np.float64)
+    S, P = 2, 1
+    y = R.nlm_dense(x, x, S, P, 1e9)
+    n1, n2 = x.shape
+    ref = np.empty_like(y)
+    for i in range(n1):
+        for j in range(n2):
+            blk = x[max(0, i - S):min(n1, i + S + 1), max(0, j - S):min(n2, j + S + 1)]
+            ref[i, j] = blk.mean()
+    assert np.abs(y - ref).max() <= 1e-12
+
+
+def test_nlm_vanishing_bandwidth_is_identity():
+    rng = np.random.default_rng(64)
+    z = rng.random((6, 7))
+    x = rng.random((6, 7))
+    y = R.nlm_dense(x, z, 2, 1, 1e-4)
+    assert np.array_equal(y, x.astype(np.float64))
