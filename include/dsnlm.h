@@ -82,6 +82,15 @@ int dsnlm_apply(const dsnlm_weights* w, const float* x, float* y, void* stream);
 int dsnlm_forward(const float* guide, const float* x, float* y, int n1, int n2,
                   int S, int P, float h, void* stream, dsnlm_weights** out);
 
+/* Plain NLM, eq. NLM of Section 3 (the row-stochastic filter DSG-NLM is
+ * derived from): y_s = sum_r k_{s,r} x_r / sum_r k_{s,r}, k the same kernel of
+ * the guide's patches (no hat), r over the border-cut window, r = s included.
+ * Arguments as for dsnlm_forward; out (NULL or a handle, created if *out is
+ * NULL) only lends its workspace: the handle then holds no DSG-NLM weights
+ * (dsnlm_apply_backward rejects it until the next DSG-NLM forward). */
+int dsnlm_nlm(const float* guide, const float* x, float* y, int n1, int n2, int S, int P, float h,
+              void* stream, dsnlm_weights** out);
+
 /* Vector-Jacobian product of y = W(guide, h) x at the x of the last apply or
  * forward on this handle (x must be passed again, unchanged).
  * dy: cotangent of y.  Outputs (each may be NULL to skip it):
@@ -179,6 +188,9 @@ typedef struct {
     int freeze_after;         /* k0 >= 1: weights rebuilt from the denoiser's
                                  input x + u while k <= k0, then frozen */
     float lo, hi;             /* box C = [lo, hi]^n (lo < hi) */
+    int denoiser;             /* 0: DSG-NLM (Section 3); 1: plain NLM (eq. NLM),
+                                 rebuilt every iteration (freeze_after is not
+                                 used; no backward) */
 } ladmm_params;
 
 /* One iteration k (1-based) of Algorithm 1 in place on x, v, u (device,

@@ -14,6 +14,7 @@ from .api import (  # noqa: F401
     dsnlm_build_weights,
     dsnlm_forward,
     dsnlm_forward_batched,
+    dsnlm_nlm,
     dsnlm_backward_batched,
     ladmm_apply_forward,
     ladmm_gradient,

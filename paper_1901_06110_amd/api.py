@@ -116,6 +116,19 @@ def dsnlm_forward(x: torch.Tensor, guide: Optional[torch.Tensor], S: int, P: int
     return y
 
 
+def dsnlm_nlm(x: torch.Tensor, guide: Optional[torch.Tensor], S: int, P: int, h: float,
+              y: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Plain NLM (eq. NLM): y_s = sum_r k x_r / sum_r k with the kernel of the
+    guide's patches (guide = x when None)."""
+    x = _img(x, "x")
+    guide = x if guide is None else _img(guide, "guide")
+    n1, n2 = x.shape
+    if y is None:
+        y = torch.empty_like(x)
+    _lib.check(_lib.get().dsnlm_nlm(_p(guide), _p(x), _p(y), n1, n2, S, P, float(h), _stream(), None))
+    return y
+
+
 def dsnlm_apply_backward(w: Weights, x: torch.Tensor, dy: torch.Tensor, need_dx: bool = True,
                          need_dguide: bool = True, need_dh: bool = True):
     x = _img(x, "x")
@@ -232,10 +245,11 @@ class LadmmParams:
     freeze_after: int = 1
     lo: float = 0.0
     hi: float = 1.0
+    denoiser: int = 0  # 0 DSG-NLM, 1 plain NLM (eq. NLM), rebuilt every iteration
 
     def c_struct(self):
         return _lib.LadmmParams(self.lam, self.rho, self.gamma, self.S, self.P, self.h, self.iters,
-                                self.freeze_after, self.lo, self.hi)
+                                self.freeze_after, self.lo, self.hi, self.denoiser)
 
 
 def ladmm_step(op, params: LadmmParams, k: int, weights: Optional[Weights], x, v, u) -> Weights:

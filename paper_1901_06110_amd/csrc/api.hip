@@ -163,6 +163,34 @@ int dsnlm_apply(const dsnlm_weights* wc, const float* x, float* y, void* stream)
     return DSNLM_OK;
 }
 
+int dsnlm_nlm(const float* guide, const float* x, float* y, int n1, int n2, int S, int P, float h, void* stream,
+              dsnlm_weights** out) {
+    if (!guide || !x || !y) return fail(DSNLM_EINVAL, "dsnlm_nlm: null pointer");
+    int rc = check_denoiser_args(n1, n2, S, P, h, "dsnlm_nlm");
+    if (rc) return rc;
+    const size_t bytes = (size_t)n1 * n2 * sizeof(float);
+    if (overlaps(x, y, bytes) || overlaps(guide, y, bytes))
+        return fail(DSNLM_EINVAL, "dsnlm_nlm: y overlaps x or the guide");
+    if (!half_lds_fits(S, P, kNLM)) return fail(DSNLM_EUNSUPPORTED, "dsnlm_nlm: S and P too large");
+    dsnlm_weights* local = nullptr;
+    dsnlm_weights** hp = out ? out : &local;
+    rc = prepare_handle(n1, n2, S, P, h, hp);
+    if (rc) return rc;
+    dsnlm_weights* w = *hp;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    rc = check_hip(hipMemcpyAsync(w->guide, guide, bytes, hipMemcpyDeviceToDevice, st), "copy guide");
+    ImgDesc d = base_desc(w);
+    d.x = x;
+    d.y = y;
+    if (!rc) rc = check_hip(launch_half(kNLM, S, P, d, nullptr, nullptr, 0, st), "plain NLM sweep");
+    if (local) {
+        hipError_t e = hipStreamSynchronize(st);
+        dsnlm_weights_destroy(local);
+        if (!rc) rc = check_hip(e, "dsnlm_nlm: synchronise");
+    }
+    return rc;
+}
+
 int dsnlm_forward(const float* guide, const float* x, float* y, int n1, int n2, int S, int P,
                   float h, void* stream, dsnlm_weights** out) {
     if (!guide || !x || !y) return fail(DSNLM_EINVAL, "dsnlm_forward: null pointer");

@@ -11,6 +11,7 @@
 //   pass A       sum_r a                       (omega)
 //   pass B, apply sum_r a c_r, sum_r a c_r x_r  (delta, B')
 //   sweep C      sum_r a t_r, sum_r a w_r      (backward)
+//   plain NLM    sum_r k, sum_r k x_r          (eq. NLM: no hat, y = ratio)
 //
 // A tile adds a * factor(r) to its own pixel s in registers and a * factor(s)
 // to the partner r in an LDS accumulator that spans the tile's partner region
@@ -155,6 +156,9 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
                     const float2 tw = reinterpret_cast<const float2*>(d.aux_in)[p];
                     v.x = tw.x;
                     v.y = tw.y;
+                } else if constexpr (MODE == kNLM) {
+                    v.x = 1.f;
+                    v.y = d.x[p];
                 } else {
                     const float cc = d.c[p];
                     v.x = cc;
@@ -166,6 +170,11 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
     }
     if constexpr (MODE == kPassA) {
         if (first && tid == 0) *d.key = 0ull;  // the pass-B gather takes the max after this
+    }
+    if constexpr (MODE == kNLM) {
+        // plain NLM has no normalisation by a maximum: store m = 1 so that the
+        // common update x + B'/m applies its increment unchanged
+        if (first && tid == 0) *d.key = ((unsigned long long)__float_as_uint(1.0f) << 32) | 0xffffffffull;
     }
 
     // ---- phase-1 item: one column strip of R rows (threads past NITEM1 idle).
@@ -400,6 +409,14 @@ k_half_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __r
         } else if constexpr (MODE == kPassC) {
             const float2 tw = reinterpret_cast<const float2*>(d.aux_in)[p];
             reinterpret_cast<float2*>(d.aux_out)[p] = make_float2(s0 + tw.x, s1 + tw.y);
+        } else if constexpr (MODE == kNLM) {
+            // d = 0: k = 1.  y = sum k x_r / sum k = x + (sum k x_r - x sum k) / sum k
+            const float xs = d.x[p];
+            s0 += 1.f;
+            s1 += xs;
+            const float inc = (s1 - xs * s0) / s0;
+            d.bp[p] = inc;
+            if (d.y) d.y[p] = xs + inc;
         } else {
             const float cs = d.c[p];
             s0 += cs;  // d = 0: a = 1, partner factor c_s
@@ -442,6 +459,7 @@ hipError_t half_attr_all() {
     if (e == hipSuccess) e = half_attr<P, S_CLASS, kPassBBuild, false>();
     if (e == hipSuccess) e = half_attr<P, S_CLASS, kApply, false>();
     if (e == hipSuccess) e = half_attr<P, S_CLASS, kPassC, false>();
+    if (e == hipSuccess) e = half_attr<P, S_CLASS, kNLM, false>();
     return e;
 }
 
@@ -459,8 +477,10 @@ hipError_t launch_half_one(int S, const ImgDesc& one, const ImgDesc* batch, cons
     hipError_t ea = half_attr<P, S_CLASS, MODE, BATCH>();
     if (ea != hipSuccess) return ea;
     const dim3 grid = BATCH ? dim3(ntiles) : dim3((one.n2 + G::TW - 1) / G::TW, (one.n1 + G::TH - 1) / G::TH);
-    const HatTable hat = make_hat(S);
-    if constexpr (MODE == kPassA) {  // the mirrored guide copy read by every half sweep
+    HatTable hat = make_hat(S);
+    if constexpr (MODE == kNLM)
+        for (float& v : hat.lg) v = 0.f;  // eq. NLM has no hat
+    if constexpr (MODE == kPassA || MODE == kNLM) {  // the mirrored guide copy read by the half sweeps
         ProfScope prof(DSNLM_K_HALF_AUX, st);
         hipLaunchKernelGGL((k_half_pad<BATCH>), grid, dim3(256), 0, st, one, batch, tiles, S + P);
         hipError_t e = hipGetLastError();
@@ -468,7 +488,7 @@ hipError_t launch_half_one(int S, const ImgDesc& one, const ImgDesc* batch, cons
     }
     {
         constexpr int kind = MODE == kPassA ? DSNLM_K_PASS_A
-                             : (MODE == kPassBApply || MODE == kPassBBuild) ? DSNLM_K_PASS_B
+                             : (MODE == kPassBApply || MODE == kPassBBuild || MODE == kNLM) ? DSNLM_K_PASS_B
                              : MODE == kApply ? DSNLM_K_APPLY
                                               : DSNLM_K_PASS_C;
         ProfScope prof(kind, st);
@@ -491,6 +511,7 @@ hipError_t half_mode(int mode, int S, const ImgDesc& one, const ImgDesc* batch, 
         case kPassBBuild: return launch_half_one<P, S_CLASS, kPassBBuild, BATCH>(S, one, batch, tiles, ntiles, st);
         case kApply: return launch_half_one<P, S_CLASS, kApply, BATCH>(S, one, batch, tiles, ntiles, st);
         case kPassC: return launch_half_one<P, S_CLASS, kPassC, BATCH>(S, one, batch, tiles, ntiles, st);
+        case kNLM: return launch_half_one<P, S_CLASS, kNLM, BATCH>(S, one, batch, tiles, ntiles, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -68,6 +68,7 @@ enum SweepMode : int {
     kApply = 3,        // B' only (weights already built)
     kPassC = 4,        // backward: sum a t_r, sum a w_r
     kPassD = 5,        // backward: guide and bandwidth gradients
+    kNLM = 6,          // plain NLM (eq. NLM): sums of k and k x, no hat (half window only)
 };
 
 // Variant table of the sweeps (tuning.hip).

@@ -379,6 +379,9 @@ int check_params(const ladmm_params* p, int n1, int n2, const char* who, float* 
     if (!(p->lo < p->hi) || !std::isfinite(p->lo) || !std::isfinite(p->hi))
         return fail(DSNLM_EINVAL, w + ": need finite lo < hi");
     if (p->freeze_after < 1) return fail(DSNLM_EINVAL, w + ": freeze_after must be >= 1");
+    if (p->denoiser != 0 && p->denoiser != 1) return fail(DSNLM_EINVAL, w + ": denoiser must be 0 or 1");
+    if (p->denoiser == 1 && !half_lds_fits(p->S, p->P, kNLM))
+        return fail(DSNLM_EUNSUPPORTED, w + ": plain NLM for these S and P");
     if (p->iters < 0) return fail(DSNLM_EINVAL, w + ": iters must be >= 0");
     if (!std::isfinite(p->h)) return fail(DSNLM_EINVAL, w + ": h must be finite");
     const float h = p->h > 0.f ? p->h : std::sqrt(p->lambda / p->rho);
@@ -435,7 +438,14 @@ int enqueue_step(const ladmm_operator* op, const OpView& ov, const ladmm_params*
     ImgDesc d = base_desc(w);
     d.x = z;
     int rc;
-    if (k <= p->freeze_after) {
+    if (p->denoiser == 1) {
+        // plain NLM of z guided by z: writes its increment into B' and m = 1
+        rc = check_hip(hipMemcpyAsync(w->guide, z, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st),
+                       "copy guide");
+        d.z = w->guide;
+        d.y = nullptr;
+        if (!rc) rc = check_hip(launch_half(kNLM, p->S, p->P, d, nullptr, nullptr, 0, st), "plain NLM");
+    } else if (k <= p->freeze_after) {
         // adaptive weights: guide = the denoiser's own input z
         rc = check_hip(hipMemcpyAsync(w->guide, z, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st),
                        "copy guide");
@@ -518,11 +528,12 @@ int ladmm_step(const ladmm_operator* op, const ladmm_params* p, int k, dsnlm_wei
     if (rc) return rc;
     if (!w || !x || !v || !u) return fail(DSNLM_EINVAL, "ladmm_step: null pointer");
     if (k < 1) return fail(DSNLM_EINVAL, "ladmm_step: k is 1-based");
-    if (k > p->freeze_after && !*w)
+    const bool adaptive = k <= p->freeze_after || p->denoiser == 1;
+    if (!adaptive && !*w)
         return fail(DSNLM_EINVAL, "ladmm_step: frozen iteration without built weights");
     if (*w && ((*w)->n1 != op->n1 || (*w)->n2 != op->n2))
         return fail(DSNLM_EINVAL, "ladmm_step: weights built for another image size");
-    if (k <= p->freeze_after) {
+    if (adaptive) {
         rc = prepare_handle(op->n1, op->n2, p->S, p->P, h, w);
         if (rc) return rc;
     }
@@ -562,7 +573,8 @@ int ladmm_solve(const ladmm_operator* op, const ladmm_params* p, float* x, float
     auto res_at = [&](int k) { return residuals ? residuals + 2 * (size_t)(k - 1) : nullptr; };
     auto ck_at = [&](int k) { return checkpoints ? checkpoints + 4 * n * (size_t)(k - 1) : nullptr; };
     int k = 1;
-    const int adaptive_end = p->freeze_after < p->iters ? p->freeze_after : p->iters;
+    // plain NLM is rebuilt every iteration (no frozen phase to capture)
+    const int adaptive_end = (p->freeze_after < p->iters && p->denoiser != 1) ? p->freeze_after : p->iters;
     for (; k <= adaptive_end && !rc; ++k)
         rc = enqueue_step(op, ov, p, h, k, w, x, v, u, lr, partials, res_at(k), ck_at(k), st);
     if (!rc && k <= p->iters) {

@@ -147,6 +147,7 @@ extern "C" int ladmm_step_backward(const ladmm_operator* op, const ladmm_params*
         !dparams)
         return fail(DSNLM_EINVAL, "ladmm_step_backward: null pointer");
     if (k < 1) return fail(DSNLM_EINVAL, "ladmm_step_backward: k is 1-based");
+    if (p->denoiser != 0) return fail(DSNLM_EUNSUPPORTED, "ladmm_step_backward: DSG-NLM denoiser only");
     if (k > p->freeze_after && !gacc)
         return fail(DSNLM_EINVAL, "ladmm_step_backward: frozen iterations need the guide-adjoint accumulator");
     const int n1 = op->n1, n2 = op->n2;
@@ -253,6 +254,7 @@ extern "C" int ladmm_solve_backward(const ladmm_operator* op, const ladmm_params
         return fail(DSNLM_EINVAL, "ladmm_solve_backward: null pointer");
     if (p->iters < 1) return DSNLM_OK;
     if (p->freeze_after < 1) return fail(DSNLM_EINVAL, "ladmm_solve_backward: freeze_after must be >= 1");
+    if (p->denoiser != 0) return fail(DSNLM_EUNSUPPORTED, "ladmm_solve_backward: DSG-NLM denoiser only");
     const size_t n = (size_t)op->n1 * op->n2;
     hipStream_t st = static_cast<hipStream_t>(stream);
     float* gacc = nullptr;
