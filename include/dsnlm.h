@@ -91,6 +91,13 @@ int dsnlm_forward(const float* guide, const float* x, float* y, int n1, int n2,
 int dsnlm_nlm(const float* guide, const float* x, float* y, int n1, int n2, int S, int P, float h,
               void* stream, dsnlm_weights** out);
 
+/* The brute-force comparator of Table 1: y = W(guide) x with every patch
+ * distance summed directly over its N_p^2 offsets (no box sums), one GPU
+ * thread per pixel.  Same arguments, outputs and handle state as
+ * dsnlm_forward; for timing comparisons, not the fast path. */
+int dsnlm_forward_brute(const float* guide, const float* x, float* y, int n1, int n2, int S, int P, float h,
+                        void* stream, dsnlm_weights** out);
+
 /* Vector-Jacobian product of y = W(guide, h) x at the x of the last apply or
  * forward on this handle (x must be passed again, unchanged).
  * dy: cotangent of y.  Outputs (each may be NULL to skip it):

@@ -15,6 +15,7 @@ from .api import (  # noqa: F401
     dsnlm_forward,
     dsnlm_forward_batched,
     dsnlm_nlm,
+    dsnlm_forward_brute,
     dsnlm_backward_batched,
     ladmm_apply_forward,
     ladmm_gradient,

@@ -93,6 +93,7 @@ def _load():
         "dsnlm_apply": (i, [vp, vp, vp, vp]),
         "dsnlm_forward": (i, [vp, vp, vp, i, i, i, i, f, vp, pp]),
         "dsnlm_nlm": (i, [vp, vp, vp, i, i, i, i, f, vp, pp]),
+        "dsnlm_forward_brute": (i, [vp, vp, vp, i, i, i, i, f, vp, pp]),
         "dsnlm_apply_backward": (i, [vp, vp, vp, vp, vp, vp, vp]),
         "dsnlm_weights_destroy": (None, [vp]),
         "dsnlm_weights_scalars": (i, [vp, C.POINTER(f), C.POINTER(i), vp]),
@@ -143,6 +144,7 @@ EXPORTED = [
     "dsnlm_profile_enable", "dsnlm_profile_query", "dsnlm_profile_reset",
     "dsnlm_tune_set", "dsnlm_tune_get", "dsnlm_tune", "dsnlm_peak_probe",
     "ladmm_step_backward", "ladmm_solve_backward", "dsnlm_backward_batched", "dsnlm_nlm",
+    "dsnlm_forward_brute",
 ]
 
 K_PASS_A, K_PASS_B, K_APPLY, K_EPILOGUE, K_BWD_PREP, K_PASS_C, K_PASS_D, K_BWD_TAIL, K_LADMM, K_HALF_AUX = range(10)

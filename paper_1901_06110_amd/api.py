@@ -129,6 +129,18 @@ def dsnlm_nlm(x: torch.Tensor, guide: Optional[torch.Tensor], S: int, P: int, h:
     return y
 
 
+def dsnlm_forward_brute(x: torch.Tensor, guide: Optional[torch.Tensor], S: int, P: int, h: float,
+                        y: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """The brute-force comparator (patch distances summed directly)."""
+    x = _img(x, "x")
+    guide = x if guide is None else _img(guide, "guide")
+    n1, n2 = x.shape
+    if y is None:
+        y = torch.empty_like(x)
+    _lib.check(_lib.get().dsnlm_forward_brute(_p(guide), _p(x), _p(y), n1, n2, S, P, float(h), _stream(), None))
+    return y
+
+
 def dsnlm_apply_backward(w: Weights, x: torch.Tensor, dy: torch.Tensor, need_dx: bool = True,
                          need_dguide: bool = True, need_dh: bool = True):
     x = _img(x, "x")

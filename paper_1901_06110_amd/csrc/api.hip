@@ -191,6 +191,35 @@ int dsnlm_nlm(const float* guide, const float* x, float* y, int n1, int n2, int 
     return rc;
 }
 
+int dsnlm_forward_brute(const float* guide, const float* x, float* y, int n1, int n2, int S, int P, float h,
+                        void* stream, dsnlm_weights** out) {
+    if (!guide || !x || !y) return fail(DSNLM_EINVAL, "dsnlm_forward_brute: null pointer");
+    int rc = check_denoiser_args(n1, n2, S, P, h, "dsnlm_forward_brute");
+    if (rc) return rc;
+    const size_t bytes = (size_t)n1 * n2 * sizeof(float);
+    if (overlaps(x, y, bytes) || overlaps(guide, y, bytes))
+        return fail(DSNLM_EINVAL, "dsnlm_forward_brute: y overlaps x or the guide");
+    dsnlm_weights* local = nullptr;
+    dsnlm_weights** hp = out ? out : &local;
+    rc = prepare_handle(n1, n2, S, P, h, hp);
+    if (rc) return rc;
+    dsnlm_weights* w = *hp;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    rc = check_hip(hipMemcpyAsync(w->guide, guide, bytes, hipMemcpyDeviceToDevice, st), "copy guide");
+    ImgDesc d = base_desc(w);
+    d.x = x;
+    d.y = y;
+    if (!rc) rc = check_hip(launch_brute(d, S, P, st), "brute-force sweeps");
+    if (!rc) rc = check_hip(launch_epilogue(d, nullptr, nullptr, 0, S, P, st), "epilogue");
+    if (!rc) w->applied = true;
+    if (local) {
+        hipError_t e = hipStreamSynchronize(st);
+        dsnlm_weights_destroy(local);
+        if (!rc) rc = check_hip(e, "dsnlm_forward_brute: synchronise");
+    }
+    return rc;
+}
+
 int dsnlm_forward(const float* guide, const float* x, float* y, int n1, int n2, int S, int P,
                   float h, void* stream, dsnlm_weights** out) {
     if (!guide || !x || !y) return fail(DSNLM_EINVAL, "dsnlm_forward: null pointer");

@@ -110,6 +110,11 @@ hipError_t launch_half(int mode, int S, int P, const ImgDesc& one, const ImgDesc
                        int ntiles, hipStream_t st);
 hipError_t prepare_half(int S, int P);
 
+// Brute-force DSG-NLM (dsnlm_brute.hip): c, delta, B' and the key of d from
+// directly summed patch distances; d.zpad must hold room for the mirrored
+// guide (margin S + P).
+hipError_t launch_brute(const ImgDesc& d, int S, int P, hipStream_t st);
+
 // Sweep D (S <= 12) runs over the half window and writes per-tile partial
 // regions; the gather turns them into the padded-grid gradient gz.  Floats
 // of the partial buffer of an n1 x n2 image, and the gather launcher.
