@@ -213,3 +213,66 @@ def ladmm(x0, grad_f, *, alpha: float, rho: float, S: int, P: int, h: float,
         if record is not None:
             record.append((x.copy(), v.copy(), u.copy(), z.copy()))
     return dict(x=x, v=v, u=u, residuals=np.asarray(res), guide=guide)
+
+
+# ---------------------------------------------------------------------------
+# Standard plug-and-play ADMM with the inversion solved by conjugate gradients
+# (the comparator of Fig. 2; symmetric boundary, where no fast exact
+# inversion exists).
+# ---------------------------------------------------------------------------
+def cg(apply_M, b, x0, iters: int):
+    """`iters` conjugate-gradient steps for M x = b (M symmetric positive
+    definite, given as a function), started at x0."""
+    x = np.asarray(x0, dtype=np.float64).copy()
+    r = b - apply_M(x)
+    p = r.copy()
+    rr = float(np.sum(r * r))
+    for _ in range(iters):
+        if rr == 0.0:
+            break
+        q = apply_M(p)
+        a = rr / float(np.sum(p * q))
+        x = x + a * p
+        r = r - a * q
+        rr_new = float(np.sum(r * r))
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+    return x
+
+
+def admm_cg(x0, y, taps, factor: int, *, rho: float, S: int, P: int, h: float, iters: int,
+            freeze_after: int, cg_iters: int, boundary: str = "symmetric", v0=None, u0=None,
+            record=None, fixed_guide=None, denoise=None) -> dict:
+    """Standard PnP-ADMM for super-resolution: the inversion step is the exact
+    minimiser of 1/2||A x - y||^2 + rho/2 ||x - (v - u)||^2, i.e. the solution
+    of (A^T A + rho I) x = A^T y + rho (v - u), approximated by `cg_iters`
+    conjugate-gradient steps warm-started at the current x (no box
+    projection); then v = D(x + u) and u <- u + x - v as in Algorithm 1.
+    `record` / `fixed_guide` / `denoise` as in ladmm()."""
+    if denoise is None:
+        def denoise(zz, gg):
+            return dsnlm_ref.dsnlm_shifts(zz, gg, S, P, h)["y"].numpy()
+    x = np.asarray(x0, dtype=np.float64).copy()
+    v = x.copy() if v0 is None else np.asarray(v0, dtype=np.float64).copy()
+    u = np.zeros_like(x) if u0 is None else np.asarray(u0, dtype=np.float64).copy()
+    shape = x.shape
+    Aty = sr_adjoint(np.asarray(y, dtype=np.float64), taps, factor, shape, boundary)
+
+    def apply_M(p):
+        return sr_adjoint(sr_forward(p, taps, factor, boundary), taps, factor, shape, boundary) + rho * p
+
+    guide = None if fixed_guide is None else np.asarray(fixed_guide, dtype=np.float64)
+    res = []
+    for k in range(1, iters + 1):
+        x = cg(apply_M, Aty + rho * (v - u), x, cg_iters)
+        z = x + u
+        if fixed_guide is None and k <= freeze_after:
+            guide = z.copy()
+        v_new = denoise(z, guide)
+        dual = rho * (v_new - v)
+        v = v_new
+        u = u + x - v
+        res.append((residual_rms(x - v), residual_rms(dual)))
+        if record is not None:
+            record.append((x.copy(), v.copy(), u.copy(), z.copy()))
+    return dict(x=x, v=v, u=u, residuals=np.asarray(res), guide=guide)

@@ -157,3 +157,34 @@ def test_fixed_weights_box_constrained_minimum():
     assert abs(F(out["x"].ravel()) - F(xk)) <= 1e-10
     f_hist = [F(r[0].ravel()) for r in rec[::100]]
     assert f_hist[-1] <= f_hist[1] and f_hist[-1] - F(xk) <= 1e-10
+
+
+def test_cg_reaches_the_dense_solution():
+    """n steps of conjugate gradients solve an n x n SPD system exactly (up to
+    rounding): compared with numpy.linalg.solve on (A^T A + rho I)."""
+    n, rho = 8, 0.7
+    taps = L.gaussian_taps(9, 1.0)
+    A = L.sr_dense((n, n), taps, 2)
+    M = A.T @ A + rho * np.eye(n * n)
+    b = np.random.default_rng(5).standard_normal(n * n)
+    xs = np.linalg.solve(M, b)
+    x = L.cg(lambda p: (M @ p.ravel()).reshape(p.shape), b.reshape(n, n), np.zeros((n, n)), n * n)
+    assert np.abs(x.ravel() - xs).max() <= 1e-9 * np.abs(xs).max()
+    # the operator form used by admm_cg is the same matrix
+    p = np.random.default_rng(6).standard_normal((n, n))
+    Mp = L.sr_adjoint(L.sr_forward(p, taps, 2), taps, 2, (n, n)) + rho * p
+    assert np.abs(Mp.ravel() - M @ p.ravel()).max() <= 1e-12
+
+
+def test_standard_admm_reaches_the_same_fixed_point():
+    """With frozen weights, standard ADMM (exact inversion by CG) converges to
+    the same solution of (W A^T A + rho (I - W)) x = W A^T y as Algorithm 1."""
+    n, rho = 16, 1.0
+    A, y, guide, W = _fixed_point_setup(n)
+    xs = np.linalg.solve(W @ A.T @ A + rho * (np.eye(n * n) - W), W @ A.T @ y)
+    taps = L.gaussian_taps(9, 1.0)
+    out = L.admm_cg(np.full((n, n), 0.5), y.reshape(n // 2, n // 2), taps, 2, rho=rho, S=3, P=1, h=0.1,
+                    iters=1500, freeze_after=1, cg_iters=20, fixed_guide=guide,
+                    denoise=lambda z, g: (W @ z.ravel()).reshape(n, n))
+    assert np.abs(out["x"].ravel() - xs).max() <= 1e-9
+    assert np.abs(out["x"] - out["v"]).max() <= 1e-9
