@@ -217,6 +217,16 @@ int ladmm_step(const ladmm_operator* op, const ladmm_params* p, int k, dsnlm_wei
 int ladmm_solve(const ladmm_operator* op, const ladmm_params* p, float* x, float* v, float* u,
                 float* residuals, float* checkpoints, void* stream);
 
+/* Standard plug-and-play ADMM, the comparator of Fig. 2 (super-resolution
+ * only): each iteration solves the inversion step exactly,
+ * (A^T A + rho I) x = A^T y + rho (v - u), by cg_iters conjugate-gradient
+ * steps warm-started at the current x (no box projection; lo, hi and gamma
+ * are not used), then v = W(x + u) with the same weight schedule as
+ * ladmm_solve and u <- u + x - v.  residuals: device [iters][2] or NULL.
+ * Synchronises the stream before returning. */
+int admm_cg_solve(const ladmm_operator* op, const ladmm_params* p, int cg_iters, float* x, float* v,
+                  float* u, float* residuals, void* stream);
+
 /* Reverse mode through iteration k of Algorithm 1 (unrolled differentiation;
  * not in the paper: the chain rule through the x-step, the projection, the
  * denoiser and the dual update).  Inputs: the iteration's guide (z_k while

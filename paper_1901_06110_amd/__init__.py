@@ -22,6 +22,7 @@ from .api import (  # noqa: F401
     ladmm_operator_norm2,
     ladmm_solve,
     ladmm_solve_backward,
+    admm_cg_solve,
     ladmm_step,
     SROperator,
     SPIOperator,

@@ -276,6 +276,15 @@ def ladmm_step(op, params: LadmmParams, k: int, weights: Optional[Weights], x, v
     return Weights(hp, op.n1, op.n2, params.S, params.P, h)
 
 
+def admm_cg_solve(op, params: LadmmParams, cg_iters: int, x, v, u,
+                  residuals: Optional[torch.Tensor] = None) -> None:
+    """Standard PnP-ADMM with the inversion solved by cg_iters CG steps."""
+    o = op.c_struct()
+    p = params.c_struct()
+    _lib.check(_lib.get().admm_cg_solve(C.byref(o), C.byref(p), int(cg_iters), _p(x), _p(v), _p(u),
+                                        _p(residuals), _stream()))
+
+
 def ladmm_solve(op, params: LadmmParams, x, v, u, residuals: Optional[torch.Tensor] = None,
                 checkpoints: Optional[torch.Tensor] = None) -> None:
     o = op.c_struct()

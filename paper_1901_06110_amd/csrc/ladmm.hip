@@ -406,35 +406,13 @@ float* scratch_floats(dsnlm_weights* w, size_t n, int* rc) {
     return w->scratch;
 }
 
-// Enqueue iteration k of Algorithm 1.  lr: scratch for the low-resolution
-// residual (SR); partials: scratch for residual partials or null; res: device
-// [2] or null; ckpt: device [4][n] or null.
-int enqueue_step(const ladmm_operator* op, const OpView& ov, const ladmm_params* p, float h, int k,
-                 dsnlm_weights* w, float* x, float* v, float* u, float* lr, float* partials,
-                 float* res, float* ckpt, hipStream_t st) {
-    const int n = op->n1 * op->n2;
-    const float alpha = 1.0f / p->gamma;
-    StepScalars s{alpha, p->rho, 1.0f / (alpha + p->rho), p->lo, p->hi};
+// The denoising and dual halves of an iteration (shared by Algorithm 1 and
+// the standard ADMM comparator): v = D(z) with z = x + u already in w->zbuf,
+// u <- u + x - v, residuals and checkpoints.
+int enqueue_denoise_dual(const ladmm_params* p, int k, dsnlm_weights* w, float* x, float* v, float* u,
+                         float* partials, float* res, float* ckpt, hipStream_t st) {
+    const int n = w->n1 * w->n2;
     float* z = w->zbuf;
-    {
-        ProfScope prof(DSNLM_K_LADMM, st);
-        if (op->kind == LADMM_OP_SR) {
-            const int mlr = ov.g.m1 * ov.g.m2;
-            if (op->boundary == 0) {
-                hipLaunchKernelGGL(k_sr_forward<0>, dim3(blocks(mlr)), dim3(256), 0, st, x, op->y, lr, ov.g, ov.taps);
-                hipLaunchKernelGGL(k_sr_adjoint_step<0>, dim3(blocks(n)), dim3(256), 0, st, lr, x, v, u, z, ov.g,
-                                   ov.taps, s, 1);
-            } else {
-                hipLaunchKernelGGL(k_sr_forward<1>, dim3(blocks(mlr)), dim3(256), 0, st, x, op->y, lr, ov.g, ov.taps);
-                hipLaunchKernelGGL(k_sr_adjoint_step<1>, dim3(blocks(n)), dim3(256), 0, st, lr, x, v, u, z, ov.g,
-                                   ov.taps, s, 1);
-            }
-        } else {
-            hipLaunchKernelGGL(k_spi_step, dim3(blocks(n)), dim3(256), 0, st, x, v, u, z, op->ones, n, ov.q, s, 1);
-        }
-        int rc = check_hip(hipGetLastError(), "x-step");
-        if (rc) return rc;
-    }
     ImgDesc d = base_desc(w);
     d.x = z;
     int rc;
@@ -474,6 +452,157 @@ int enqueue_step(const ladmm_operator* op, const OpView& ov, const ladmm_params*
         if (!rc) rc = check_hip(hipMemcpyAsync(ckpt + 3 * (size_t)n, z, b, hipMemcpyDeviceToDevice, st), "checkpoint");
     }
     return rc;
+}
+
+// Enqueue iteration k of Algorithm 1.  lr: scratch for the low-resolution
+// residual (SR); partials: scratch for residual partials or null; res: device
+// [2] or null; ckpt: device [4][n] or null.
+int enqueue_step(const ladmm_operator* op, const OpView& ov, const ladmm_params* p, float h, int k,
+                 dsnlm_weights* w, float* x, float* v, float* u, float* lr, float* partials,
+                 float* res, float* ckpt, hipStream_t st) {
+    const int n = op->n1 * op->n2;
+    const float alpha = 1.0f / p->gamma;
+    StepScalars s{alpha, p->rho, 1.0f / (alpha + p->rho), p->lo, p->hi};
+    float* z = w->zbuf;
+    {
+        ProfScope prof(DSNLM_K_LADMM, st);
+        if (op->kind == LADMM_OP_SR) {
+            const int mlr = ov.g.m1 * ov.g.m2;
+            if (op->boundary == 0) {
+                hipLaunchKernelGGL(k_sr_forward<0>, dim3(blocks(mlr)), dim3(256), 0, st, x, op->y, lr, ov.g, ov.taps);
+                hipLaunchKernelGGL(k_sr_adjoint_step<0>, dim3(blocks(n)), dim3(256), 0, st, lr, x, v, u, z, ov.g,
+                                   ov.taps, s, 1);
+            } else {
+                hipLaunchKernelGGL(k_sr_forward<1>, dim3(blocks(mlr)), dim3(256), 0, st, x, op->y, lr, ov.g, ov.taps);
+                hipLaunchKernelGGL(k_sr_adjoint_step<1>, dim3(blocks(n)), dim3(256), 0, st, lr, x, v, u, z, ov.g,
+                                   ov.taps, s, 1);
+            }
+        } else {
+            hipLaunchKernelGGL(k_spi_step, dim3(blocks(n)), dim3(256), 0, st, x, v, u, z, op->ones, n, ov.q, s, 1);
+        }
+        int rc = check_hip(hipGetLastError(), "x-step");
+        if (rc) return rc;
+    }
+    return enqueue_denoise_dual(p, k, w, x, v, u, partials, res, ckpt, st);
+}
+
+// ---- standard plug-and-play ADMM with a conjugate-gradient inversion (the
+// comparator of Fig. 2).  The x-update solves (A^T A + rho I) x = A^T y +
+// rho (v - u); CG scalars live on the device (no host round trip).
+
+struct CGScalars {
+    float rr, pq, alpha, beta;
+};
+
+// fixed-order block partial of a dot product
+__device__ __forceinline__ void block_partial(float val, float* partials) {
+    __shared__ float sh[256];
+    sh[threadIdx.x] = val;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = sh[0];
+}
+
+// r = A^T y + rho (v - u) - (A^T A x + rho x) (Mx holds A^T A x); p = r
+__global__ void __launch_bounds__(256)
+k_cg_start(const float* __restrict__ aty, const float* __restrict__ Mx, const float* __restrict__ x,
+           const float* __restrict__ v, const float* __restrict__ u, float* __restrict__ r, float* __restrict__ pd,
+           float rho, int n, float* __restrict__ partials) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    float val = 0.f;
+    if (idx < n) {
+        const float ri = aty[idx] + rho * (v[idx] - u[idx]) - (Mx[idx] + rho * x[idx]);
+        r[idx] = ri;
+        pd[idx] = ri;
+        val = ri * ri;
+    }
+    block_partial(val, partials);
+}
+
+// q <- q + rho p (q held A^T A p); partial of p . q
+__global__ void __launch_bounds__(256)
+k_cg_pq(const float* __restrict__ pd, float* __restrict__ q, float rho, int n, float* __restrict__ partials) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    float val = 0.f;
+    if (idx < n) {
+        const float qi = q[idx] + rho * pd[idx];
+        q[idx] = qi;
+        val = pd[idx] * qi;
+    }
+    block_partial(val, partials);
+}
+
+// x += alpha p, r -= alpha q; partial of r . r
+__global__ void __launch_bounds__(256)
+k_cg_update(float* __restrict__ x, float* __restrict__ r, const float* __restrict__ pd, const float* __restrict__ q,
+            const CGScalars* __restrict__ sc, int n, float* __restrict__ partials) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    const float a = sc->alpha;
+    float val = 0.f;
+    if (idx < n) {
+        x[idx] += a * pd[idx];
+        const float ri = r[idx] - a * q[idx];
+        r[idx] = ri;
+        val = ri * ri;
+    }
+    block_partial(val, partials);
+}
+
+// p = r + beta p
+__global__ void __launch_bounds__(256)
+k_cg_dir(const float* __restrict__ r, float* __restrict__ pd, const CGScalars* __restrict__ sc, int n) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx < n) pd[idx] = r[idx] + sc->beta * pd[idx];
+}
+
+// which: 0 -> rr, 1 -> pq and alpha = rr / pq, 2 -> beta = rr_new / rr, rr = rr_new
+__global__ void __launch_bounds__(256) k_cg_reduce(const float* __restrict__ partials, int nblk, CGScalars* sc,
+                                                   int which) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) acc += partials[b];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const float t = (float)sh[0];
+    if (which == 0) {
+        sc->rr = t;
+    } else if (which == 1) {
+        sc->pq = t;
+        sc->alpha = t > 0.f ? sc->rr / t : 0.f;
+    } else {
+        sc->beta = sc->rr > 0.f ? t / sc->rr : 0.f;
+        sc->rr = t;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_add(const float* __restrict__ a, const float* __restrict__ b, float* __restrict__ out, int n) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx < n) out[idx] = a[idx] + b[idx];
+}
+
+// out = A^T A x (the low-resolution scratch lr holds A x)
+void enqueue_AtA(const ladmm_operator* op, const OpView& ov, const float* x, float* lr, float* out,
+                 hipStream_t st) {
+    const int n = op->n1 * op->n2, mlr = ov.g.m1 * ov.g.m2;
+    StepScalars s{};
+    if (op->boundary == 0) {
+        hipLaunchKernelGGL(k_sr_forward<0>, dim3(blocks(mlr)), dim3(256), 0, st, x, nullptr, lr, ov.g, ov.taps);
+        hipLaunchKernelGGL(k_sr_adjoint_step<0>, dim3(blocks(n)), dim3(256), 0, st, lr, out, nullptr, nullptr,
+                           nullptr, ov.g, ov.taps, s, 0);
+    } else {
+        hipLaunchKernelGGL(k_sr_forward<1>, dim3(blocks(mlr)), dim3(256), 0, st, x, nullptr, lr, ov.g, ov.taps);
+        hipLaunchKernelGGL(k_sr_adjoint_step<1>, dim3(blocks(n)), dim3(256), 0, st, lr, out, nullptr, nullptr,
+                           nullptr, ov.g, ov.taps, s, 0);
+    }
 }
 
 // Solver scratch layout inside the handle: [z: n][lr: m][partials: 2*blocks(n)]
@@ -725,3 +854,75 @@ int ladmm_operator_norm2(const ladmm_operator* op, int iters, float* out, void* 
 }
 
 }  // extern "C"
+
+extern "C" int admm_cg_solve(const ladmm_operator* op, const ladmm_params* p, int cg_iters, float* x, float* v,
+                             float* u, float* residuals, void* stream) {
+    OpView ov;
+    int rc = check_operator(op, true, "admm_cg_solve", &ov);
+    if (rc) return rc;
+    if (op->kind != LADMM_OP_SR) return fail(DSNLM_EINVAL, "admm_cg_solve: super-resolution operator only");
+    float h;
+    rc = check_params(p, op->n1, op->n2, "admm_cg_solve", &h);
+    if (rc) return rc;
+    if (cg_iters < 0) return fail(DSNLM_EINVAL, "admm_cg_solve: cg_iters must be >= 0");
+    if (!x || !v || !u) return fail(DSNLM_EINVAL, "admm_cg_solve: null pointer");
+    if (p->iters == 0) return DSNLM_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    dsnlm_weights* w = nullptr;
+    rc = prepare_handle(op->n1, op->n2, p->S, p->P, h, &w);
+    if (rc) return rc;
+    float *lr, *partials;
+    rc = ensure_solver_scratch(w, ov, op, &lr, &partials);
+    const size_t n = (size_t)op->n1 * op->n2;
+    const int nb = blocks(n);
+    // CG vectors: A^T y, r, p, q (n each) and the device scalars
+    float* cgbuf = nullptr;
+    if (!rc) rc = check_hip(hipMalloc(&cgbuf, (4 * n + 64) * sizeof(float)), "admm_cg_solve scratch");
+    if (rc) {
+        dsnlm_weights_destroy(w);
+        return rc;
+    }
+    float* aty = cgbuf;
+    float* r = aty + n;
+    float* pd = r + n;
+    float* q = pd + n;
+    CGScalars* sc = reinterpret_cast<CGScalars*>(q + n);
+    {
+        ProfScope prof(DSNLM_K_LADMM, st);
+        StepScalars s{};
+        if (op->boundary == 0) {
+            hipLaunchKernelGGL(k_sr_adjoint_step<0>, dim3(nb), dim3(256), 0, st, op->y, aty, nullptr, nullptr,
+                               nullptr, ov.g, ov.taps, s, 0);
+        } else {
+            hipLaunchKernelGGL(k_sr_adjoint_step<1>, dim3(nb), dim3(256), 0, st, op->y, aty, nullptr, nullptr,
+                               nullptr, ov.g, ov.taps, s, 0);
+        }
+        rc = check_hip(hipGetLastError(), "A^T y");
+    }
+    for (int k = 1; k <= p->iters && !rc; ++k) {
+        {
+            ProfScope prof(DSNLM_K_LADMM, st);
+            enqueue_AtA(op, ov, x, lr, q, st);
+            hipLaunchKernelGGL(k_cg_start, dim3(nb), dim3(256), 0, st, aty, q, x, v, u, r, pd, p->rho, (int)n,
+                               partials);
+            hipLaunchKernelGGL(k_cg_reduce, dim3(1), dim3(256), 0, st, partials, nb, sc, 0);
+            for (int it = 0; it < cg_iters; ++it) {
+                enqueue_AtA(op, ov, pd, lr, q, st);
+                hipLaunchKernelGGL(k_cg_pq, dim3(nb), dim3(256), 0, st, pd, q, p->rho, (int)n, partials);
+                hipLaunchKernelGGL(k_cg_reduce, dim3(1), dim3(256), 0, st, partials, nb, sc, 1);
+                hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(256), 0, st, x, r, pd, q, sc, (int)n, partials);
+                hipLaunchKernelGGL(k_cg_reduce, dim3(1), dim3(256), 0, st, partials, nb, sc, 2);
+                hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(256), 0, st, r, pd, sc, (int)n);
+            }
+            hipLaunchKernelGGL(k_add, dim3(nb), dim3(256), 0, st, x, u, w->zbuf, (int)n);
+            rc = check_hip(hipGetLastError(), "conjugate gradients");
+        }
+        if (!rc)
+            rc = enqueue_denoise_dual(p, k, w, x, v, u, partials,
+                                      residuals ? residuals + 2 * (size_t)(k - 1) : nullptr, nullptr, st);
+    }
+    if (!rc) rc = check_hip(hipStreamSynchronize(st), "admm_cg_solve synchronise");
+    (void)hipFree(cgbuf);
+    dsnlm_weights_destroy(w);
+    return rc;
+}

@@ -233,3 +233,29 @@ def test_full_config_sr_solve_properties():
     err0 = float(np.sqrt(np.mean((x0 - cfg["clean"]) ** 2)))
     err = float(torch.sqrt(torch.mean((x - xc) ** 2)))
     assert err < err0
+
+
+@pytest.mark.parametrize("k0,steps", [(1, 3), (2, 4)])
+def test_standard_admm_cg_matches_oracle(k0, steps):
+    """Standard ADMM (CG inversion, 8 CG steps) from the same start: every
+    iterate against the FP64 oracle run for the same number of outer steps."""
+    M = _M()
+    n, S, P, cg = 32, 3, 1, 8
+    clean, y, x0 = _sr_problem(n, 41, S, P)
+    lam, rho = np.float32(1e-2), np.float32(1.0)
+    h = float(np.float32(math.sqrt(lam / rho)))
+    taps32 = TAPS.astype(np.float32)
+    op = _sr_op(M, n, n, y=_t(y))
+    prm = M.LadmmParams(lam=float(lam), rho=float(rho), gamma=1.0, S=S, P=P, freeze_after=k0, iters=steps)
+    x, v, u = _t(x0), _t(x0), torch.zeros((n, n), device="cuda")
+    res = torch.zeros((steps, 2), device="cuda")
+    M.admm_cg_solve(op, prm, cg, x, v, u, residuals=res)
+    out = L.admm_cg(x0, y, taps32, 2, rho=float(rho), S=S, P=P, h=h, iters=steps, freeze_after=k0,
+                    cg_iters=cg, v0=x0, u0=np.zeros_like(x0))
+    tol = 1e-4 * steps
+    assert np.abs(x.cpu().numpy() - out["x"]).max() <= tol
+    assert np.abs(v.cpu().numpy() - out["v"]).max() <= tol
+    assert np.abs(u.cpu().numpy() - out["u"]).max() <= tol
+    r = res.cpu().numpy()
+    assert np.all(np.isfinite(r))
+    assert np.abs(r[-1] - out["residuals"][-1]).max() <= 1e-4
