@@ -67,7 +67,10 @@ struct BwdArgs {
 __device__ __forceinline__ void write_sweep_d_factors(const BwdArgs& a, int idx, float obar, float cc,
                                                       float bb, float xv, float f) {
     if (a.aux4) {
-        reinterpret_cast<float4*>(a.aux5)[kAux4Lead + idx] = make_float4(obar, cc, bb, xv);
+        // column-major: sweep D's lanes walk down rows, so a wave's partner
+        // loads read consecutive entries
+        const int i = idx / a.n2, j = idx - i * a.n2;
+        reinterpret_cast<float4*>(a.aux5)[kAux4Lead + (size_t)j * a.n1 + i] = make_float4(obar, cc, bb, xv);
     } else {
         float* o = a.aux5 + 5 * (size_t)idx;
         o[0] = obar;
@@ -614,6 +617,8 @@ int enqueue_backward(dsnlm_weights* w, const float* x, const float* dy, float* d
     a.cw = cw;
     a.aux5 = aux5;
     a.aux4 = S <= 12;
+    a.n1 = n1;
+    a.n2 = n2;
     a.dx = dx;
     a.partials = partials;
     a.mbar = mbar;

@@ -239,7 +239,7 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
     float mb = 0.f;                 // mbar, routed to the argmax pixel s*
     int si = -1, sj = -1;           // s*
     bool fnear = false;             // can a pair of this tile touch s*?
-    int roff = 0;                   // byte offset of this thread's run at shift 0
+    int roff[LD];                   // byte offsets of this thread's partners at shift 0
     const float4* rbase = nullptr;  // buffer base and size (bytes) for the partner reads
     int rbytes = 0;
     if constexpr (MODE == kPassD) {
@@ -250,18 +250,21 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
         sj = sstar - si * n2;
         mb = *d.mbar;
         fnear = si >= ti0 - S && si < ti0 + TH + S && sj >= tj0 - S && sj < tj0 + TW + S;
-        const int row0 = ti0 - S > 0 ? ti0 - S : 0;
+        // the factors are stored column-major (entry j n1 + i); the buffer
+        // starts at the first column this tile's partners can reach
+        const int col0 = tj0 - S > 0 ? tj0 - S : 0;
         const float4* img4 = reinterpret_cast<const float4*>(d.aux5) + kAux4Lead;
-        rbase = img4 + (size_t)row0 * n2 - kAux4Lead;
-        const size_t recs = ((size_t)(n1 - row0) * n2 + kAux4Lead + kAux4Trail) * 16;
+        rbase = img4 + (size_t)col0 * n1 - kAux4Lead;
+        const size_t recs = ((size_t)(n2 - col0) * n1 + kAux4Lead + kAux4Trail) * 16;
         rbytes = (int)(recs < 0x7ffffff0u ? recs : 0x7ffffff0u);
-        roff = ((gi_own - row0) * n2 + gj_own + kAux4Lead) * 16;
+#pragma unroll
+        for (int k = 0; k < L; ++k) roff[k] = ((gj_own + k - col0) * n1 + gi_own + kAux4Lead) * 16;
 #pragma unroll
         for (int k = 0; k < L; ++k) {
             zown[k] = Zs[(pj + k + S + P) * ZC + pi + S + P];
             const int gj = gj_own + k;
             const bool in = (unsigned)gi_own < (unsigned)n1 && (unsigned)gj < (unsigned)n2;
-            const float4 o = in ? img4[(size_t)gi_own * n2 + gj] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float4 o = in ? img4[(size_t)gj * n1 + gi_own] : make_float4(0.f, 0.f, 0.f, 0.f);
             ow[k] = nk * o.x;
             oc[k] = nk * o.y;
             ob[k] = o.z;
@@ -329,13 +332,13 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
     };
     auto loadr = [&](int dy, int dx) {
         if constexpr (MODE == kPassD) {
-            const int o = roff + (dy * n2 + dx) * 16;
+            const int o = (dx * n1 + dy) * 16;
             // keep these loads at this point of the schedule: hoisting them
             // into earlier shifts only raises register pressure
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int k = 0; k < L; ++k)
-                rv[k] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, o + 16 * k, 0, 0));
+                rv[k] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, roff[k] + o, 0, 0));
             __builtin_amdgcn_sched_barrier(0);
         } else {
             (void)dy;
