@@ -64,23 +64,6 @@ struct BwdArgs {
     float h;
 };
 
-__device__ __forceinline__ void write_sweep_d_factors(const BwdArgs& a, int idx, float obar, float cc,
-                                                      float bb, float xv, float f) {
-    if (a.aux4) {
-        // column-major: sweep D's lanes walk down rows, so a wave's partner
-        // loads read consecutive entries
-        const int i = idx / a.n2, j = idx - i * a.n2;
-        reinterpret_cast<float4*>(a.aux5)[kAux4Lead + (size_t)j * a.n1 + i] = make_float4(obar, cc, bb, xv);
-    } else {
-        float* o = a.aux5 + 5 * (size_t)idx;
-        o[0] = obar;
-        o[1] = cc * bb;
-        o[2] = cc * (f - xv * bb);
-        o[3] = cc;
-        o[4] = cc * xv;
-    }
-}
-
 // B'bar, the (t, w) pairs, and per-block sums of ybar B'.
 __global__ void __launch_bounds__(256) k_bwd_prep(BwdArgs a) {
     const int idx = blockIdx.x * 256 + threadIdx.x;
@@ -125,26 +108,52 @@ __global__ void __launch_bounds__(256) k_bwd_mbar(BwdArgs a, int nblk) {
     }
 }
 
-// xbar, cbar and the per-pixel factors of sweep D.
-__global__ void __launch_bounds__(256) k_bwd_mid(BwdArgs a) {
-    const int idx = blockIdx.x * 256 + threadIdx.x;
-    if (idx >= a.n) return;
-    const unsigned long long key = *a.key;
-    const float m = __uint_as_float((unsigned)(key >> 32));
-    const int sstar = (int)(~(unsigned)(key & 0xffffffffu));
-    const float f = idx == sstar ? *a.mbar : 0.f;
-    const float yb = a.dy[idx];
-    const float bb = yb / m;
-    const float cc = a.c[idx];
-    const float dl = a.delta[idx];
-    const float xv = a.x[idx];
-    const float U = a.cw[2 * idx];
-    const float Wc = a.cw[2 * idx + 1];
-    if (a.dx) a.dx[idx] = yb - dl * bb + cc * U;
-    const float cbar = bb * a.bp[idx] / cc + f * dl / cc + xv * U + Wc;
-    const float obar = -0.5f * cbar * cc * cc * cc;
-    write_sweep_d_factors(a, idx, obar, cc, bb, xv, f);
+// xbar, cbar and the per-pixel factors of sweep D for a 16 x 16 tile (256
+// threads).  The float4 factors are written column-major through an LDS
+// transpose, so both the row-major reads and the column-major writes of a
+// wave are contiguous.
+__device__ __forceinline__ void mid_tile(const BwdArgs& a, int i0, int j0) {
+    __shared__ float4 tile[16][17];
+    const int n1 = a.n1, n2 = a.n2;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int i = i0 + ty, j = j0 + tx;
+    float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (i < n1 && j < n2) {
+        const int idx = i * n2 + j;
+        const unsigned long long key = *a.key;
+        const float m = __uint_as_float((unsigned)(key >> 32));
+        const int sstar = (int)(~(unsigned)(key & 0xffffffffu));
+        const float f = idx == sstar ? *a.mbar : 0.f;
+        const float yb = a.dy[idx];
+        const float bb = yb / m;
+        const float cc = a.c[idx];
+        const float dl = a.delta[idx];
+        const float xv = a.x[idx];
+        const float U = a.cw[2 * idx];
+        const float Wc = a.cw[2 * idx + 1];
+        if (a.dx) a.dx[idx] = yb - dl * bb + cc * U;
+        const float cbar = bb * a.bp[idx] / cc + f * dl / cc + xv * U + Wc;
+        const float obar = -0.5f * cbar * cc * cc * cc;
+        if (a.aux4) {
+            val = make_float4(obar, cc, bb, xv);
+        } else {
+            float* o = a.aux5 + 5 * (size_t)idx;
+            o[0] = obar;
+            o[1] = cc * bb;
+            o[2] = cc * (f - xv * bb);
+            o[3] = cc;
+            o[4] = cc * xv;
+        }
+    }
+    if (!a.aux4) return;  // uniform per launch
+    tile[tx][ty] = val;
+    __syncthreads();
+    const int wc = threadIdx.x >> 4, wr = threadIdx.x & 15;  // lanes walk down a column
+    const int gi = i0 + wr, gj = j0 + wc;
+    if (gi < n1 && gj < n2) reinterpret_cast<float4*>(a.aux5)[kAux4Lead + (size_t)gj * n1 + gi] = tile[wc][wr];
 }
+
+__global__ void __launch_bounds__(256) k_bwd_mid(BwdArgs a) { mid_tile(a, blockIdx.y * 16, blockIdx.x * 16); }
 
 
 // ---- segmented forms for a batch: block b of the grid works on image
@@ -197,26 +206,14 @@ __global__ void __launch_bounds__(256) k_bwd_mbar_seg(const BwdArgs* __restrict_
     }
 }
 
+// tmap[b] = (image, 16 x 16 tile index in row-major tile order)
 __global__ void __launch_bounds__(256) k_bwd_mid_seg(const BwdArgs* __restrict__ imgs,
-                                                     const int2* __restrict__ map) {
-    const int2 mb = map[blockIdx.x];
+                                                     const int2* __restrict__ tmap) {
+    const int2 mb = tmap[blockIdx.x];
     const BwdArgs a = imgs[mb.x];
-    const int idx = mb.y * 256 + threadIdx.x;
-    if (idx >= a.n) return;
-    const unsigned long long key = *a.key;
-    const float m = __uint_as_float((unsigned)(key >> 32));
-    const int sstar = (int)(~(unsigned)(key & 0xffffffffu));
-    const float f = idx == sstar ? *a.mbar : 0.f;
-    const float yb = a.dy[idx];
-    const float bb = yb / m;
-    const float cc = a.c[idx];
-    const float dl = a.delta[idx];
-    const float xv = a.x[idx];
-    const float U = a.cw[2 * idx];
-    const float Wc = a.cw[2 * idx + 1];
-    if (a.dx) a.dx[idx] = yb - dl * bb + cc * U;
-    const float cbar = bb * a.bp[idx] / cc + f * dl / cc + xv * U + Wc;
-    write_sweep_d_factors(a, idx, -0.5f * cbar * cc * cc * cc, cc, bb, xv, f);
+    const int ntx = (a.n2 + 15) / 16;
+    const int ti = mb.y / ntx, tj = mb.y - ti * ntx;
+    mid_tile(a, ti * 16, tj * 16);
 }
 
 __global__ void __launch_bounds__(256) k_fold_seg(const BwdArgs* __restrict__ imgs, const int2* __restrict__ map) {
@@ -638,7 +635,7 @@ int enqueue_backward(dsnlm_weights* w, const float* x, const float* dy, float* d
     if (rc) return rc;
     {
         ProfScope prof(DSNLM_K_BWD_PREP, st);
-        hipLaunchKernelGGL(k_bwd_mid, dim3(nb), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_bwd_mid, dim3((n2 + 15) / 16, (n1 + 15) / 16), dim3(256), 0, st, a);
         rc = check_hip(hipGetLastError(), "backward mid");
         if (rc) return rc;
     }
@@ -692,6 +689,9 @@ struct BwdBatchWs {
     size_t map_cap = 0;
     TileRef* dtiles = nullptr;
     size_t dtiles_cap = 0;
+    int2* tmap = nullptr;
+    size_t tmap_cap = 0;
+    std::vector<int2> h_tmap;
     std::vector<BwdArgs> h_args;
     std::vector<ImgDesc> h_descs;
     std::vector<int2> h_map;
@@ -751,7 +751,7 @@ int enqueue_backward_batch(const BwdImage* ims, int count, int S, int P, const T
     if (rc) return rc;
     std::vector<BwdArgs> args(count);
     std::vector<ImgDesc> descs(count);
-    std::vector<int2> map;
+    std::vector<int2> map, tmap;
     std::vector<TileRef> dtiles;
     for (int k = 0; k < count; ++k) {
         const ImgDesc& f = *ims[k].fwd;
@@ -794,16 +794,20 @@ int enqueue_backward_batch(const BwdImage* ims, int count, int S, int P, const T
         d.tile_base = (int)dtiles.size();
         descs[k] = d;
         for (int b2 = 0; b2 < nb[k]; ++b2) map.push_back(make_int2(k, b2));
+        const int nt16 = ((f.n1 + 15) / 16) * ((f.n2 + 15) / 16);
+        for (int t = 0; t < nt16; ++t) tmap.push_back(make_int2(k, t));
         const int tyn = (f.n1 + 2 * P + CHn - 1) / CHn, txn = (f.n2 + 2 * P + CWn - 1) / CWn;
         for (int ty = 0; ty < tyn; ++ty)
             for (int tx = 0; tx < txn; ++tx) dtiles.push_back(TileRef{k, ty * CHn - 2 * P, tx * CWn - 2 * P, 0});
     }
     rc = check_hip(grow_b(&g_bws.map, &g_bws.map_cap, map.size()), "batched backward map");
     if (!rc) rc = check_hip(grow_b(&g_bws.dtiles, &g_bws.dtiles_cap, dtiles.size()), "batched backward tiles");
+    if (!rc) rc = check_hip(grow_b(&g_bws.tmap, &g_bws.tmap_cap, tmap.size()), "batched backward tile map");
     if (!rc) rc = upload_if_changed(g_bws.args, g_bws.h_args, args, st, "upload backward args");
     if (!rc) rc = upload_if_changed(g_bws.descs, g_bws.h_descs, descs, st, "upload backward descriptors");
     if (!rc) rc = upload_if_changed(g_bws.map, g_bws.h_map, map, st, "upload backward map");
     if (!rc) rc = upload_if_changed(g_bws.dtiles, g_bws.h_dtiles, dtiles, st, "upload backward tiles");
+    if (!rc) rc = upload_if_changed(g_bws.tmap, g_bws.h_tmap, tmap, st, "upload backward tile map");
     if (rc) return rc;
     const int nmap = (int)map.size();
     {
@@ -819,7 +823,7 @@ int enqueue_backward_batch(const BwdImage* ims, int count, int S, int P, const T
     if (rc) return rc;
     {
         ProfScope prof(DSNLM_K_BWD_PREP, st);
-        hipLaunchKernelGGL(k_bwd_mid_seg, dim3(nmap), dim3(256), 0, st, g_bws.args, g_bws.map);
+        hipLaunchKernelGGL(k_bwd_mid_seg, dim3((unsigned)tmap.size()), dim3(256), 0, st, g_bws.args, g_bws.tmap);
         rc = check_hip(hipGetLastError(), "batched backward mid");
         if (rc) return rc;
     }
