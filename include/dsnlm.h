@@ -144,7 +144,8 @@ int dsnlm_forward_batched(const dsnlm_image* imgs, int count, int S, int P, void
  * images, same order; its inputs must be unchanged): per image, dy is the
  * cotangent of y and dx = W dy, dguide, dh (device scalar) are written; each
  * output may be NULL.  One launch per backward sweep for the whole batch.
- * Guide and bandwidth gradients need S <= 12 here. */
+ * Guide and bandwidth gradients cover every supported S (LDS permitting:
+ * DSNLM_EUNSUPPORTED otherwise). */
 typedef struct {
     const float* dy;
     float* dx;

@@ -174,10 +174,10 @@ extern "C" int dsnlm_backward_batched(const dsnlm_image_grad* grads, int count, 
         return fail(DSNLM_EINVAL, "dsnlm_backward_batched: count differs from the last dsnlm_forward_batched");
     if (count == 0) return DSNLM_OK;
     const int S = g_ws.last_S, P = g_ws.last_P;
-    if (S > 12 && (count > 0))
+    if (!sweep_d2_fits(S, P))
         for (int k = 0; k < count; ++k)
             if (grads[k].dguide || grads[k].dh)
-                return fail(DSNLM_EUNSUPPORTED, "dsnlm_backward_batched: guide/bandwidth gradients need S <= 12");
+                return fail(DSNLM_EUNSUPPORTED, "dsnlm_backward_batched: guide/bandwidth gradients need S <= 24");
     std::vector<BwdImage> ims(count);
     for (int k = 0; k < count; ++k) {
         const ImgDesc& f = g_ws.last_descs[k];

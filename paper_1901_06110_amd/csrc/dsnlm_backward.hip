@@ -18,8 +18,8 @@
 //   hbar = -(1/h) sum_{s,d} Dbar_{s,d} D_{s,d}
 //   zbar(p) = 2 sum_d (z(p) - z(p+d)) sum_{|s-p| <= P} Dbar_{s,d}  (padded grid)
 //   dguide = fold of zbar through the mirror padding.
-// Sweep D recomputes D_{s,d} for an s-tile, forms Dbar_{s,d} in LDS, box-sums
-// it over the patch, and accumulates zbar for the s-tile's core pixels.
+// Sweep D (dsnlm_sweep_d.hip) recomputes D_{s,d} on the forward's tiles,
+// forms Dbar_{s,d} in LDS, box-sums it over the patch and scatters zbar.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -48,13 +48,12 @@ struct BwdArgs {
     const unsigned long long* key;  // (m, s*)
     float* pairs;        // [2n] t, w  (input of sweep C)
     float* cw;           // [2n] U, Wc (output of sweep C)
-    float* aux5;         // sweep-D factors: [5n] omegabar, beta, gamma, c, c x (aux4 == 0)
-                         // or padded float4 (omegabar, c, B'bar, x) (aux4 == 1)
+    float* aux5;         // sweep-D factors: float4 (omegabar, c, B'bar, x) per pixel,
+                         // column-major after a lead pad of kAux4Lead entries
     float* dx;           // W ybar (nullable)
     float* partials;     // per-block partial sums
     float* mbar;         // device scalar
     int n;
-    int aux4;
     // batched form only
     float* gz;           // padded-grid guide gradient
     float* dguide;       // guide gradient (nullable)
@@ -134,18 +133,8 @@ __device__ __forceinline__ void mid_tile(const BwdArgs& a, int i0, int j0) {
         if (a.dx) a.dx[idx] = yb - dl * bb + cc * U;
         const float cbar = bb * a.bp[idx] / cc + f * dl / cc + xv * U + Wc;
         const float obar = -0.5f * cbar * cc * cc * cc;
-        if (a.aux4) {
-            val = make_float4(obar, cc, bb, xv);
-        } else {
-            float* o = a.aux5 + 5 * (size_t)idx;
-            o[0] = obar;
-            o[1] = cc * bb;
-            o[2] = cc * (f - xv * bb);
-            o[3] = cc;
-            o[4] = cc * xv;
-        }
+        val = make_float4(obar, cc, bb, xv);
     }
-    if (!a.aux4) return;  // uniform per launch
     tile[tx][ty] = val;
     __syncthreads();
     const int wc = threadIdx.x >> 4, wr = threadIdx.x & 15;  // lanes walk down a column
@@ -254,244 +243,6 @@ __global__ void __launch_bounds__(256) k_dh_seg(const BwdArgs* __restrict__ imgs
     if (threadIdx.x == 0) *a.dh = (float)(-sh[0] / a.h);
 }
 
-// ---- sweep D -----------------------------------------------------------
-// s-tile 32 x 32 (128 threads), core = the s-tile minus P on each side; the
-// cores tile the padded grid [-P, n+P)^2.
-template <int P, int S_CLASS>
-struct GeoD {
-    static constexpr int TH = 32, TW = 32;
-    static constexpr int R = 8, L = 8;
-    static constexpr int NT = TH * (TW / L);  // 128
-    static constexpr int TWE = TW + 2 * P;
-    static constexpr int NITEM1 = TWE * (TH / R);
-    static constexpr int ROUNDS1 = (NITEM1 + NT - 1) / NT;
-    static constexpr int CH = TH - 2 * P, CW = TW - 2 * P;  // core
-    static constexpr int ZW = TW + 2 * (S_CLASS + P);
-    static constexpr int AW = TW + 2 * S_CLASS + 1;          // aux5 row stride (pixels)
-    static constexpr int VW0 = ((TWE + 3) / 4) * 4;
-    static constexpr int VW = ((VW0 / 4) % 2) ? VW0 : VW0 + 4;
-    static constexpr int BW = TW + 2 * P + 1;                // Dbar / its vertical sums
-};
-
-template <int P, int S_CLASS>
-size_t lds_floats_d(int S) {
-    using G = GeoD<P, S_CLASS>;
-    const size_t ZH = G::TH + 2 * (S + P);
-    const size_t AH = G::TH + 2 * S;
-    size_t n = (ZH * G::ZW + 3) & ~(size_t)3;
-    n += (AH * G::AW * 5 + 3) & ~(size_t)3;
-    n += (size_t)2 * G::TH * G::VW;          // V (double buffer)
-    n += (size_t)G::TH * G::BW;              // Dbar
-    n += (size_t)G::TH * G::BW;              // vertical sums of Dbar
-    return n;
-}
-
-struct DArgs {
-    const float* z;      // guide
-    const float* aux5;   // [5n]
-    float* gz;           // padded-grid gradient (n1 + 2P) x (n2 + 2P)
-    float* hpart;        // per-block partial of sum Dbar D
-    int n1, n2;
-    float beta;          // log2(e) kappa
-    float kappa;
-    int tiles_x;         // core tiles along columns
-};
-
-template <int P, int S_CLASS>
-__global__ void __launch_bounds__(128) k_sweep_d(DArgs A, int S, HatTable hat) {
-    using G = GeoD<P, S_CLASS>;
-    constexpr int NT = G::NT, TH = G::TH, TW = G::TW, R = G::R, L = G::L;
-    constexpr int ZW = G::ZW, AW = G::AW, VW = G::VW, BW = G::BW;
-    constexpr int NE = R + 2 * P;
-    extern __shared__ __align__(16) float lds[];
-    const int tid = threadIdx.x;
-    const int n1 = A.n1, n2 = A.n2;
-    // core origin on the padded grid and the s-tile origin (image coordinates)
-    const int cti = blockIdx.x / A.tiles_x, ctj = blockIdx.x - cti * A.tiles_x;
-    const int ti0 = -P + cti * G::CH - P;  // s-tile row origin
-    const int tj0 = -P + ctj * G::CW - P;
-    const int ZH = TH + 2 * (S + P), ZWr = TW + 2 * (S + P);
-    const int AH = TH + 2 * S, AWr = TW + 2 * S;
-    float* Zs = lds;
-    int off = (ZH * ZW + 3) & ~3;
-    float* Aux = lds + off;
-    off += (AH * AW * 5 + 3) & ~3;
-    float* Vb = lds + off;
-    off += 2 * TH * VW;
-    float* Db = lds + off;
-    off += TH * BW;
-    float* VDb = lds + off;
-
-    for (int idx = tid; idx < ZH * ZWr; idx += NT) {
-        const int r = idx / ZWr, q = idx - r * ZWr;
-        const int gi = reflect_clamp_b(ti0 - S - P + r, n1);
-        const int gj = reflect_clamp_b(tj0 - S - P + q, n2);
-        Zs[r * ZW + q] = A.z[(size_t)gi * n2 + gj];
-    }
-    for (int idx = tid; idx < AH * AWr; idx += NT) {
-        const int r = idx / AWr, q = idx - r * AWr;
-        const int gi = ti0 - S + r, gj = tj0 - S + q;
-        const bool in = (unsigned)gi < (unsigned)n1 && (unsigned)gj < (unsigned)n2;
-        float* dst = Aux + 5 * (r * AW + q);
-        const float* src = A.aux5 + 5 * ((size_t)gi * n2 + gj);
-#pragma unroll
-        for (int k = 0; k < 5; ++k) dst[k] = in ? src[k] : 0.f;
-    }
-    // zero the padding column of Dbar (read by the horizontal box sums)
-    for (int idx = tid; idx < TH * BW; idx += NT) {
-        Db[idx] = 0.f;
-        VDb[idx] = 0.f;
-    }
-    __syncthreads();
-
-    // phase-1 reference columns (registers)
-    float ref[G::ROUNDS1][NE];
-    int zoff[G::ROUNDS1], voff[G::ROUNDS1];
-#pragma unroll
-    for (int k1 = 0; k1 < G::ROUNDS1; ++k1) {
-        int it = tid + k1 * NT;
-        it = it < G::NITEM1 ? it : G::NITEM1 - 1;
-        const int strip = it / G::TWE;
-        const int c = it - strip * G::TWE;
-        zoff[k1] = (strip * R + S) * ZW + c + S;
-        voff[k1] = strip * R * VW + c;
-#pragma unroll
-        for (int q = 0; q < NE; ++q) ref[k1][q] = Zs[zoff[k1] + q * ZW];
-    }
-
-    const int pi = tid % TH;
-    const int pj = (tid / TH) * L;
-    const int gi = ti0 + pi;
-    // own per-pixel factors (zero outside the image)
-    float own[L][5];
-    bool sin[L], core[L];
-    float zown[L];
-#pragma unroll
-    for (int k = 0; k < L; ++k) {
-        const float* src = Aux + 5 * ((pi + S) * AW + pj + k + S);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) own[k][q] = src[q];
-        const int gj = tj0 + pj + k;
-        sin[k] = (unsigned)gi < (unsigned)n1 && (unsigned)gj < (unsigned)n2;
-        core[k] = pi >= P && pi < TH - P && pj + k >= P && pj + k < TW - P;
-        zown[k] = Zs[(pi + S + P) * ZW + pj + k + S + P];
-    }
-    float accz[L];
-#pragma unroll
-    for (int k = 0; k < L; ++k) accz[k] = 0.f;
-    float hacc = 0.f;
-    const float beta = A.beta, kappa = A.kappa;
-
-    int buf = 0;
-    for (int dy = -S; dy <= S; ++dy) {
-        for (int dx = -S; dx <= S; ++dx) {
-            const float lg = hat.lg[dy + S] + hat.lg[dx + S];
-            float* V = Vb + buf * (TH * VW);
-            const int sh = dy * ZW + dx;
-            // phase 1: vertical box sums of e_d over the s-tile (+P columns)
-#pragma unroll
-            for (int k1 = 0; k1 < G::ROUNDS1; ++k1) {
-                if (tid + k1 * NT < G::NITEM1) {
-                    const float* zq = Zs + zoff[k1] + sh;
-                    float tq[NE];
-#pragma unroll
-                    for (int q = 0; q < NE; ++q) tq[q] = ref[k1][q] - zq[q * ZW];
-                    float v = 0.f;
-#pragma unroll
-                    for (int q = 0; q <= 2 * P; ++q) v = fmaf(tq[q], tq[q], v);
-                    float* vo = V + voff[k1];
-                    vo[0] = v;
-#pragma unroll
-                    for (int q = 1; q < R; ++q) {
-                        v = fmaf(tq[q + 2 * P], tq[q + 2 * P], v);
-                        v = fmaf(-tq[q - 1], tq[q - 1], v);
-                        vo[q * VW] = v;
-                    }
-                }
-            }
-            __syncthreads();
-            // phase 2: D, a, Dbar (both orders of the pair) -> LDS
-            {
-                const float* vr = V + pi * VW + pj;
-                constexpr int NV = ((L + 2 * P + 3) / 4) * 4;
-                float vv[NV];
-#pragma unroll
-                for (int q = 0; q < NV / 4; ++q) {
-                    const float4 t4 = reinterpret_cast<const float4*>(vr)[q];
-                    vv[4 * q + 0] = t4.x;
-                    vv[4 * q + 1] = t4.y;
-                    vv[4 * q + 2] = t4.z;
-                    vv[4 * q + 3] = t4.w;
-                }
-                float hs = 0.f;
-#pragma unroll
-                for (int q = 0; q <= 2 * P; ++q) hs += vv[q];
-                const bool rowok = (unsigned)(gi + dy) < (unsigned)n1;
-                const float* nb = Aux + 5 * ((pi + dy + S) * AW + pj + dx + S);
-#pragma unroll
-                for (int k = 0; k < L; ++k) {
-                    if (k > 0) hs += vv[k + 2 * P] - vv[k - 1];
-                    const float D = hs;
-                    const float a = __builtin_amdgcn_exp2f(lg - beta * D);
-                    const float* r5 = nb + 5 * k;
-                    // abar_{s,d} + abar_{s+d,-d}
-                    float as = own[k][0] + r5[0];
-                    as = fmaf(own[k][1], r5[4], as);
-                    as = fmaf(own[k][2], r5[3], as);
-                    as = fmaf(r5[1], own[k][4], as);
-                    as = fmaf(r5[2], own[k][3], as);
-                    const bool ok = sin[k] && rowok && (unsigned)(tj0 + pj + k + dx) < (unsigned)n2;
-                    const float db = ok ? -kappa * a * as : 0.f;
-                    if (core[k]) hacc = fmaf(db, D, hacc);
-                    Db[pi * BW + pj + k + P] = db;
-                }
-            }
-            __syncthreads();
-            // phase 3: vertical box sums of Dbar for the core rows
-            for (int idx = tid; idx < G::CH * TW; idx += NT) {
-                const int r = P + idx / TW, c = idx - (idx / TW) * TW;
-                float v = 0.f;
-#pragma unroll
-                for (int t = -P; t <= P; ++t) v += Db[(r + t) * BW + c + P];
-                VDb[r * BW + c + P] = v;
-            }
-            __syncthreads();
-            // phase 4: horizontal box sums -> G, accumulate zbar on the core
-            {
-                const float* vr = VDb + pi * BW + pj;  // column pj + k - P + P
-                float hs = 0.f;
-#pragma unroll
-                for (int q = 0; q <= 2 * P; ++q) hs += vr[q];
-                const float* zq = Zs + (pi + S + P + dy) * ZW + pj + S + P + dx;
-#pragma unroll
-                for (int k = 0; k < L; ++k) {
-                    if (k > 0) hs += vr[k + 2 * P] - vr[k - 1];
-                    accz[k] = fmaf(2.f * (zown[k] - zq[k]), hs, accz[k]);
-                }
-            }
-            buf ^= 1;
-        }
-    }
-    // write zbar on the core (padded-grid coordinates, offset by P)
-    const int W2 = n2 + 2 * P;
-#pragma unroll
-    for (int k = 0; k < L; ++k) {
-        const int gj = tj0 + pj + k;
-        if (core[k] && gi >= -P && gi < n1 + P && gj >= -P && gj < n2 + P)
-            A.gz[(size_t)(gi + P) * W2 + gj + P] = accz[k];
-    }
-    // block partial of sum Dbar D (fixed order: LDS tree in the V buffer,
-    // whose last reads were in phase 2, two barriers ago)
-    float* red = Vb;
-    red[tid] = hacc;
-    __syncthreads();
-    for (int w = NT / 2; w > 0; w >>= 1) {
-        if (tid < w) red[tid] += red[tid + w];
-        __syncthreads();
-    }
-    if (tid == 0) A.hpart[blockIdx.x] = red[0];
-}
-
 // dguide(q) = sum of zbar over the padded positions that mirror onto q.
 __global__ void __launch_bounds__(256) k_fold(const float* __restrict__ gz, float* __restrict__ dz, int n1,
                                               int n2, int P) {
@@ -528,52 +279,9 @@ __global__ void __launch_bounds__(256) k_dh(const float* __restrict__ hpart, int
     if (threadIdx.x == 0) *dh = (float)(-sh[0] / h);
 }
 
-template <int P, int S_CLASS>
-hipError_t launch_d(const DArgs& a, int S, int nblk, hipStream_t st) {
-    auto kern = k_sweep_d<P, S_CLASS>;
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           160 * 1024);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
-    const size_t lds = lds_floats_d<P, S_CLASS>(S) * sizeof(float);
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
-    HatTable hat = make_hat(S);
-    hipLaunchKernelGGL(kern, dim3(nblk), dim3(GeoD<P, S_CLASS>::NT), lds, st, a, S, hat);
-    return hipGetLastError();
-}
-
-template <int P>
-hipError_t launch_d_s(const DArgs& a, int S, int nblk, hipStream_t st) {
-    if (S <= 12) return launch_d<P, 12>(a, S, nblk, st);
-    return launch_d<P, kMaxS>(a, S, nblk, st);
-}
-
-hipError_t launch_sweep_d(const DArgs& a, int S, int P, int nblk, hipStream_t st) {
-    switch (P) {
-        case 0: return launch_d_s<0>(a, S, nblk, st);
-        case 1: return launch_d_s<1>(a, S, nblk, st);
-        case 2: return launch_d_s<2>(a, S, nblk, st);
-        case 3: return launch_d_s<3>(a, S, nblk, st);
-        case 4: return launch_d_s<4>(a, S, nblk, st);
-        case 5: return launch_d_s<5>(a, S, nblk, st);
-        default: return hipErrorInvalidValue;
-    }
-}
-
 inline int blocks256(size_t n) { return (int)((n + 255) / 256); }
 
 }  // namespace
-
-size_t sweep_d_lds_bytes(int S, int P) {
-    const int SC = S <= 12 ? 12 : kMaxS;
-    const size_t TH = 32, TW = 32;
-    const size_t ZW = TW + 2 * (SC + P), AW = TW + 2 * SC + 1, VW = TW + 2 * P + 8, BW = TW + 2 * P + 1;
-    const size_t n = (TH + 2 * (S + P)) * ZW + (TH + 2 * S) * AW * 5 + 2 * TH * VW + 2 * TH * BW + 16;
-    return n * sizeof(float);
-}
 
 ImgDesc base_desc(const dsnlm_weights* w);
 bool overlaps(const void* a, const void* b, size_t bytes);
@@ -581,10 +289,9 @@ bool overlaps(const void* a, const void* b, size_t bytes);
 // Scratch (floats) needed by dsnlm_apply_backward for an n1 x n2 image.
 size_t backward_scratch_floats(int n1, int n2, int S, int P) {
     const size_t n = (size_t)n1 * n2;
-    const int CH = 32 - 2 * P, CW = 32 - 2 * P;
-    const size_t tiles = (size_t)((n1 + 2 * P + CH - 1) / CH) * ((n2 + 2 * P + CW - 1) / CW);
-    return 2 * (size_t)kFacLead + 2 * n + 2 * n + std::max(5 * n, aux4_floats(n)) +
-           (size_t)(n1 + 2 * P) * (n2 + 2 * P) + blocks256(n) + tiles + 8 + sweep_d_part_floats(n1, n2, S, P);
+    const size_t tiles = (size_t)((n1 + 31) / 32) * ((n2 + 63) / 64);
+    return 2 * (size_t)kFacLead + 2 * n + 2 * n + aux4_floats(n) + (size_t)(n1 + 2 * P) * (n2 + 2 * P) +
+           blocks256(n) + tiles + 8 + sweep_d2_part_floats(n1, n2, S, P);
 }
 
 int enqueue_backward(dsnlm_weights* w, const float* x, const float* dy, float* dx, float* dguide, float* dh,
@@ -593,14 +300,13 @@ int enqueue_backward(dsnlm_weights* w, const float* x, const float* dy, float* d
     const size_t n = (size_t)n1 * n2;
     float* pairs = scratch + 2 * kFacLead;  // read by the half-window sweep C as partner factors
     float* cw = pairs + 2 * n;
-    float* aux5 = cw + 2 * n;
-    float* gz = aux5 + std::max(5 * n, aux4_floats(n));
+    float* aux5 = cw + 2 * n;               // 16-byte aligned: read as float4
+    float* gz = aux5 + aux4_floats(n);
     float* partials = gz + (size_t)(n1 + 2 * P) * (n2 + 2 * P);
     const int nb = blocks256(n);
-    const int CH = 32 - 2 * P, CW = 32 - 2 * P;
-    const int tiles_y = (n1 + 2 * P + CH - 1) / CH, tiles_x = (n2 + 2 * P + CW - 1) / CW;
+    const int nd = ((n1 + 31) / 32) * ((n2 + 63) / 64);  // sweep-D tiles (one partial of hbar each)
     float* hpart = partials + nb;
-    float* mbar = hpart + (size_t)tiles_y * tiles_x;
+    float* mbar = hpart + nd;
     float* dpart = mbar + 8;  // sweep-D partial regions
 
     BwdArgs a{};
@@ -613,7 +319,6 @@ int enqueue_backward(dsnlm_weights* w, const float* x, const float* dy, float* d
     a.pairs = pairs;
     a.cw = cw;
     a.aux5 = aux5;
-    a.aux4 = S <= 12;
     a.n1 = n1;
     a.n2 = n2;
     a.dx = dx;
@@ -640,35 +345,14 @@ int enqueue_backward(dsnlm_weights* w, const float* x, const float* dy, float* d
         if (rc) return rc;
     }
     if (!dguide && !dh) return DSNLM_OK;
-    int nd;  // blocks of sweep D (one partial of hbar each)
-    if (S <= 12) {
-        // sweep D on the forward sweep's machinery (32 x 64 s-tiles)
-        d.aux5 = aux5;
-        d.mbar = mbar;
-        d.gz = gz;
-        d.hpart = hpart;
-        d.dpart = dpart;
-        const int CHn = 32 - 2 * P, CWn = 64 - 2 * P;
-        nd = ((n1 + 2 * P + CHn - 1) / CHn) * ((n2 + 2 * P + CWn - 1) / CWn);
-        rc = check_hip(launch_sweep(kPassD, S, P, d, nullptr, nullptr, 0, st), "backward sweep D");
-        if (!rc) rc = check_hip(launch_d_gather(S, P, d, nullptr, nullptr, 0, st), "backward sweep D gather");
-        if (rc) return rc;
-    } else {
-        DArgs da{};
-        da.z = w->guide;
-        da.aux5 = aux5;
-        da.gz = gz;
-        da.hpart = hpart;
-        da.n1 = n1;
-        da.n2 = n2;
-        da.beta = d.beta;
-        da.kappa = d.kappa;
-        da.tiles_x = tiles_x;
-        nd = tiles_y * tiles_x;
-        ProfScope prof(DSNLM_K_PASS_D, st);
-        rc = check_hip(launch_sweep_d(da, S, P, nd, st), "backward sweep D");
-        if (rc) return rc;
-    }
+    d.aux5 = aux5;
+    d.mbar = mbar;
+    d.gz = gz;
+    d.hpart = hpart;
+    d.dpart = dpart;
+    rc = check_hip(launch_sweep_d2(S, P, d, nullptr, nullptr, 0, st), "backward sweep D");
+    if (!rc) rc = check_hip(launch_d2_gather(S, P, d, nullptr, nullptr, 0, st), "backward sweep D gather");
+    if (rc) return rc;
     ProfScope prof(DSNLM_K_BWD_TAIL, st);
     if (dguide) hipLaunchKernelGGL(k_fold, dim3(nb), dim3(256), 0, st, gz, dguide, n1, n2, P);
     if (dh) hipLaunchKernelGGL(k_dh, dim3(1), dim3(256), 0, st, hpart, nd, w->h, dh);
@@ -687,15 +371,15 @@ struct BwdBatchWs {
     size_t descs_cap = 0;
     int2* map = nullptr;
     size_t map_cap = 0;
-    TileRef* dtiles = nullptr;
-    size_t dtiles_cap = 0;
+    int2* gmap = nullptr;
+    size_t gmap_cap = 0;
     int2* tmap = nullptr;
     size_t tmap_cap = 0;
     std::vector<int2> h_tmap;
     std::vector<BwdArgs> h_args;
     std::vector<ImgDesc> h_descs;
     std::vector<int2> h_map;
-    std::vector<TileRef> h_dtiles;
+    std::vector<int2> h_gmap;
 };
 BwdBatchWs g_bws;
 
@@ -730,7 +414,6 @@ int upload_if_changed(T* dev, std::vector<T>& keep, const std::vector<T>& now, h
 
 int enqueue_backward_batch(const BwdImage* ims, int count, int S, int P, const TileRef* fwd_tiles, int nfwd_tiles,
                            hipStream_t st) {
-    const int CHn = 32 - 2 * P, CWn = 64 - 2 * P;
     // workspace layout per image: pairs 2n | cw 2n | sweep-D factors | gz | partials nb | hpart nd | mbar
     size_t total = 0;
     std::vector<size_t> base(count);
@@ -739,10 +422,10 @@ int enqueue_backward_batch(const BwdImage* ims, int count, int S, int P, const T
         const ImgDesc& f = *ims[k].fwd;
         const size_t n = (size_t)f.n1 * f.n2;
         nb[k] = (int)((n + 255) / 256);
-        nd[k] = ((f.n1 + 2 * P + CHn - 1) / CHn) * ((f.n2 + 2 * P + CWn - 1) / CWn);
+        nd[k] = ((f.n1 + 31) / 32) * ((f.n2 + 63) / 64);  // forward tiles
         base[k] = total;  // 256-byte aligned: the factors are read as float4
         total += 2 * (size_t)kFacLead + 4 * n + aux4_floats(n) + (size_t)(f.n1 + 2 * P) * (f.n2 + 2 * P) +
-                 nb[k] + nd[k] + 4 + sweep_d_part_floats(f.n1, f.n2, S, P);
+                 nb[k] + nd[k] + 4 + sweep_d2_part_floats(f.n1, f.n2, S, P);
         total = (total + 63) & ~(size_t)63;
     }
     int rc = check_hip(grow_b(&g_bws.arrays, &g_bws.arrays_cap, total), "batched backward workspace");
@@ -752,7 +435,7 @@ int enqueue_backward_batch(const BwdImage* ims, int count, int S, int P, const T
     std::vector<BwdArgs> args(count);
     std::vector<ImgDesc> descs(count);
     std::vector<int2> map, tmap;
-    std::vector<TileRef> dtiles;
+    std::vector<int2> gmap;
     for (int k = 0; k < count; ++k) {
         const ImgDesc& f = *ims[k].fwd;
         const size_t n = (size_t)f.n1 * f.n2;
@@ -767,7 +450,6 @@ int enqueue_backward_batch(const BwdImage* ims, int count, int S, int P, const T
         a.pairs = b;
         a.cw = b + 2 * n;
         a.aux5 = b + 4 * n;
-        a.aux4 = 1;
         a.gz = b + 4 * n + aux4_floats(n);
         a.partials = a.gz + (size_t)(f.n1 + 2 * P) * (f.n2 + 2 * P);
         a.hpart = a.partials + nb[k];
@@ -791,22 +473,20 @@ int enqueue_backward_batch(const BwdImage* ims, int count, int S, int P, const T
         d.gz = a.gz;
         d.hpart = a.hpart;
         d.dpart = dpart;
-        d.tile_base = (int)dtiles.size();
         descs[k] = d;
         for (int b2 = 0; b2 < nb[k]; ++b2) map.push_back(make_int2(k, b2));
         const int nt16 = ((f.n1 + 15) / 16) * ((f.n2 + 15) / 16);
         for (int t = 0; t < nt16; ++t) tmap.push_back(make_int2(k, t));
-        const int tyn = (f.n1 + 2 * P + CHn - 1) / CHn, txn = (f.n2 + 2 * P + CWn - 1) / CWn;
-        for (int ty = 0; ty < tyn; ++ty)
-            for (int tx = 0; tx < txn; ++tx) dtiles.push_back(TileRef{k, ty * CHn - 2 * P, tx * CWn - 2 * P, 0});
+        const int ng = (int)(((size_t)(f.n1 + 2 * P) * (f.n2 + 2 * P) + 255) / 256);
+        for (int g = 0; g < ng; ++g) gmap.push_back(make_int2(k, g));
     }
     rc = check_hip(grow_b(&g_bws.map, &g_bws.map_cap, map.size()), "batched backward map");
-    if (!rc) rc = check_hip(grow_b(&g_bws.dtiles, &g_bws.dtiles_cap, dtiles.size()), "batched backward tiles");
+    if (!rc) rc = check_hip(grow_b(&g_bws.gmap, &g_bws.gmap_cap, gmap.size()), "batched backward gather map");
     if (!rc) rc = check_hip(grow_b(&g_bws.tmap, &g_bws.tmap_cap, tmap.size()), "batched backward tile map");
     if (!rc) rc = upload_if_changed(g_bws.args, g_bws.h_args, args, st, "upload backward args");
     if (!rc) rc = upload_if_changed(g_bws.descs, g_bws.h_descs, descs, st, "upload backward descriptors");
     if (!rc) rc = upload_if_changed(g_bws.map, g_bws.h_map, map, st, "upload backward map");
-    if (!rc) rc = upload_if_changed(g_bws.dtiles, g_bws.h_dtiles, dtiles, st, "upload backward tiles");
+    if (!rc) rc = upload_if_changed(g_bws.gmap, g_bws.h_gmap, gmap, st, "upload backward gather map");
     if (!rc) rc = upload_if_changed(g_bws.tmap, g_bws.h_tmap, tmap, st, "upload backward tile map");
     if (rc) return rc;
     const int nmap = (int)map.size();
@@ -830,10 +510,9 @@ int enqueue_backward_batch(const BwdImage* ims, int count, int S, int P, const T
     bool need_d = false;
     for (int k = 0; k < count; ++k) need_d = need_d || ims[k].dguide || ims[k].dh;
     if (!need_d) return DSNLM_OK;
-    rc = check_hip(launch_sweep(kPassD, S, P, none, g_bws.descs, g_bws.dtiles, (int)dtiles.size(), st),
-                   "batched sweep D");
+    rc = check_hip(launch_sweep_d2(S, P, none, g_bws.descs, fwd_tiles, nfwd_tiles, st), "batched sweep D");
     if (!rc)
-        rc = check_hip(launch_d_gather(S, P, none, g_bws.descs, g_bws.dtiles, (int)dtiles.size(), st),
+        rc = check_hip(launch_d2_gather(S, P, none, g_bws.descs, g_bws.gmap, (int)gmap.size(), st),
                        "batched sweep D gather");
     if (rc) return rc;
     ProfScope prof(DSNLM_K_BWD_TAIL, st);
@@ -852,8 +531,8 @@ extern "C" int dsnlm_apply_backward(const dsnlm_weights* wc, const float* x, con
     dsnlm_weights* w = const_cast<dsnlm_weights*>(wc);
     if (!w->applied)
         return fail(DSNLM_EINVAL, "dsnlm_apply_backward: the handle holds no forward to differentiate");
-    if ((dguide || dh) && sweep_d_lds_bytes(w->S, w->P) > 160 * 1024)
-        return fail(DSNLM_EUNSUPPORTED, "dsnlm_apply_backward: guide/bandwidth gradients support S <= 16");
+    if ((dguide || dh) && !sweep_d2_fits(w->S, w->P))
+        return fail(DSNLM_EUNSUPPORTED, "dsnlm_apply_backward: guide/bandwidth gradients need S <= 24");
     const size_t bytes = (size_t)w->n1 * w->n2 * sizeof(float);
     if (dx && (overlaps(dx, x, bytes) || overlaps(dx, dy, bytes)))
         return fail(DSNLM_EINVAL, "dsnlm_apply_backward: dx overlaps x or dy");

@@ -44,12 +44,12 @@ __device__ __forceinline__ int reflect_clamp(int k, int n) {
 // Tile geometry.  S_CLASS is the largest search half-width the instance
 // serves; it fixes the LDS row strides at compile time so every LDS access in
 // the shift loop is a base register plus an immediate offset.
-template <int P, int S_CLASS, int L_ = 8>
+template <int P, int S_CLASS>
 struct Geo {
     static constexpr int TH = 32, TW = 64;   // output tile
     static constexpr int R = 8;              // phase-1 strip height
-    static constexpr int L = L_;             // phase-2 segment length
-    static constexpr int NT = TH * (TW / L);  // threads: 256 (L = 8) or 512 (L = 4)
+    static constexpr int L = 8;              // phase-2 segment length
+    static constexpr int NT = TH * (TW / L);  // threads: 256
     static constexpr int TWE = TW + 2 * P;   // tile widened by the patch
     static constexpr int NITEM1 = TWE * (TH / R);
     static constexpr int ROUNDS1 = (NITEM1 + NT - 1) / NT;
@@ -66,22 +66,12 @@ struct Geo {
     // V row stride: 4 * odd, for conflict-free float4 reads down rows
     static constexpr int VW0 = ((TWE + 3) / 4) * 4;
     static constexpr int VW = ((VW0 / 4) % 2) ? VW0 : VW0 + 4;
-    static constexpr int BW = TW + 2 * P + 1;         // sweep D: Dbar rows
-    static constexpr int CH = TH - 2 * P, CW = TW - 2 * P;  // sweep D core
-    // sweep D partner region of the core: CH + S rows, CW + 2S columns
-    static constexpr int RWc = (CW + 2 * S_CLASS) | 1;
     static_assert(TH % R == 0 && TW % L == 0 && L % 4 == 0, "tile shape");
 };
 
-// Sweep D carries many more live values per output (its own factors, the
-// partner factors, the guide-gradient accumulators), so it gives each thread
-// 4 outputs instead of 8 and runs 512 threads per tile.
-template <int P, int S_CLASS, int MODE>
-using GeoOf = Geo<P, S_CLASS, MODE == kPassD ? 4 : 8>;
-
-// per-pixel floats staged in LDS: none for pass A (its partners only mask) and
-// sweep D (it reads partner factors straight from memory), two otherwise
-constexpr int naux(int mode) { return (mode == kPassA || mode == kPassD) ? 0 : 2; }
+// per-pixel floats staged in LDS: none for pass A (its partners only mask),
+// two otherwise
+constexpr int naux(int mode) { return mode == kPassA ? 0 : 2; }
 
 template <int P, int S_CLASS>
 size_t lds_floats(int S, int mode) {
@@ -90,13 +80,7 @@ size_t lds_floats(int S, int mode) {
     const size_t AH = G::TH + 2 * S;
     size_t n = (ZWr * G::ZC + 3) & ~(size_t)3;
     n += (AH * G::AW * naux(mode) + 3) & ~(size_t)3;
-    if (mode == kPassD) {
-        n += (size_t)G::TH * G::VW;               // one V buffer
-        n += (size_t)2 * G::TH * G::BW;           // Dbar and its vertical box sums
-        n += (size_t)(G::CH + S) * G::RWc;        // partner region of the core
-    } else {
-        n += (size_t)2 * G::TH * G::VW;
-    }
+    n += (size_t)2 * G::TH * G::VW;
     return n;
 }
 
@@ -109,14 +93,11 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
     return v;
 }
 
-// Sweep D: 512 threads, and registers capped at 128 so that two tiles share a
-// CU (its LDS would allow three).
 template <int P, int S_CLASS, int MODE, bool BATCH, int PIPE>
-__global__ void __launch_bounds__(MODE == kPassD ? 512 : 256)
-    __attribute__((amdgpu_waves_per_eu(MODE == kPassD ? 4 : 1)))
+__global__ void __launch_bounds__(256)
 k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__ tiles, int S,
         HatTable hat) {
-    using G = GeoOf<P, S_CLASS, MODE>;
+    using G = Geo<P, S_CLASS>;
     constexpr int NT = G::NT, TH = G::TH, TW = G::TW, R = G::R, L = G::L;
     constexpr int ZC = G::ZC, AW = G::AW, VW = G::VW;
     constexpr int NA = naux(MODE);
@@ -135,14 +116,8 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
         first = (t.flags & 1) != 0;
     } else {
         d = one;
-        if constexpr (MODE == kPassD) {
-            // s-tiles overlap by 2P: their cores tile the padded grid [-P, n+P)
-            ti0 = blockIdx.y * G::CH - 2 * P;
-            tj0 = blockIdx.x * G::CW - 2 * P;
-        } else {
-            ti0 = blockIdx.y * TH;
-            tj0 = blockIdx.x * TW;
-        }
+        ti0 = blockIdx.y * TH;
+        tj0 = blockIdx.x * TW;
         first = blockIdx.x == 0 && blockIdx.y == 0;
     }
     const int n1 = d.n1, n2 = d.n2;
@@ -152,11 +127,7 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
     int off = (ZWr * ZC + 3) & ~3;
     float* Aux = lds + off;
     off += (AH * AW * NA + 3) & ~3;
-    float* Vb = lds + off;
-    constexpr int NVB = (MODE == kPassD) ? 1 : 2;  // V buffers
-    float* Db = Vb + NVB * TH * VW;                // sweep D only
-    float* VDb = Db + TH * G::BW;
-    float* Rg = VDb + TH * G::BW;                  // sweep D partner region (stride RWc)
+    float* Vb = lds + off;  // two V buffers
 
     // ---- stage the guide tile (halo S+P, mirrored) and the per-pixel inputs
     for (int idx = tid; idx < ZH * ZWr; idx += NT) {
@@ -164,10 +135,6 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
         const int gi = reflect_clamp(ti0 - S - P + r, n1);
         const int gj = reflect_clamp(tj0 - S - P + q, n2);
         Zs[q * ZC + r] = d.z[(size_t)gi * n2 + gj];
-    }
-    if constexpr (MODE == kPassD) {
-        // Dbar, its box sums and the partner region start at zero
-        for (int idx = tid; idx < 2 * TH * G::BW + (G::CH + S) * G::RWc; idx += NT) Db[idx] = 0.f;
     }
     if constexpr (NA == 2) {
         for (int idx = tid; idx < AH * AWr; idx += NT) {
@@ -225,56 +192,6 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
     const int gi_own = ti0 + pi;
     const int gj_own = tj0 + pj;
 
-    // sweep D: own factors (omegabar and c scaled by -kappa, B'bar, x), own
-    // guide value, core / in-image flags and the guide-gradient accumulators.
-    // Partner factors are read from memory per shift through a buffer
-    // resource; its range check returns zeros past the image's array, and
-    // pairs with a partner outside the image are masked anyway.
-    constexpr int LD = (MODE == kPassD) ? L : 1;
-    float ow[LD], oc[LD], ob[LD], ox[LD];
-    float zown[LD];
-    float accz[LD], hk[LD];
-    bool s_in = false;              // every s of the tile inside the image
-    float nk = 0.f;                 // -kappa
-    float mb = 0.f;                 // mbar, routed to the argmax pixel s*
-    int si = -1, sj = -1;           // s*
-    bool fnear = false;             // can a pair of this tile touch s*?
-    int roff[LD];                   // byte offsets of this thread's partners at shift 0
-    const float4* rbase = nullptr;  // buffer base and size (bytes) for the partner reads
-    int rbytes = 0;
-    if constexpr (MODE == kPassD) {
-        nk = -d.kappa;
-        const unsigned long long key = *d.key;
-        const int sstar = (int)(~(unsigned)(key & 0xffffffffu));
-        si = sstar / n2;
-        sj = sstar - si * n2;
-        mb = *d.mbar;
-        fnear = si >= ti0 - S && si < ti0 + TH + S && sj >= tj0 - S && sj < tj0 + TW + S;
-        // the factors are stored column-major (entry j n1 + i); the buffer
-        // starts at the first column this tile's partners can reach
-        const int col0 = tj0 - S > 0 ? tj0 - S : 0;
-        const float4* img4 = reinterpret_cast<const float4*>(d.aux5) + kAux4Lead;
-        rbase = img4 + (size_t)col0 * n1 - kAux4Lead;
-        const size_t recs = ((size_t)(n2 - col0) * n1 + kAux4Lead + kAux4Trail) * 16;
-        rbytes = (int)(recs < 0x7ffffff0u ? recs : 0x7ffffff0u);
-#pragma unroll
-        for (int k = 0; k < L; ++k) roff[k] = ((gj_own + k - col0) * n1 + gi_own + kAux4Lead) * 16;
-#pragma unroll
-        for (int k = 0; k < L; ++k) {
-            zown[k] = Zs[(pj + k + S + P) * ZC + pi + S + P];
-            const int gj = gj_own + k;
-            const bool in = (unsigned)gi_own < (unsigned)n1 && (unsigned)gj < (unsigned)n2;
-            const float4 o = in ? img4[(size_t)gj * n1 + gi_own] : make_float4(0.f, 0.f, 0.f, 0.f);
-            ow[k] = nk * o.x;
-            oc[k] = nk * o.y;
-            ob[k] = o.z;
-            ox[k] = o.w;
-            accz[k] = 0.f;
-            hk[k] = 0.f;
-        }
-        s_in = ti0 >= 0 && ti0 + TH <= n1 && tj0 >= 0 && tj0 + TW <= n2;
-    }
-
     // phase 1: vertical sliding box sums of e_d = (z(p) - z(p+d))^2 down the
     // column strips, written to V.  The running sum adds the entering square
     // and removes the leaving one with two FMAs.
@@ -307,13 +224,9 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
     // phase 2 is split so its LDS reads can be issued before the next
     // shift's phase 1: load() fetches V (and the per-pixel inputs), math()
     // forms D by horizontal sliding sums and a = exp2(log2 Lambda - beta D).
-    const __amdgpu_buffer_rsrc_t rsrc =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<float4*>(rbase), (short)0, rbytes, 0x00020000);
     constexpr int NV = ((L + 2 * P + 3) / 4) * 4;
     float vv[NV];
     float2 cv[L];
-    constexpr int LR = (MODE == kPassD) ? L : 1;
-    float4 rv[LR];
     auto load2 = [&](int dy, int dx, const float* V) {
         const float* vr = V + pi * VW + pj;
 #pragma unroll
@@ -328,21 +241,6 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
             const float2* ap = reinterpret_cast<const float2*>(Aux) + aux_base + (dy * AW + dx);
 #pragma unroll
             for (int k = 0; k < L; ++k) cv[k] = ap[k];
-        }
-    };
-    auto loadr = [&](int dy, int dx) {
-        if constexpr (MODE == kPassD) {
-            const int o = (dx * n1 + dy) * 16;
-            // keep these loads at this point of the schedule: hoisting them
-            // into earlier shifts only raises register pressure
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int k = 0; k < L; ++k)
-                rv[k] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, roff[k] + o, 0, 0));
-            __builtin_amdgcn_sched_barrier(0);
-        } else {
-            (void)dy;
-            (void)dx;
         }
     };
     auto math2 = [&](int dy, int dx) {
@@ -373,38 +271,6 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
                     acc0[k] += ok ? a : 0.f;
                 }
             }
-        } else if constexpr (MODE == kPassD) {
-            // -kappa (abar_{s,d} + abar_{s+d,-d}) with r = s + d:
-            //   -kappa (omegabar_s + omegabar_r)
-            //   - kappa c_s c_r ((B'bar_s - B'bar_r)(x_r - x_s) + f_s + f_r)
-            auto abar = [&](int k) {
-                const float4 r = rv[k];
-                return fmaf(oc[k] * r.y, (ob[k] - r.z) * (r.w - ox[k]), fmaf(nk, r.x, ow[k]));
-            };
-            const bool inside = s_in && ti0 + dy >= 0 && ti0 + TH - 1 + dy < n1 && tj0 + dx >= 0 &&
-                                tj0 + TW - 1 + dx < n2;
-            if (inside && !fnear) {
-                // every s of the tile and every partner is in the image
-#pragma unroll
-                for (int k = 0; k < L; ++k)
-                    Db[pi * G::BW + pj + k + P] = __builtin_amdgcn_exp2f(lg - beta * Dk[k]) * abar(k);
-            } else {
-                const bool rowok = (unsigned)(gi_own + dy) < (unsigned)n1 && (unsigned)gi_own < (unsigned)n1;
-                const bool rs = gi_own + dy == si, ss = gi_own == si;
-#pragma unroll
-                for (int k = 0; k < L; ++k) {
-                    float as = abar(k);
-                    if (fnear) {  // the f terms live on s* alone
-                        const float fr = (rs && gj_own + k + dx == sj) ? mb : 0.f;
-                        const float fs = (ss && gj_own + k == sj) ? mb : 0.f;
-                        as = fmaf(oc[k] * rv[k].y, fs + fr, as);
-                    }
-                    const float a = __builtin_amdgcn_exp2f(lg - beta * Dk[k]);
-                    const bool ok = rowok && (unsigned)(gj_own + k + dx) < (unsigned)n2 &&
-                                    (unsigned)(gj_own + k) < (unsigned)n2;
-                    Db[pi * G::BW + pj + k + P] = ok ? a * as : 0.f;
-                }
-            }
         } else {
 #pragma unroll
             for (int k = 0; k < L; ++k) {
@@ -412,59 +278,6 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
                 acc0[k] = fmaf(a, cv[k].x, acc0[k]);
                 if constexpr (MODE != kPassBBuild) acc1[k] = fmaf(a, cv[k].y, acc1[k]);
             }
-        }
-    };
-
-    // sweep D after D-bar of a shift is in LDS: box-sum it over the patch
-    // (phase 3 vertical on the core rows, column strips; phase 4 horizontal)
-    // and accumulate 2 (z(p) - z(p+d)) box(Dbar)(p) on the core.  Phase 3 of
-    // shift t shares a barrier interval with phase 1 of shift t+1, and phase 4
-    // of shift t with phase 2 of shift t+1, so a shift costs two barriers.
-    auto phase3 = [&]() {
-        if constexpr (MODE == kPassD) {
-            constexpr int BW = G::BW;
-            constexpr int R3 = (G::CH + 3) / 4;
-            const int c = tid % TW, strip = tid / TW;
-            const int r0 = P + strip * R3;
-            const int r1 = (r0 + R3 < TH - P) ? r0 + R3 : TH - P;
-            if (r0 < r1) {
-                float v = Db[(r0 - P) * BW + c + P];
-#pragma unroll
-                for (int t = 1; t <= 2 * P; ++t) v += Db[(r0 - P + t) * BW + c + P];
-                VDb[r0 * BW + c + P] = v;
-                for (int r = r0 + 1; r < r1; ++r) {
-                    v += Db[(r + P) * BW + c + P] - Db[(r - P - 1) * BW + c + P];
-                    VDb[r * BW + c + P] = v;
-                }
-            }
-        }
-    };
-    auto phase4 = [&](int dy, int dx) {
-        if constexpr (MODE == kPassD) {
-            constexpr int BW = G::BW;
-            const float* vr = VDb + pi * BW + pj;
-            float hs = vr[0];
-#pragma unroll
-            for (int q = 1; q <= 2 * P; ++q) hs += vr[q];
-            const float* zq = Zs + (pj + S + P + dx) * ZC + pi + S + P + dy;
-            // partner-region entry of output 0 moved by d (core coordinates)
-            float* rq = Rg + (pi - P + dy) * G::RWc + pj - P + dx + S;
-            const bool crow = pi >= P && pi < TH - P;
-#pragma unroll
-            for (int k = 0; k < L; ++k) {
-                if (k > 0) hs += vr[k + 2 * P] - vr[k - 1];
-                // T = dz G: zbar(q) += 2T and, for the mirrored pair, zbar(q+d)
-                // -= 2T (the 2 is applied by the gather); the bandwidth sum
-                // needs sum_s Dbar D = sum_q e_d(q) G(q), e_d = dz^2
-                const float dz = zown[k] - zq[k * ZC];
-                const float t = dz * hs;
-                accz[k] += t;
-                hk[k] = fmaf(dz, t, hk[k]);
-                if (crow && pj + k >= P && pj + k < TW - P) rq[k] -= t;
-            }
-        } else {
-            (void)dy;
-            (void)dx;
         }
     };
 
@@ -479,10 +292,8 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
         constexpr int GW = G::GWIN;
         constexpr int NW = NE + GW - 1;
         int t = 0;
-        int pdy = 0, pdx = 0;  // previous shift (sweep D)
         for (dx = -S; dx <= S; ++dx) {
-            // sweep D visits the half window (its pairs are symmetric)
-            for (int dy0 = (MODE == kPassD ? (dx > 0 ? 0 : 1) : -S); dy0 <= S; dy0 += GW) {
+            for (int dy0 = -S; dy0 <= S; dy0 += GW) {
                 float win[G::ROUNDS1][NW];
 #pragma unroll
                 for (int k1 = 0; k1 < G::ROUNDS1; ++k1) {
@@ -493,7 +304,7 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
 #pragma unroll
                 for (int g = 0; g < GW; ++g) {
                     if (dy0 + g <= S) {
-                        float* V = Vb + ((NVB == 2) ? (t & 1) : 0) * (TH * VW);
+                        float* V = Vb + (t & 1) * (TH * VW);
 #pragma unroll
                         for (int k1 = 0; k1 < G::ROUNDS1; ++k1) {
                             if (tid + k1 * NT < G::NITEM1) {
@@ -513,30 +324,13 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
                                 }
                             }
                         }
-                        if constexpr (MODE == kPassD) {
-                            loadr(dy0 + g, dx);  // in flight over phases 3 and 4
-                            if (t > 0) phase3();
-                        }
                         __syncthreads();
-                        if constexpr (MODE == kPassD) {
-                            if (t > 0) phase4(pdy, pdx);
-                        }
                         load2(dy0 + g, dx, V);
                         math2(dy0 + g, dx);
-                        if constexpr (MODE == kPassD) {
-                            __syncthreads();
-                            pdy = dy0 + g;
-                            pdx = dx;
-                        }
                         ++t;
                     }
                 }
             }
-        }
-        if constexpr (MODE == kPassD) {  // drain the last shift
-            phase3();
-            __syncthreads();
-            phase4(pdy, pdx);
         }
     } else if constexpr (PIPE == 1) {
         // software pipeline: phase 1 of shift t+1 and phase 2 of shift t share
@@ -568,38 +362,6 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
                 ++dy;
             }
         }
-    }
-
-    if constexpr (MODE == kPassD) {
-        // the core: the s-tile less P on each side (cores tile the padded grid)
-        auto core = [&](int k) { return pi >= P && pi < TH - P && pj + k >= P && pj + k < TW - P; };
-        __syncthreads();  // every scatter of the last shift is in the region
-#pragma unroll
-        for (int k = 0; k < L; ++k)
-            if (core(k)) Rg[(pi - P) * G::RWc + pj + k - P + S] += accz[k];
-        float hacc = 0.f;
-#pragma unroll
-        for (int k = 0; k < L; ++k) hacc += core(k) ? hk[k] : 0.f;
-        __syncthreads();
-        const int tile = BATCH ? (int)blockIdx.x - d.tile_base : (int)(blockIdx.y * gridDim.x + blockIdx.x);
-        const int RH = G::CH + S, RWr = G::CW + 2 * S;
-        float* part = d.dpart + (size_t)tile * RH * RWr;
-        for (int idx = tid; idx < RH * RWr; idx += NT) {
-            const int r = idx / RWr, q = idx - r * RWr;
-            part[idx] = Rg[r * G::RWc + q];
-        }
-        // block partial of sum Dbar D over the half window, doubled for the
-        // mirrored pairs: fixed-order LDS tree (V is free: its last reads, in
-        // the last shift's phase 2, precede the barriers above)
-        float* red = Vb;
-        red[tid] = 2.f * hacc;
-        __syncthreads();
-        for (int w = NT / 2; w > 0; w >>= 1) {
-            if (tid < w) red[tid] += red[tid + w];
-            __syncthreads();
-        }
-        if (tid == 0) d.hpart[tile] = red[0];
-        return;
     }
 
     // ---- per-pixel epilogue of the pass
@@ -684,14 +446,11 @@ hipError_t ensure_attr() {
 template <int P, int S_CLASS, int MODE, bool BATCH, int PIPE>
 hipError_t launch_var(int S, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
                       int ntiles, hipStream_t st) {
-    using G = GeoOf<P, S_CLASS, MODE>;
+    using G = Geo<P, S_CLASS>;
     const size_t lds = lds_floats<P, S_CLASS>(S, MODE) * sizeof(float);
     hipError_t e = ensure_attr<P, S_CLASS, MODE, BATCH, PIPE>();
     if (e != hipSuccess) return e;
-    dim3 grid = BATCH ? dim3(ntiles)
-                      : (MODE == kPassD
-                             ? dim3((one.n2 + 2 * P + G::CW - 1) / G::CW, (one.n1 + 2 * P + G::CH - 1) / G::CH)
-                             : dim3((one.n2 + G::TW - 1) / G::TW, (one.n1 + G::TH - 1) / G::TH));
+    dim3 grid = BATCH ? dim3(ntiles) : dim3((one.n2 + G::TW - 1) / G::TW, (one.n1 + G::TH - 1) / G::TH);
     HatTable hat = make_hat(S);
     hipLaunchKernelGGL((k_sweep<P, S_CLASS, MODE, BATCH, PIPE>), grid, dim3(G::NT), lds, st, one,
                        batch, tiles, S, hat);
@@ -701,15 +460,10 @@ hipError_t launch_var(int S, const ImgDesc& one, const ImgDesc* batch, const Til
 template <int P, int S_CLASS, int MODE, bool BATCH>
 hipError_t launch_one(int S, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
                       int ntiles, hipStream_t st) {
-    if constexpr (MODE == kPassD) {
-        if (lds_floats<P, S_CLASS>(S, MODE) * sizeof(float) > 160 * 1024) return hipErrorInvalidValue;
-        return launch_var<P, S_CLASS, MODE, BATCH, 2>(S, one, batch, tiles, ntiles, st);
-    } else {
-        switch (sweep_variant(MODE, S, P)) {
-            case 0: return launch_var<P, S_CLASS, MODE, BATCH, 0>(S, one, batch, tiles, ntiles, st);
-            case 1: return launch_var<P, S_CLASS, MODE, BATCH, 1>(S, one, batch, tiles, ntiles, st);
-            default: return launch_var<P, S_CLASS, MODE, BATCH, 2>(S, one, batch, tiles, ntiles, st);
-        }
+    switch (sweep_variant(MODE, S, P)) {
+        case 0: return launch_var<P, S_CLASS, MODE, BATCH, 0>(S, one, batch, tiles, ntiles, st);
+        case 1: return launch_var<P, S_CLASS, MODE, BATCH, 1>(S, one, batch, tiles, ntiles, st);
+        default: return launch_var<P, S_CLASS, MODE, BATCH, 2>(S, one, batch, tiles, ntiles, st);
     }
 }
 
@@ -720,10 +474,6 @@ hipError_t dispatch_mode(int mode, int S, const ImgDesc& one, const ImgDesc* bat
         case kPassA: return launch_one<P, S_CLASS, kPassA, BATCH>(S, one, batch, tiles, ntiles, st);
         case kPassBApply: return launch_one<P, S_CLASS, kPassBApply, BATCH>(S, one, batch, tiles, ntiles, st);
         case kPassC: return launch_one<P, S_CLASS, kPassC, BATCH>(S, one, batch, tiles, ntiles, st);
-        case kPassD:
-            if constexpr (S_CLASS <= kSmallS)
-                return launch_one<P, S_CLASS, kPassD, BATCH>(S, one, batch, tiles, ntiles, st);
-            return hipErrorInvalidValue;
         default: break;
     }
     if constexpr (!BATCH) {
@@ -825,77 +575,12 @@ hipError_t launch_sweep(int mode, int S, int P, const ImgDesc& one, const ImgDes
     const int kind = mode == kPassA ? DSNLM_K_PASS_A
                      : (mode == kPassBApply || mode == kPassBBuild) ? DSNLM_K_PASS_B
                      : mode == kApply ? DSNLM_K_APPLY
-                     : mode == kPassD ? DSNLM_K_PASS_D
                                       : DSNLM_K_PASS_C;
     if (one.part && half_mode_ok(mode) && sweep_variant(mode, S, P) == kHalfVariant && half_lds_fits(S, P, mode))
         return launch_half(mode, S, P, one, batch, tiles, ntiles, st);  // times its kernels itself
     ProfScope prof(kind, st);
     if (batch) return dispatch_p<true>(mode, S, P, one, batch, tiles, ntiles, st);
     return dispatch_p<false>(mode, S, P, one, batch, tiles, ntiles, st);
-}
-
-// Sweep D gather: every padded-grid pixel q of a tile's core sums the partial
-// regions of the (at most six) tiles covering it in a fixed order (own, left,
-// right, above, above-left, above-right) and gz(q) = 2 x the sum.
-template <bool BATCH>
-__global__ void __launch_bounds__(256)
-k_d_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__ tiles, int S, int P,
-           int CH, int CW) {
-    ImgDesc d;
-    int ti0, tj0, tile;
-    if constexpr (BATCH) {
-        const TileRef t = tiles[blockIdx.x];
-        d = batch[t.img];
-        ti0 = t.ti0;
-        tj0 = t.tj0;
-        tile = (int)blockIdx.x - d.tile_base;
-    } else {
-        d = one;
-        ti0 = blockIdx.y * CH - 2 * P;
-        tj0 = blockIdx.x * CW - 2 * P;
-        tile = blockIdx.y * gridDim.x + blockIdx.x;
-    }
-    const int n1 = d.n1, n2 = d.n2, W2 = n2 + 2 * P;
-    const int tx_n = (n2 + 2 * P + CW - 1) / CW;
-    const int ty = (ti0 + 2 * P) / CH, tx = (tj0 + 2 * P) / CW;
-    const int RH = CH + S, RWr = CW + 2 * S;
-    const size_t reg = (size_t)RH * RWr;
-    for (int e = threadIdx.x; e < CH * CW; e += 256) {
-        const int li = e / CW, lj = e - li * CW;
-        const int qi = ti0 + P + li, qj = tj0 + P + lj;  // padded-grid position
-        if (qi >= n1 + P || qj >= n2 + P) continue;
-        auto at = [&](int t, int r, int q) { return d.dpart[(size_t)t * reg + (size_t)r * RWr + q]; };
-        const bool left = tx > 0 && lj < S, right = tx + 1 < tx_n && lj >= CW - S;
-        float acc = at(tile, li, lj + S);
-        if (left) acc += at(tile - 1, li, lj + CW + S);
-        if (right) acc += at(tile + 1, li, lj - CW + S);
-        if (ty > 0 && li < S) {
-            const int up = tile - tx_n;
-            acc += at(up, li + CH, lj + S);
-            if (left) acc += at(up - 1, li + CH, lj + CW + S);
-            if (right) acc += at(up + 1, li + CH, lj - CW + S);
-        }
-        d.gz[(size_t)(qi + P) * W2 + qj + P] = 2.f * acc;
-    }
-}
-
-size_t sweep_d_part_floats(int n1, int n2, int S, int P) {
-    const int CH = 32 - 2 * P, CW = 64 - 2 * P;
-    const size_t nd = (size_t)((n1 + 2 * P + CH - 1) / CH) * ((n2 + 2 * P + CW - 1) / CW);
-    return nd * (size_t)(CH + S) * (CW + 2 * S);
-}
-
-hipError_t launch_d_gather(int S, int P, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
-                           int ntiles, hipStream_t st) {
-    const int CH = 32 - 2 * P, CW = 64 - 2 * P;
-    ProfScope prof(DSNLM_K_BWD_TAIL, st);
-    if (batch) {
-        hipLaunchKernelGGL((k_d_gather<true>), dim3(ntiles), dim3(256), 0, st, one, batch, tiles, S, P, CH, CW);
-    } else {
-        const dim3 grid((one.n2 + 2 * P + CW - 1) / CW, (one.n1 + 2 * P + CH - 1) / CH);
-        hipLaunchKernelGGL((k_d_gather<false>), grid, dim3(256), 0, st, one, batch, tiles, S, P, CH, CW);
-    }
-    return hipGetLastError();
 }
 
 hipError_t launch_epilogue(const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,

@@ -67,7 +67,7 @@ enum SweepMode : int {
     kPassBBuild = 2,   // delta and the key only
     kApply = 3,        // B' only (weights already built)
     kPassC = 4,        // backward: sum a t_r, sum a w_r
-    kPassD = 5,        // backward: guide and bandwidth gradients
+    kPassD = 5,        // backward: guide and bandwidth gradients (dsnlm_sweep_d.hip)
     kNLM = 6,          // plain NLM (eq. NLM): sums of k and k x, no hat (half window only)
 };
 
@@ -115,17 +115,21 @@ hipError_t prepare_half(int S, int P);
 // guide (margin S + P).
 hipError_t launch_brute(const ImgDesc& d, int S, int P, hipStream_t st);
 
-// Sweep D (S <= 12) runs over the half window and writes per-tile partial
-// regions; the gather turns them into the padded-grid gradient gz.  Floats
-// of the partial buffer of an n1 x n2 image, and the gather launcher.
-size_t sweep_d_part_floats(int n1, int n2, int S, int P);
-hipError_t launch_d_gather(int S, int P, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
-                           int ntiles, hipStream_t st);
+// Sweep D on the forward's 32 x 64 tiling (dsnlm_sweep_d.hip): every pair
+// is evaluated by one tile, whose contributions land in a partial region
+// (rows ti0 - P .. ti0 + 32 + P + S, columns tj0 - P - S .. tj0 + 64 + P + S);
+// the gather sums the covering regions into gz on the padded grid.  The
+// tile list of a batch launch is the forward's; d.hpart gets one entry per
+// forward tile of the image.
+bool sweep_d2_fits(int S, int P);
+size_t sweep_d2_part_floats(int n1, int n2, int S, int P);
+hipError_t launch_sweep_d2(int S, int P, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles, int ntiles,
+                           hipStream_t st);
+// map[b] = (image, block of 256 padded-grid pixels) for a batch launch
+hipError_t launch_d2_gather(int S, int P, const ImgDesc& one, const ImgDesc* batch, const int2* map, int nblocks,
+                            hipStream_t st);
 
 // Backward launchers (dsnlm_backward.hip).
-// Backward (dsnlm_backward.hip): LDS bytes of sweep D and the largest S it
-// supports for patch half-width P.
-size_t sweep_d_lds_bytes(int S, int P);
 int enqueue_backward(dsnlm_weights* w, const float* x, const float* dy, float* dx, float* dguide,
                      float* dh, float* scratch, hipStream_t st);
 size_t backward_scratch_floats(int n1, int n2, int S, int P);

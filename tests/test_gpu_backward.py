@@ -35,7 +35,7 @@ def _case(n1, n2, seed, sep_guide=True):
 
 
 CASES = [(32, 32, 7, 3, 0.1), (29, 41, 3, 1, 0.08), (40, 24, 5, 2, 0.12), (33, 70, 10, 3, 0.1),
-         (12, 12, 6, 2, 0.15)]
+         (12, 12, 6, 2, 0.15), (40, 70, 16, 2, 0.1), (28, 30, 18, 2, 0.12)]
 
 
 @pytest.mark.parametrize("n1,n2,S,P,h", CASES)
@@ -113,7 +113,7 @@ def test_backward_c3_batch_shape_runs_and_is_deterministic():
             assert torch.equal(u, v)
 
 
-@pytest.mark.parametrize("S,P", [(7, 3), (4, 1), (10, 2)])
+@pytest.mark.parametrize("S,P", [(7, 3), (4, 1), (10, 2), (16, 3)])
 def test_batched_backward_matches_fp64_autograd(S, P):
     """One batched forward and backward over images of uneven sizes (several
     tiles and ragged tails): every image's gradients against the FP64
