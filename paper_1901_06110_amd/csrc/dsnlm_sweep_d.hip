@@ -139,9 +139,14 @@ k_d2(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__
     const int col0 = tj0 - S > 0 ? tj0 - S : 0;
     const float4* img4 = reinterpret_cast<const float4*>(d.aux5) + kAux4Lead;
     const size_t recs = ((size_t)(n2 - col0) * n1 + kAux4Lead + kAux4Trail) * 16;
-    const __amdgpu_buffer_rsrc_t rsrc =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<float4*>(img4 + (size_t)col0 * n1 - kAux4Lead), (short)0,
-                                          (int)(recs < 0x7ffffff0u ? recs : 0x7ffffff0u), 0x00020000);
+    // the base and size are uniform: keep them in scalar registers, so each
+    // partner load is a single buffer instruction
+    const unsigned long long rb = reinterpret_cast<unsigned long long>(img4 + (size_t)col0 * n1 - kAux4Lead);
+    const unsigned rlo = __builtin_amdgcn_readfirstlane((unsigned)rb);
+    const unsigned rhi = __builtin_amdgcn_readfirstlane((unsigned)(rb >> 32));
+    const int rn = __builtin_amdgcn_readfirstlane((int)(recs < 0x7ffffff0u ? recs : 0x7ffffff0u));
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        reinterpret_cast<void*>(((unsigned long long)rhi << 32) | rlo), (short)0, rn, 0x00020000);
     float ow[L], oc[L], ob[L], ox[L];
     int roff[L];
 #pragma unroll
@@ -250,9 +255,9 @@ k_d2(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__
         const int r1 = (r0 + R3 < TH + P) ? r0 + R3 : TH + P;
         if (r0 < r1) {
             const float* col = Db + c;
-            float v = 0.f;
+            float v = col[(r0 + P) * DBW];
 #pragma unroll
-            for (int t = -P; t <= P; ++t) v += col[(r0 + t + 2 * P) * DBW];
+            for (int t = 1 - P; t <= P; ++t) v += col[(r0 + t + 2 * P) * DBW];
             VDb[(r0 + P) * VBW + c + 2 * P] = v;
             for (int r = r0 + 1; r < r1; ++r) {
                 v += col[(r + P + 2 * P) * DBW] - col[(r - P - 1 + 2 * P) * DBW];
