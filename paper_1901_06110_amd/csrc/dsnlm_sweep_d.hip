@@ -27,7 +27,7 @@ struct DGeo {
     static constexpr int NT = TH * (TW / L);  // 512
     static constexpr int TWE = TW + 2 * P;
     static constexpr int NITEM1 = TWE * (TH / R);
-    static constexpr int GW = P >= 3 ? 1 : 2;  // shifts sharing a register window
+    static constexpr int GW = 1;  // shifts sharing a register window of the shifted column
     // guide rows ti0-P .. ti0+TH+S+P (+ window slack), column-major, odd stride
     static constexpr int ZC = (TH + S_CLASS + 2 * P + GW - 1) | 1;
     static constexpr int VW0 = ((TWE + 3) / 4) * 4;
@@ -270,20 +270,31 @@ k_d2(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__
     // at q (registers) and subtracted at q + d (region)
     auto phase4 = [&](int dy, int dx) {
         if (has4) {
+            // every read before the first write: the writes could alias the
+            // reads as far as the compiler knows, and would force reloads
             const float* vr = VDb + (qr + P) * VBW + qc + P;
-            float hs = vr[0];
-#pragma unroll
-            for (int q = 1; q <= 2 * P; ++q) hs += vr[q];
             const float* zq = Zs + (qc + P + S + dx) * ZC + qr + P + dy;
             float* rq = Rg + (qr + P + dy) * RWc + qc + P + S + dx;
+            float vq[L4 + 2 * P], zs[L4], rg[L4];
+#pragma unroll
+            for (int q = 0; q < L4 + 2 * P; ++q) vq[q] = vr[q];
 #pragma unroll
             for (int k = 0; k < L4; ++k) {
-                if (k > 0) hs += vr[k + 2 * P] - vr[k - 1];
-                const float dz = zown[k] - zq[k * ZC];
-                const float t = dz * hs;
-                accz[k] += t;
-                rq[k] -= t;
+                zs[k] = zq[k * ZC];
+                rg[k] = rq[k];
             }
+            float hs = vq[0];
+#pragma unroll
+            for (int q = 1; q <= 2 * P; ++q) hs += vq[q];
+#pragma unroll
+            for (int k = 0; k < L4; ++k) {
+                if (k > 0) hs += vq[k + 2 * P] - vq[k - 1];
+                const float t = (zown[k] - zs[k]) * hs;
+                accz[k] += t;
+                rg[k] -= t;
+            }
+#pragma unroll
+            for (int k = 0; k < L4; ++k) rq[k] = rg[k];
         }
     };
 
