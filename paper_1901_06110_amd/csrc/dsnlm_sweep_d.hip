@@ -23,7 +23,7 @@ namespace {
 
 template <int P, int S_CLASS>
 struct DGeo {
-    static constexpr int TH = 32, TW = 64, R = 8, L = 4;
+    static constexpr int TH = 32, TW = 64, R = 8, L = 4;  // L = 4: one float4 of D-bar per thread
     static constexpr int NT = TH * (TW / L);  // 512
     static constexpr int TWE = TW + 2 * P;
     static constexpr int NITEM1 = TWE * (TH / R);
@@ -32,7 +32,8 @@ struct DGeo {
     static constexpr int ZC = (TH + S_CLASS + 2 * P + GW - 1) | 1;
     static constexpr int VW0 = ((TWE + 3) / 4) * 4;
     static constexpr int VW = ((VW0 / 4) % 2) ? VW0 : VW0 + 4;
-    static constexpr int DBH = TH + 4 * P, DBW = TW | 1;           // D-bar, rows -2P..TH+2P
+    // D-bar, rows -2P..TH+2P; row stride 4 x odd, for conflict-free float4 writes
+    static constexpr int DBH = TH + 4 * P, DBW = TW + 4;
     // phase 4 covers the tile widened by P: rows of (TW + 2P) positions cut
     // into segments of L4, one per thread (the last threads of the block, so
     // that the waves doing phase 1 get fewer); the last segment of a row may
@@ -42,8 +43,16 @@ struct DGeo {
     static constexpr int WWP = NSEG * L4;                           // padded widened width
     static constexpr int NQ = (TH + 2 * P) * NSEG;                  // phase-4 threads
     static constexpr int ZWX = WWP - (TW + 2 * P);                  // extra guide columns
-    static constexpr int VBH = TH + 2 * P, VBW = (WWP + 2 * P) | 1;  // vertical box, cols -2P..
-    static constexpr int RWc = (WWP + 2 * S_CLASS) | 1;             // region stride
+    // LDS layouts for phase 4, whose lane l of a wave works on segment q0 + l:
+    // with row strides congruent to WWP mod 64 the first position of segment
+    // q sits at bank 7q, so the 64 lanes of a read or write hit 64 banks.
+    // The vertical box sums (cols -2P..) use stride WWP itself: the last 2P
+    // entries of a row are the first 2P of the next, zero in both (phase 3
+    // writes columns 0..TW-1 of D-bar, at 2P..TW+2P-1).
+    static constexpr int VBH = TH + 2 * P, VBW = WWP;
+    static constexpr int VBN = ((VBH * VBW + 2 * P) + 3) & ~3;      // floats of the box sums
+    static constexpr int RWc = WWP + 64;                            // region stride (>= WWP + 2S)
+    static_assert(2 * S_CLASS <= 64 && TW + 2 * P <= WWP, "layout");
     static_assert(NQ <= NT, "one phase-4 segment per thread");
     static_assert(NITEM1 <= NT, "one phase-1 item per thread");
 };
@@ -54,7 +63,7 @@ size_t d2_lds_floats(int S) {
     const size_t ZWr = G::TW + 2 * (S + P) + G::ZWX;
     size_t n = (ZWr * G::ZC + 3) & ~(size_t)3;
     n += (size_t)G::TH * G::VW;
-    n += (size_t)G::DBH * G::DBW + (size_t)G::VBH * G::VBW;
+    n += (size_t)G::DBH * G::DBW + (size_t)G::VBN;
     n += (size_t)(G::TH + 2 * P + S) * G::RWc;
     return n;
 }
@@ -97,7 +106,7 @@ k_d2(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__
     float* V = lds + off;
     float* Db = V + TH * VW;
     float* VDb = Db + G::DBH * DBW;
-    float* Rg = VDb + G::VBH * VBW;
+    float* Rg = VDb + G::VBN;
 
     // ---- staging: guide rows ti0-P .. ti0+TH+S+P, columns tj0-S-P .. (mirrored);
     // D-bar, its box sums and the region start at zero
@@ -107,14 +116,22 @@ k_d2(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__
         const int gj = reflect_d(tj0 - S - P + q, n2);
         Zs[q * ZC + r] = d.z[(size_t)gi * n2 + gj];
     }
-    for (int idx = tid; idx < G::DBH * DBW + G::VBH * VBW + RH * RWc; idx += NT) Db[idx] = 0.f;
+    for (int idx = tid; idx < G::DBH * DBW + G::VBN + RH * RWc; idx += NT) Db[idx] = 0.f;
     __syncthreads();
 
-    // ---- phase-1 item: one column strip of R rows of s (reference in registers)
+    // ---- phase-1 item: one column strip of R rows of s (reference in registers).
+    // Waves 0-3 take the first 64 columns of strips 0-3 (one strip per wave,
+    // conflict-free), the next threads the remaining 2P columns of each strip.
     const bool has1 = tid < G::NITEM1;
-    const int it = has1 ? tid : 0;
-    const int strip = it / G::TWE;
-    const int c1 = it - strip * G::TWE;
+    int strip = tid >> 6, c1 = tid & 63;
+    if constexpr (G::TWE > 64) {
+        if (tid >= 256) {
+            const int e = has1 ? tid - 256 : 0;
+            strip = e / (G::TWE - 64);
+            c1 = 64 + e - strip * (G::TWE - 64);
+        }
+    }
+    if (!has1) strip = c1 = 0;
     const int zoff = (c1 + S) * ZC + strip * R;  // Zs column c1 + S is global column tj0 - P + c1
     const int voff = strip * R * VW + c1;
     float ref[NE];
@@ -214,7 +231,7 @@ k_d2(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__
             hs += vv[k + 2 * P] - vv[k - 1];
             Dk[k] = hs;
         }
-        float* dbo = Db + (pi + 2 * P) * DBW + pj;
+        float db[L];
         auto abar = [&](int k) {
             const float4 r = rv[k];
             return fmaf(oc[k] * r.y, (ob[k] - r.z) * (r.w - ox[k]), fmaf(nk, r.x, ow[k]));
@@ -222,11 +239,7 @@ k_d2(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__
         const bool inside = s_in && ti0 + TH - 1 + dy < n1 && tj0 + dx >= 0 && tj0 + TW - 1 + dx < n2;
         if (inside && !fnear) {
 #pragma unroll
-            for (int k = 0; k < L; ++k) {
-                const float db = __builtin_amdgcn_exp2f(lg - d.beta * Dk[k]) * abar(k);
-                dbo[k] = db;
-                hsum = fmaf(db, Dk[k], hsum);
-            }
+            for (int k = 0; k < L; ++k) db[k] = __builtin_amdgcn_exp2f(lg - d.beta * Dk[k]) * abar(k);
         } else {
             const bool rowok = gi_own < n1 && gi_own + dy < n1;
             const bool rs = gi_own + dy == si, ss = gi_own == si;
@@ -240,11 +253,12 @@ k_d2(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__
                 }
                 const float a = __builtin_amdgcn_exp2f(lg - d.beta * Dk[k]);
                 const bool ok = rowok && gj_own + k < n2 && (unsigned)(gj_own + k + dx) < (unsigned)n2;
-                const float db = ok ? a * as : 0.f;
-                dbo[k] = db;
-                hsum = fmaf(db, Dk[k], hsum);
+                db[k] = ok ? a * as : 0.f;
             }
         }
+#pragma unroll
+        for (int k = 0; k < L; ++k) hsum = fmaf(db[k], Dk[k], hsum);
+        *reinterpret_cast<float4*>(Db + (pi + 2 * P) * DBW + pj) = make_float4(db[0], db[1], db[2], db[3]);
     };
 
     // phase 3: vertical box of D-bar for rows -P..TH+P-1 (column strips)
