@@ -165,7 +165,8 @@ k_d2(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__
     const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
         reinterpret_cast<void*>(((unsigned long long)rhi << 32) | rlo), (short)0, rn, 0x00020000);
     float ow[L], oc[L], ob[L], ox[L];
-    int roff[L];
+    // byte offset of the partner of output 0 at shift 0; output k adds k n1 16
+    const int roff = ((gj_own - col0) * n1 + gi_own + kAux4Lead) * 16;
 #pragma unroll
     for (int k = 0; k < L; ++k) {
         const int gj = gj_own + k;
@@ -175,7 +176,6 @@ k_d2(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__
         oc[k] = nk * o.y;
         ob[k] = o.z;
         ox[k] = o.w;
-        roff[k] = ((gj - col0) * n1 + gi_own + kAux4Lead) * 16;
     }
     // phase-4 role: a segment of L4 positions q of the widened tile (row qr,
     // first column qc, tile coordinates), their guide values and the sums of T
@@ -200,7 +200,8 @@ k_d2(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int k = 0; k < L; ++k)
-            rv[k] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, roff[k] + o, 0, 0));
+            rv[k] = __builtin_bit_cast(
+                float4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, roff + (o + k * n1 * 16), 0, 0));
         __builtin_amdgcn_sched_barrier(0);
     };
 
