@@ -199,7 +199,9 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
     for (int q = 0; q < NE; ++q) ref[q] = __builtin_bit_cast(float, zload(zbase + q * W2));
 
     const int pi = tid % TH;
-    const int pj = (tid / TH) * L;
+    // a wave holds two column groups 32 apart: with odd row strides its scalar
+    // LDS accesses then hit 64 distinct banks
+    const int pj = ((tid / TH) & 1) * (TW / 2) + (tid / (2 * TH)) * L;
     const int own = pi * AW + pj + S;  // own pixel in the partner region
     __syncthreads();
     float acc0[L], acc1[L], f0[L], f1[L];
