@@ -166,3 +166,57 @@ def test_batched_backward_input_gradient_only_and_errors():
         assert _rel(dx.cpu().numpy(), ref) <= 1e-4
     with pytest.raises(M.api._lib.DsnlmError):
         M.dsnlm_backward_batched([_t(ybars[0])])
+
+
+def test_batched_backward_full_size_directional_derivatives():
+    """The differentiated denoiser's full batch (8 x 256^2, S = 7, P = 3), at a
+    size the FP64 autograd reference cannot reach: for the loss L = <ybar, y>
+    (linear in y), the batched backward's gradients must match central
+    differences of the GPU forward itself along chosen directions:
+      guide: a +-1 pattern on a 24 x 24 window far from the argmax pixel s*
+             (m and s* do not move, so only pixels near the window change);
+      x:     <dx, u> = <ybar, W u> for a random u (W is symmetric);
+      h:     a step of 1e-3 in h.
+    The sums are taken in FP64 on the host."""
+    M = _M()
+    S, P, h = 7, 3, 0.1
+    batch = synth.config3_batch()
+    dev = [(_t(noisy), _t(noisy), h) for _, noisy in batch]
+    ys = M.dsnlm_forward_batched(dev, S, P)
+    rng = np.random.default_rng(2024)
+    ybars = [_t(rng.standard_normal(y.shape)) for y in ys]
+    out = M.dsnlm_backward_batched(ybars)
+    torch.cuda.synchronize()
+
+    def loss(z, x, hh, yb):
+        y = M.dsnlm_forward(x, z, S, P, hh)
+        return float((y.double() * yb.double()).sum())
+
+    for k in (0, 5):
+        z, x, _ = dev[k]
+        yb = ybars[k]
+        dx, dg, dh = out[k]
+        _, w = M.dsnlm_forward(x, z, S, P, h, keep=True)
+        m, am = w.scalars()
+        si, sj = divmod(am, z.shape[1])
+        print(f"full-size directional check image {k}: s* = ({si}, {sj})", flush=True)
+        i0 = 16 if si >= 128 else 216
+        j0 = 16 if sj >= 128 else 216
+        v = torch.zeros_like(z)
+        v[i0:i0 + 24, j0:j0 + 24] = _t(rng.choice([-1.0, 1.0], size=(24, 24)))
+        eps = 4e-3
+        for sgn in (1.0, -1.0):
+            _, wp = M.dsnlm_forward(x, z + sgn * eps * v, S, P, h, keep=True)
+            assert wp.scalars()[1] == am
+        fd = (loss(z + eps * v, x, h, yb) - loss(z - eps * v, x, h, yb)) / (2 * eps)
+        an = float((dg.double() * v.double()).sum())
+        assert abs(fd - an) <= 2e-3 * abs(an), (fd, an)
+        u = _t(rng.standard_normal(z.shape))
+        wu = M.dsnlm_forward(u, z, S, P, h)
+        lhs = float((dx.double() * u.double()).sum())
+        rhs = float((yb.double() * wu.double()).sum())
+        assert abs(lhs - rhs) <= 1e-5 * float(dx.double().abs().sum()), (lhs, rhs)
+        dhf = (loss(z, x, h + 1e-3, yb) - loss(z, x, h - 1e-3, yb)) / 2e-3
+        print(f"  guide {an:.6g} vs fd {fd:.6g}; x {lhs:.8g} vs {rhs:.8g}; h {float(dh.cpu()):.6g} vs fd {dhf:.6g}",
+              flush=True)
+        assert abs(float(dh.cpu()) - dhf) <= 2e-3 * abs(dhf), (float(dh.cpu()), dhf)
