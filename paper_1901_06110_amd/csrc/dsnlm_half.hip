@@ -437,8 +437,17 @@ k_half_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __r
         }
     }
     if constexpr (MODE == kPassBApply || MODE == kPassBBuild) {
+        // one atomic per block: wave maxima, then the block's in LDS
+        __shared__ unsigned long long wmax[4];
         best = wave_max_u64_h(best);
-        if ((threadIdx.x & 63) == 0 && best != 0ull) atomicMax(d.key, best);
+        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = best;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long b = wmax[0];
+#pragma unroll
+            for (int w = 1; w < 4; ++w) b = wmax[w] > b ? wmax[w] : b;
+            if (b != 0ull) atomicMax(d.key, b);
+        }
     }
 }
 
