@@ -67,7 +67,6 @@ enum SweepMode : int {
     kPassBBuild = 2,   // delta and the key only
     kApply = 3,        // B' only (weights already built)
     kPassC = 4,        // backward: sum a t_r, sum a w_r
-    kPassD = 5,        // backward: guide and bandwidth gradients (dsnlm_sweep_d.hip)
     kNLM = 6,          // plain NLM (eq. NLM): sums of k and k x, no hat (half window only)
 };
 
