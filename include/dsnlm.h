@@ -30,7 +30,10 @@
  *      (index -1 -> 0, n -> n-1), which needs P < min(n1, n2);
  *   h  bandwidth: k_{s,r} = exp(-||P_s - P_r||^2 / (2 (2P+1)^2 h^2));
  *      must be finite and > 0.
- *   Supported: 0 <= S <= 24, 0 <= P <= 5.
+ *   Supported: 0 <= S <= 24, 0 <= P <= 5; dsnlm_build_weights, dsnlm_apply,
+ *   dsnlm_forward and dsnlm_forward_brute also take 5 < P <= 15 (patch sides
+ *   up to 31, Table 1's range) through slower full-window passes; the other
+ *   entry points return DSNLM_EUNSUPPORTED for P > 5.
  * The weights are Lambda_{s,r} k_{s,r} with the separable hat
  * Lambda = (1 - |r1-s1|/(S+1)) (1 - |r2-s2|/(S+1)) (step S1), normalised
  * symmetrically by the row sums (step S2) and scaled by the largest

@@ -27,18 +27,23 @@ int check_hip(hipError_t e, const char* what) {
     return e == hipErrorOutOfMemory ? DSNLM_ENOMEM : DSNLM_EDEVICE;
 }
 
-// Validate the denoiser arguments shared by every build/apply entry point.
-int check_denoiser_args(int n1, int n2, int S, int P, float h, const char* who) {
+// Validate the denoiser arguments shared by every build/apply entry point
+// (pmax: the largest patch half-width the entry point serves).
+int check_denoiser_args_p(int n1, int n2, int S, int P, float h, const char* who, int pmax) {
     std::string w(who);
     if (n1 < 1 || n2 < 1) return fail(DSNLM_EINVAL, w + ": image must be at least 1x1");
     if (S < 0 || P < 0) return fail(DSNLM_EINVAL, w + ": S and P must be >= 0");
     if (P >= n1 || P >= n2) return fail(DSNLM_EINVAL, w + ": P must be < min(n1, n2)");
     if (!std::isfinite(h) || !(h > 0.f)) return fail(DSNLM_EINVAL, w + ": h must be finite and > 0");
-    if (S > kMaxS || P > kMaxP)
-        return fail(DSNLM_EUNSUPPORTED, w + ": this build supports S <= 24 and P <= 5");
+    if (S > kMaxS || P > pmax)
+        return fail(DSNLM_EUNSUPPORTED, w + ": this entry point supports S <= 24 and P <= " + std::to_string(pmax));
     if ((long long)n1 * n2 > (1LL << 31) - 1)
         return fail(DSNLM_EUNSUPPORTED, w + ": images above 2^31-1 pixels are not supported");
     return DSNLM_OK;
+}
+
+int check_denoiser_args(int n1, int n2, int S, int P, float h, const char* who) {
+    return check_denoiser_args_p(n1, n2, S, P, h, who, kMaxP);
 }
 
 bool overlaps(const void* a, const void* b, size_t bytes) {
@@ -55,7 +60,7 @@ ImgDesc base_desc(const dsnlm_weights* w) {
     d.bp = w->bp;
     d.key = w->key;
     d.part = w->part;
-    d.zpad = w->part ? half_zpad(w->part, w->n1, w->n2, w->S) : nullptr;
+    d.zpad = w->part ? half_zpad(w->part, w->n1, w->n2, w->S, w->P) : nullptr;
     d.n1 = w->n1;
     d.n2 = w->n2;
     const double np = 2.0 * w->P + 1.0;
@@ -131,7 +136,7 @@ void dsnlm_weights_destroy(dsnlm_weights* w) {
 int dsnlm_build_weights(const float* guide, int n1, int n2, int S, int P, float h, void* stream,
                         dsnlm_weights** out) {
     if (!guide || !out) return fail(DSNLM_EINVAL, "dsnlm_build_weights: null pointer");
-    int rc = check_denoiser_args(n1, n2, S, P, h, "dsnlm_build_weights");
+    int rc = check_denoiser_args_p(n1, n2, S, P, h, "dsnlm_build_weights", kMaxPWide);
     if (rc) return rc;
     rc = prepare_handle(n1, n2, S, P, h, out);
     if (rc) return rc;
@@ -194,7 +199,7 @@ int dsnlm_nlm(const float* guide, const float* x, float* y, int n1, int n2, int 
 int dsnlm_forward_brute(const float* guide, const float* x, float* y, int n1, int n2, int S, int P, float h,
                         void* stream, dsnlm_weights** out) {
     if (!guide || !x || !y) return fail(DSNLM_EINVAL, "dsnlm_forward_brute: null pointer");
-    int rc = check_denoiser_args(n1, n2, S, P, h, "dsnlm_forward_brute");
+    int rc = check_denoiser_args_p(n1, n2, S, P, h, "dsnlm_forward_brute", kMaxPWide);
     if (rc) return rc;
     const size_t bytes = (size_t)n1 * n2 * sizeof(float);
     if (overlaps(x, y, bytes) || overlaps(guide, y, bytes))
@@ -223,7 +228,7 @@ int dsnlm_forward_brute(const float* guide, const float* x, float* y, int n1, in
 int dsnlm_forward(const float* guide, const float* x, float* y, int n1, int n2, int S, int P,
                   float h, void* stream, dsnlm_weights** out) {
     if (!guide || !x || !y) return fail(DSNLM_EINVAL, "dsnlm_forward: null pointer");
-    int rc = check_denoiser_args(n1, n2, S, P, h, "dsnlm_forward");
+    int rc = check_denoiser_args_p(n1, n2, S, P, h, "dsnlm_forward", kMaxPWide);
     if (rc) return rc;
     const size_t bytes = (size_t)n1 * n2 * sizeof(float);
     if (overlaps(x, y, bytes) || overlaps(guide, y, bytes))

@@ -114,7 +114,7 @@ extern "C" int dsnlm_forward_batched(const dsnlm_image* imgs, int count, int S, 
         d.bp = g_ws.arrays + 2 * total + off;
         d.key = g_ws.keys + k;
         d.part = g_ws.part + part_off;
-        d.zpad = half_zpad(d.part, im.n1, im.n2, S);
+        d.zpad = half_zpad(d.part, im.n1, im.n2, S, P);
         part_off += half_part_floats(im.n1, im.n2, S, P);
         d.n1 = im.n1;
         d.n2 = im.n2;

@@ -531,6 +531,8 @@ extern "C" int dsnlm_apply_backward(const dsnlm_weights* wc, const float* x, con
     dsnlm_weights* w = const_cast<dsnlm_weights*>(wc);
     if (!w->applied)
         return fail(DSNLM_EINVAL, "dsnlm_apply_backward: the handle holds no forward to differentiate");
+    if (w->P > kMaxP)
+        return fail(DSNLM_EUNSUPPORTED, "dsnlm_apply_backward: the backward supports P <= 5");
     if ((dguide || dh) && !sweep_d2_fits(w->S, w->P))
         return fail(DSNLM_EUNSUPPORTED, "dsnlm_apply_backward: guide/bandwidth gradients need S <= 24");
     const size_t bytes = (size_t)w->n1 * w->n2 * sizeof(float);

@@ -23,6 +23,7 @@
 // d = 0 term, and finishes the pass exactly as the full-window sweep does.
 // The sums are the same as the full window's, up to the order of the FP32
 // additions.
+#include <algorithm>
 #include <cmath>
 
 #include "internal.h"
@@ -550,18 +551,21 @@ hipError_t half_p(int mode, int S, int P, const ImgDesc& one, const ImgDesc* bat
 
 }  // namespace
 
-size_t half_part_floats(int n1, int n2, int S, int P) {
+// floats before the mirrored guide: the half-window partial regions, or for
+// wide patches the wide passes' group sums if those are larger
+static size_t part_regions(int n1, int n2, int S, int P) {
     const size_t tiles = (size_t)((n1 + 31) / 32) * ((n2 + 63) / 64);
-    const size_t regions = tiles * (size_t)(32 + S) * (64 + 2 * S) * 2;
-    const size_t m = (size_t)S + P;
-    return ((regions + 63) & ~(size_t)63) + (n1 + 2 * m) * (n2 + 2 * m) + 64;
+    size_t regions = tiles * (size_t)(32 + S) * (64 + 2 * S) * 2;
+    if (P > kMaxP) regions = std::max(regions, wide_part_floats(n1, n2, S));
+    return (regions + 63) & ~(size_t)63;
 }
 
-float* half_zpad(float* part, int n1, int n2, int S) {
-    const size_t tiles = (size_t)((n1 + 31) / 32) * ((n2 + 63) / 64);
-    const size_t regions = tiles * (size_t)(32 + S) * (64 + 2 * S) * 2;
-    return part + ((regions + 63) & ~(size_t)63);
+size_t half_part_floats(int n1, int n2, int S, int P) {
+    const size_t m = (size_t)S + P;
+    return part_regions(n1, n2, S, P) + (n1 + 2 * m) * (n2 + 2 * m) + 64;
 }
+
+float* half_zpad(float* part, int n1, int n2, int S, int P) { return part + part_regions(n1, n2, S, P); }
 
 bool half_lds_fits(int S, int P, int mode) {
     size_t f = 0;

@@ -576,6 +576,7 @@ hipError_t launch_sweep(int mode, int S, int P, const ImgDesc& one, const ImgDes
                      : (mode == kPassBApply || mode == kPassBBuild) ? DSNLM_K_PASS_B
                      : mode == kApply ? DSNLM_K_APPLY
                                       : DSNLM_K_PASS_C;
+    if (P > kMaxP) return batch ? hipErrorInvalidValue : launch_wide(mode, S, P, one, st);
     if (one.part && half_mode_ok(mode) && sweep_variant(mode, S, P) == kHalfVariant && half_lds_fits(S, P, mode))
         return launch_half(mode, S, P, one, batch, tiles, ntiles, st);  // times its kernels itself
     ProfScope prof(kind, st);

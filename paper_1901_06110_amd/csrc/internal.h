@@ -11,7 +11,8 @@
 namespace dsnlm {
 
 constexpr int kMaxS = 24;
-constexpr int kMaxP = 5;
+constexpr int kMaxP = 5;       // the register-resident sweeps (every entry point)
+constexpr int kMaxPWide = 15;  // forward, build, apply and brute force (dsnlm_wide.hip)
 
 // log2 of one factor of the separable hat of step S1, for offsets -S..S.
 struct HatTable {
@@ -102,12 +103,21 @@ hipError_t launch_epilogue(const ImgDesc& one, const ImgDesc* batch, const TileR
 // Lead pad (float2 entries) before the backward's (t, w) pair array.
 constexpr int kFacLead = 32;
 size_t half_part_floats(int n1, int n2, int S, int P);  // partial regions + mirrored guide
-float* half_zpad(float* part, int n1, int n2, int S);   // the mirrored guide inside it
+float* half_zpad(float* part, int n1, int n2, int S, int P);  // the mirrored guide inside it
 bool half_lds_fits(int S, int P, int mode);
 bool half_mode_ok(int mode);
 hipError_t launch_half(int mode, int S, int P, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
                        int ntiles, hipStream_t st);
 hipError_t prepare_half(int S, int P);
+
+// Wide patches, kMaxP < P <= kMaxPWide (dsnlm_wide.hip): single-image passes
+// A, B (both forms) and apply; launch_sweep routes such P here.
+// The dy range of the window is split into wide_groups() groups whose
+// per-pixel sums go to d.part (wide_part_floats() floats).
+bool wide_fits(int S, int P);
+int wide_groups(int n1, int n2, int S);
+size_t wide_part_floats(int n1, int n2, int S);
+hipError_t launch_wide(int mode, int S, int P, const ImgDesc& d, hipStream_t st);
 
 // Brute-force DSG-NLM (dsnlm_brute.hip): c, delta, B' and the key of d from
 // directly summed patch distances; d.zpad must hold room for the mirrored

@@ -4,10 +4,11 @@ The paper times a 256 x 256 image with a fixed window N_s = 21 and patch
 sides N_p = 11, 17, 23, 29 (Table 1), on a CPU.  Here both implementations run
 on the GPU: the brute-force comparator sums every patch distance over its N_p^2
 offsets (`dsnlm_forward_brute`), the fast path uses box sums whose cost does
-not depend on N_p (`dsnlm_forward`).  The window is taken both ways the paper
-can be read: 21 x 21 (S = 10) and 43 x 43 (S = 21).  This build supports patch
-half-widths P <= 5, so N_p runs over 3, 5, 7, 9, 11 (11 is the paper's first
-value).  Each time is the median of 20 runs after 3 warm-ups, inputs resident.
+not depend on N_p (`dsnlm_forward`: the register-resident half-window sweeps
+for P <= 5, the wide-patch passes for P > 5).  The window is taken both ways
+the paper can be read: 21 x 21 (S = 10) and 43 x 43 (S = 21).  N_p runs over
+3, 5, 7, 9, 11 and the paper's 17, 23, 29.  Each fast time is the median of 20
+runs after 3 warm-ups, each brute-force time the median of 5; inputs resident.
 Usage: python -m paper_1901_06110_amd.table1
 """
 from __future__ import annotations
@@ -50,7 +51,7 @@ def main() -> None:
     y = torch.empty_like(x)
     rows = []
     for S in (10, 21):
-        for P in (1, 2, 3, 4, 5):
+        for P in (1, 2, 3, 4, 5, 8, 11, 14):
             h = 0.1
             _, w = M.dsnlm_forward(x, None, S, P, h, y=y, keep=True)
             fast = _median_ms(lambda: M.dsnlm_forward(x, None, S, P, h, y=y, weights=w))

@@ -66,4 +66,4 @@ def test_unsupported_sizes_reported(lib):
     hp = C.c_void_p()
     fake = C.c_void_p(0x1000)
     assert lib.dsnlm_build_weights(fake, 64, 64, 25, 1, 0.1, None, C.byref(hp)) == -5
-    assert lib.dsnlm_build_weights(fake, 64, 64, 3, 6, 0.1, None, C.byref(hp)) == -5
+    assert lib.dsnlm_build_weights(fake, 64, 64, 3, 16, 0.1, None, C.byref(hp)) == -5
