@@ -130,6 +130,7 @@ void dsnlm_weights_destroy(dsnlm_weights* w) {
     (void)hipFree(w->scratch);
     (void)hipFree(w->bscratch);
     (void)hipFree(w->part);
+    (void)hipFree(w->gpart);
     delete w;
 }
 

@@ -111,7 +111,7 @@ k_half_pad(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __rest
 template <int P, int S_CLASS, int MODE, bool BATCH>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(MODE == kPassA && P < 5 ? 6 : 1)))
 k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__ tiles, int S,
-       HatTable hat) {
+       HatTable hat, int ngrp) {
     // window length by measurement on gfx950 (pass A: 15, the others: 11; at
     // S = 10 either covers every dy of a dx in one group)
     using G = HGeo<P, S_CLASS, MODE == kPassA ? 15 : 11>;
@@ -135,8 +135,13 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
         d = one;
         ti0 = blockIdx.y * TH;
         tj0 = blockIdx.x * TW;
-        first = blockIdx.x == 0 && blockIdx.y == 0;
+        first = blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0;
     }
+    // dx group of this block (a single-image launch may split the half
+    // window's dx range over blockIdx.z; each group has its own regions)
+    const int grp = BATCH ? 0 : (int)blockIdx.z;
+    const int dxlo = BATCH ? -S : -S + grp * (2 * S + 1) / ngrp;
+    const int dxhi = BATCH ? S + 1 : -S + (grp + 1) * (2 * S + 1) / ngrp;  // exclusive
     const int n1 = d.n1, n2 = d.n2;
     const int AH = TH + S, AWr = TW + 2 * S;
     float* Vb = lds;
@@ -228,6 +233,7 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
     constexpr int NW = NE + GW - 1;
     int t = 0;
     for (int dx = -S; dx <= S; ++dx) {
+        if (dx < dxlo || dx >= dxhi) continue;  // another group's (uniform)
         const int dylo = dx > 0 ? 0 : 1;  // the half window
         for (int dy0 = dylo; dy0 <= S; dy0 += GW) {
             float win[NW];
@@ -333,7 +339,9 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
     __syncthreads();
     const size_t reg = (size_t)AH * AWr;
     const int lt = local_tile(ti0, tj0, n2, TH, TW);
-    float* part = d.part + (size_t)lt * reg * half_np(MODE);
+    const size_t ntl = (size_t)((n1 + TH - 1) / TH) * ((n2 + TW - 1) / TW);
+    float* part = (grp == 0 ? d.part : d.gpart + (grp - 1) * ntl * reg * half_np(MODE)) +
+                  (size_t)lt * reg * half_np(MODE);
     for (int idx = tid; idx < AH * AWr; idx += NT) {
         const int r = idx / AWr, q = idx - r * AWr;
         if constexpr (NC == 1) {
@@ -359,7 +367,8 @@ __device__ __forceinline__ unsigned long long wave_max_u64_h(unsigned long long 
 // adds the d = 0 term and finishes the pass.
 template <int MODE, bool BATCH>
 __global__ void __launch_bounds__(256)
-k_half_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__ tiles, int S) {
+k_half_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__ tiles, int S,
+              int ngrp) {
     constexpr int TH = 32, TW = 64;
     constexpr int NP = half_np(MODE);
     ImgDesc d;
@@ -380,6 +389,7 @@ k_half_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __r
     const int ntx = (n2 + TW - 1) / TW;
     const int lt = (ti0 / TH) * ntx + tj0 / TW;
     const int tx = tj0 / TW;
+    const size_t ntl = (size_t)((n1 + TH - 1) / TH) * ntx;
     unsigned long long best = 0ull;
     for (int e = threadIdx.x; e < TH * TW; e += 256) {
         const int li = e / TW, lj = e - li * TW;
@@ -388,12 +398,15 @@ k_half_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __r
         float s0 = 0.f, s1 = 0.f;
         auto add = [&](int tile, int r, int q) {
             const size_t o = (size_t)tile * reg + (size_t)r * AWr + q;
-            if constexpr (NP == 1) {
-                s0 += d.part[o];
-            } else {
-                const float2 v = reinterpret_cast<const float2*>(d.part)[o];
-                s0 += v.x;
-                s1 += v.y;
+            for (int g = 0; g < ngrp; ++g) {  // the dx groups, in order
+                const float* src = g == 0 ? d.part : d.gpart + (g - 1) * ntl * reg * NP;
+                if constexpr (NP == 1) {
+                    s0 += src[o];
+                } else {
+                    const float2 v = reinterpret_cast<const float2*>(src)[o];
+                    s0 += v.x;
+                    s1 += v.y;
+                }
             }
         };
         const bool left = tx > 0 && lj < S, right = tx + 1 < ntx && lj >= TW - S;
@@ -489,6 +502,8 @@ hipError_t launch_half_one(int S, const ImgDesc& one, const ImgDesc* batch, cons
     hipError_t ea = half_attr<P, S_CLASS, MODE, BATCH>();
     if (ea != hipSuccess) return ea;
     const dim3 grid = BATCH ? dim3(ntiles) : dim3((one.n2 + G::TW - 1) / G::TW, (one.n1 + G::TH - 1) / G::TH);
+    const int ngrp = (BATCH || one.groups < 2 || !one.gpart) ? 1 : std::min(one.groups, 2 * S + 1);
+    const dim3 sgrid(grid.x, grid.y, ngrp);
     HatTable hat = make_hat(S);
     if constexpr (MODE == kNLM)
         for (float& v : hat.lg) v = 0.f;  // eq. NLM has no hat
@@ -504,13 +519,13 @@ hipError_t launch_half_one(int S, const ImgDesc& one, const ImgDesc* batch, cons
                              : MODE == kApply ? DSNLM_K_APPLY
                                               : DSNLM_K_PASS_C;
         ProfScope prof(kind, st);
-        hipLaunchKernelGGL((k_half<P, S_CLASS, MODE, BATCH>), grid, dim3(G::NT), lds, st, one, batch, tiles, S,
-                           hat);
+        hipLaunchKernelGGL((k_half<P, S_CLASS, MODE, BATCH>), sgrid, dim3(G::NT), lds, st, one, batch, tiles, S,
+                           hat, ngrp);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     ProfScope prof(DSNLM_K_HALF_AUX, st);
-    hipLaunchKernelGGL((k_half_gather<MODE, BATCH>), grid, dim3(256), 0, st, one, batch, tiles, S);
+    hipLaunchKernelGGL((k_half_gather<MODE, BATCH>), grid, dim3(256), 0, st, one, batch, tiles, S, ngrp);
     return hipGetLastError();
 }
 
@@ -558,6 +573,18 @@ static size_t part_regions(int n1, int n2, int S, int P) {
     size_t regions = tiles * (size_t)(32 + S) * (64 + 2 * S) * 2;
     if (P > kMaxP) regions = std::max(regions, wide_part_floats(n1, n2, S));
     return (regions + 63) & ~(size_t)63;
+}
+
+int half_split_groups(int n1, int n2, int S) {
+    // two groups when the image has fewer tiles than the 256 CUs can hold
+    // twice over: measured on the 512 x 512 solver, more groups gain nothing
+    const int tiles = ((n1 + 31) / 32) * ((n2 + 63) / 64);
+    return (tiles < 512 && S > 0) ? 2 : 1;
+}
+
+size_t half_group_floats(int n1, int n2, int S, int groups) {
+    const size_t tiles = (size_t)((n1 + 31) / 32) * ((n2 + 63) / 64);
+    return groups > 1 ? (size_t)(groups - 1) * tiles * (32 + S) * (64 + 2 * S) * 2 : 0;
 }
 
 size_t half_part_floats(int n1, int n2, int S, int P) {

@@ -40,6 +40,8 @@ struct ImgDesc {
     float* hpart;          // sweep D output: per-block partial sums for dh
     float* part;           // half-window sweeps: per-tile partner-region partial sums
     float* zpad;           // half-window sweeps: the guide mirrored into a margin of S + P
+    float* gpart;          // half-window sweeps split into `groups` dx groups (single image):
+    int groups;            // partial regions of groups 1.. (group 0 uses part); 0 or 1: no split
     int n1, n2;
     float beta;            // log2(e) / (2 (2P+1)^2 h^2)
     float kappa;           // 1 / (2 (2P+1)^2 h^2)
@@ -103,6 +105,11 @@ hipError_t launch_epilogue(const ImgDesc& one, const ImgDesc* batch, const TileR
 // Lead pad (float2 entries) before the backward's (t, w) pair array.
 constexpr int kFacLead = 32;
 size_t half_part_floats(int n1, int n2, int S, int P);  // partial regions + mirrored guide
+// A single-image sweep may split the half window's dx range over `groups`
+// blocks per tile (ImgDesc::groups, ::gpart), which fills the GPU for a small
+// image; the result then differs from the unsplit one by summation order.
+int half_split_groups(int n1, int n2, int S);                       // the split used by the solver
+size_t half_group_floats(int n1, int n2, int S, int groups);        // floats of ImgDesc::gpart
 float* half_zpad(float* part, int n1, int n2, int S, int P);  // the mirrored guide inside it
 bool half_lds_fits(int S, int P, int mode);
 bool half_mode_ok(int mode);
@@ -191,5 +198,7 @@ struct dsnlm_weights {
     size_t bscratch_cap;
     float* part;       // partial buffer of the half-window sweeps (grow-only)
     size_t part_cap;
+    float* gpart;      // partial regions of the solver's extra dx groups (grow-only)
+    size_t gpart_cap;
     bool applied;      // bp holds B' of the last apply
 };
