@@ -36,7 +36,7 @@ def _case(n1, n2, seed, sep_guide=True):
 
 CASES = [(32, 32, 7, 3, 0.1), (29, 41, 3, 1, 0.08), (40, 24, 5, 2, 0.12), (33, 70, 10, 3, 0.1),
          (12, 12, 6, 2, 0.15), (40, 70, 16, 2, 0.1), (28, 30, 18, 2, 0.12), (26, 30, 13, 4, 0.12),
-         (24, 26, 14, 5, 0.15)]
+         (24, 26, 14, 5, 0.15), (20, 37, 3, 0, 0.1), (1, 40, 2, 0, 0.1), (3, 45, 4, 1, 0.1)]
 
 
 @pytest.mark.parametrize("n1,n2,S,P,h", CASES)
