@@ -180,7 +180,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the batch would shard image by image; see the design notes)", file=sys.stderr)
+              "(a batch would shard image by image across GPUs, with no communication)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
