@@ -179,7 +179,7 @@ def main():
     ap.add_argument("--no-fb", action="store_true", help="skip the forward+backward timing")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: this library has no multi-GPU path "
               "(a batch would shard image by image across GPUs, with no communication)", file=sys.stderr)
         sys.exit(2)
 

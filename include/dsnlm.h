@@ -58,7 +58,7 @@ typedef enum {
     DSNLM_ENOMEM = -2,      /* device allocation failed                      */
     DSNLM_EDEVICE = -3,     /* the HIP runtime reported an error             */
     DSNLM_ENONFINITE = -4,  /* a solver produced a non-finite residual       */
-    DSNLM_EUNSUPPORTED = -5 /* valid per the paper but outside this build    */
+    DSNLM_EUNSUPPORTED = -5 /* valid per the paper but outside this library  */
 } dsnlm_status;
 
 typedef struct dsnlm_weights dsnlm_weights;
