@@ -415,8 +415,11 @@ int enqueue_denoise_dual(const ladmm_params* p, int k, dsnlm_weights* w, float* 
     float* z = w->zbuf;
     ImgDesc d = base_desc(w);
     d.x = z;
-    d.gpart = w->gpart;  // the solver's sweeps split the half window (ensure_solver_scratch)
-    d.groups = w->gpart ? half_split_groups(w->n1, w->n2, p->S) : 1;
+    // the solver's sweeps split the half window (buffer from ensure_solver_scratch)
+    const int groups = half_split_groups(w->n1, w->n2, p->S);
+    const bool split = w->gpart && w->gpart_cap >= half_group_floats(w->n1, w->n2, p->S, groups);
+    d.gpart = split ? w->gpart : nullptr;
+    d.groups = split ? groups : 1;
     int rc;
     if (p->denoiser == 1) {
         // plain NLM of z guided by z: writes its increment into B' and m = 1
@@ -675,6 +678,9 @@ int ladmm_step(const ladmm_operator* op, const ladmm_params* p, int k, dsnlm_wei
         return fail(DSNLM_EINVAL, "ladmm_step: frozen iteration without built weights");
     if (*w && ((*w)->n1 != op->n1 || (*w)->n2 != op->n2))
         return fail(DSNLM_EINVAL, "ladmm_step: weights built for another image size");
+    // frozen iterations reuse the handle's buffers, sized for its S and P
+    if (!adaptive && ((*w)->S != p->S || (*w)->P != p->P))
+        return fail(DSNLM_EINVAL, "ladmm_step: frozen iteration with S or P other than the weights'");
     if (adaptive) {
         rc = prepare_handle(op->n1, op->n2, p->S, p->P, h, w);
         if (rc) return rc;

@@ -170,6 +170,11 @@ def test_solve_equals_steps_and_checkpoints():
     assert abs(r[-1, 0] - float(xv.pow(2).mean().sqrt())) <= 1e-6 + 1e-4 * r[-1, 0]
     dv = (ck[-1, 1] - ck[-2, 1]).double()
     assert abs(r[-1, 1] - float(dv.pow(2).mean().sqrt())) <= 1e-6 + 1e-4 * r[-1, 1]
+    # a frozen step must use the weights' own S and P (their buffers are sized for them)
+    prm2 = M.LadmmParams(lam=1e-2, rho=1.0, gamma=1.0 / 0.3321609, S=S + 2, P=P, h=0.05,
+                         freeze_after=k0, iters=iters)
+    with pytest.raises(M.api._lib.DsnlmError):
+        M.ladmm_step(op, prm2, iters + 1, w, x2, v2, u2)
 
 
 def test_frozen_weights_converge_to_fixed_point():
