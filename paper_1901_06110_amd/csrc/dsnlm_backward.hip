@@ -289,7 +289,7 @@ bool overlaps(const void* a, const void* b, size_t bytes);
 // Scratch (floats) needed by dsnlm_apply_backward for an n1 x n2 image.
 size_t backward_scratch_floats(int n1, int n2, int S, int P) {
     const size_t n = (size_t)n1 * n2;
-    const size_t tiles = (size_t)((n1 + 31) / 32) * ((n2 + 63) / 64);
+    const size_t tiles = (size_t)((n1 + 31) / 32) * ((n2 + 63) / 64) * sweep_d2_groups(n1, n2, S);
     return 2 * (size_t)kFacLead + 2 * n + 2 * n + aux4_floats(n) + (size_t)(n1 + 2 * P) * (n2 + 2 * P) +
            blocks256(n) + tiles + 8 + sweep_d2_part_floats(n1, n2, S, P);
 }
@@ -304,7 +304,8 @@ int enqueue_backward(dsnlm_weights* w, const float* x, const float* dy, float* d
     float* gz = aux5 + aux4_floats(n);
     float* partials = gz + (size_t)(n1 + 2 * P) * (n2 + 2 * P);
     const int nb = blocks256(n);
-    const int nd = ((n1 + 31) / 32) * ((n2 + 63) / 64);  // sweep-D tiles (one partial of hbar each)
+    // sweep-D blocks (tiles x dx groups), one partial of hbar each
+    const int nd = ((n1 + 31) / 32) * ((n2 + 63) / 64) * sweep_d2_groups(n1, n2, S);
     float* hpart = partials + nb;
     float* mbar = hpart + nd;
     float* dpart = mbar + 8;  // sweep-D partial regions

@@ -78,7 +78,8 @@ __device__ __forceinline__ int reflect_d(int k, int n) {
 
 template <int P, int S_CLASS, bool BATCH>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
-k_d2(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__ tiles, int S, HatTable hat) {
+k_d2(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__ tiles, int S, HatTable hat,
+     int ngrp) {
     using G = DGeo<P, S_CLASS>;
     constexpr int NT = G::NT, TH = G::TH, TW = G::TW, R = G::R, L = G::L;
     constexpr int ZC = G::ZC, VW = G::VW, DBW = G::DBW, VBW = G::VBW, RWc = G::RWc;
@@ -320,7 +321,14 @@ k_d2(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__
     constexpr int GW = G::GW;
     constexpr int NW = NE + GW - 1;
     int t = 0, pdy = 0, pdx = 0;
+    // a single-image launch may split the dx range over blockIdx.z (a small
+    // image would leave CUs idle); each group writes its own region and hbar
+    // partial, and the gather adds the groups in order
+    const int grp = BATCH ? 0 : (int)blockIdx.z;
+    const int dxlo = BATCH ? -S : -S + grp * (2 * S + 1) / ngrp;
+    const int dxhi = BATCH ? S + 1 : -S + (grp + 1) * (2 * S + 1) / ngrp;
     for (int dx = -S; dx <= S; ++dx) {
+        if (dx < dxlo || dx >= dxhi) continue;  // another group's (uniform)
         for (int dy0 = dx > 0 ? 0 : 1; dy0 <= S; dy0 += GW) {
             float win[NW];
             {
@@ -374,7 +382,7 @@ k_d2(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__
     }
     __syncthreads();
     const int ntx = (n2 + TW - 1) / TW;
-    const int lt = (ti0 / TH) * ntx + tj0 / TW;
+    const int lt = ((ti0 / TH) * ntx + tj0 / TW) * ngrp + grp;  // (tile, group)
     float* part = d.dpart + (size_t)lt * RH * RWr;
     for (int idx = tid; idx < RH * RWr; idx += NT) {
         const int r = idx / RWr, q = idx - r * RWr;
@@ -397,7 +405,8 @@ k_d2(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__
 // map[b] = (image, block of 256 padded-grid pixels).
 template <bool BATCH>
 __global__ void __launch_bounds__(256)
-k_d2_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const int2* __restrict__ map, int S, int P) {
+k_d2_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const int2* __restrict__ map, int S, int P,
+            int ngrp) {
     constexpr int TH = 32, TW = 64;
     ImgDesc d;
     int e;
@@ -426,7 +435,8 @@ k_d2_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const int2* __restri
     for (int ty = ty0; ty <= ty1; ++ty)
         for (int tx = tx0; tx <= tx1; ++tx) {
             const int r = qi - ty * TH + P, c = qj - tx * TW + P + S;
-            acc += d.dpart[(size_t)(ty * ntx + tx) * reg + (size_t)r * RWr + c];
+            for (int g = 0; g < ngrp; ++g)
+                acc += d.dpart[((size_t)(ty * ntx + tx) * ngrp + g) * reg + (size_t)r * RWr + c];
         }
     d.gz[e] = 2.f * acc;
 }
@@ -444,8 +454,11 @@ hipError_t launch_d2_one(int S, const ImgDesc& one, const ImgDesc* batch, const 
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    const dim3 grid = BATCH ? dim3(ntiles) : dim3((one.n2 + G::TW - 1) / G::TW, (one.n1 + G::TH - 1) / G::TH);
-    hipLaunchKernelGGL((k_d2<P, S_CLASS, BATCH>), grid, dim3(G::NT), lds, st, one, batch, tiles, S, make_hat(S));
+    const int ngrp = BATCH ? 1 : sweep_d2_groups(one.n1, one.n2, S);
+    const dim3 grid = BATCH ? dim3(ntiles)
+                            : dim3((one.n2 + G::TW - 1) / G::TW, (one.n1 + G::TH - 1) / G::TH, ngrp);
+    hipLaunchKernelGGL((k_d2<P, S_CLASS, BATCH>), grid, dim3(G::NT), lds, st, one, batch, tiles, S, make_hat(S),
+                       ngrp);
     return hipGetLastError();
 }
 
@@ -490,9 +503,17 @@ bool sweep_d2_fits(int S, int P) {
     return S <= kMaxS && f * sizeof(float) <= 160 * 1024;
 }
 
+int sweep_d2_groups(int n1, int n2, int S) {
+    // up to two blocks per CU on 256 CUs, at most 8 groups, at least one dx each
+    const int tiles = ((n1 + 31) / 32) * ((n2 + 63) / 64);
+    int g = (512 + tiles - 1) / tiles;
+    g = g > 8 ? 8 : g;
+    return g < 1 ? 1 : (g > 2 * S + 1 ? 2 * S + 1 : g);
+}
+
 size_t sweep_d2_part_floats(int n1, int n2, int S, int P) {
     const size_t tiles = (size_t)((n1 + 31) / 32) * ((n2 + 63) / 64);
-    return tiles * (size_t)(32 + 2 * P + S) * (64 + 2 * P + 2 * S);
+    return tiles * sweep_d2_groups(n1, n2, S) * (size_t)(32 + 2 * P + S) * (64 + 2 * P + 2 * S);
 }
 
 hipError_t launch_sweep_d2(int S, int P, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles, int ntiles,
@@ -506,10 +527,11 @@ hipError_t launch_d2_gather(int S, int P, const ImgDesc& one, const ImgDesc* bat
                             hipStream_t st) {
     ProfScope prof(DSNLM_K_BWD_TAIL, st);
     if (batch) {
-        hipLaunchKernelGGL((k_d2_gather<true>), dim3(nblocks), dim3(256), 0, st, one, batch, map, S, P);
+        hipLaunchKernelGGL((k_d2_gather<true>), dim3(nblocks), dim3(256), 0, st, one, batch, map, S, P, 1);
     } else {
         const int np = (one.n1 + 2 * P) * (one.n2 + 2 * P);
-        hipLaunchKernelGGL((k_d2_gather<false>), dim3((np + 255) / 256), dim3(256), 0, st, one, batch, map, S, P);
+        hipLaunchKernelGGL((k_d2_gather<false>), dim3((np + 255) / 256), dim3(256), 0, st, one, batch, map, S, P,
+                           sweep_d2_groups(one.n1, one.n2, S));
     }
     return hipGetLastError();
 }

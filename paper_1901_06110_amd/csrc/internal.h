@@ -137,8 +137,11 @@ hipError_t launch_brute(const ImgDesc& d, int S, int P, hipStream_t st);
 // the gather sums the covering regions into gz on the padded grid.  The
 // tile list of a batch launch is the forward's; d.hpart gets one entry per
 // forward tile of the image.
+// A single-image launch splits the dx range into sweep_d2_groups() groups
+// (partial regions and hbar partials per (tile, group)); a batch uses one.
 bool sweep_d2_fits(int S, int P);
-size_t sweep_d2_part_floats(int n1, int n2, int S, int P);
+int sweep_d2_groups(int n1, int n2, int S);
+size_t sweep_d2_part_floats(int n1, int n2, int S, int P);  // for the single-image groups
 hipError_t launch_sweep_d2(int S, int P, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles, int ntiles,
                            hipStream_t st);
 // map[b] = (image, block of 256 padded-grid pixels) for a batch launch
