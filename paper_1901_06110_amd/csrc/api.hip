@@ -61,6 +61,12 @@ ImgDesc base_desc(const dsnlm_weights* w) {
     d.key = w->key;
     d.part = w->part;
     d.zpad = w->part ? half_zpad(w->part, w->n1, w->n2, w->S, w->P) : nullptr;
+    // a small image splits each tile's dx range over several blocks
+    const int groups = half_split_groups(w->n1, w->n2, w->S);
+    if (groups > 1 && w->gpart && w->gpart_cap >= half_group_floats(w->n1, w->n2, w->S, groups)) {
+        d.gpart = w->gpart;
+        d.groups = groups;
+    }
     d.n1 = w->n1;
     d.n2 = w->n2;
     const double np = 2.0 * w->P + 1.0;
@@ -102,6 +108,15 @@ int prepare_handle(int n1, int n2, int S, int P, float h, dsnlm_weights** out) {
         int rc = check_hip(hipMalloc(&w->part, need * sizeof(float)), "hipMalloc partial buffer");
         if (rc) return rc;
         w->part_cap = need;
+    }
+    const size_t gneed = half_group_floats(n1, n2, S, half_split_groups(n1, n2, S));
+    if (w->gpart_cap < gneed) {
+        (void)hipFree(w->gpart);
+        w->gpart = nullptr;
+        w->gpart_cap = 0;
+        int rc = check_hip(hipMalloc(&w->gpart, gneed * sizeof(float)), "hipMalloc group regions");
+        if (rc) return rc;
+        w->gpart_cap = gneed;
     }
     w->S = S;
     w->P = P;

@@ -22,7 +22,6 @@
 // forms Dbar_{s,d} in LDS, box-sums it over the patch and scatters zbar.
 #include <algorithm>
 #include <cmath>
-#include <cstdint>
 #include <cstring>
 #include <vector>
 
@@ -292,7 +291,7 @@ size_t backward_scratch_floats(int n1, int n2, int S, int P) {
     const size_t n = (size_t)n1 * n2;
     const size_t tiles = (size_t)((n1 + 31) / 32) * ((n2 + 63) / 64) * sweep_d2_groups(n1, n2, S);
     return 2 * (size_t)kFacLead + 2 * n + 2 * n + aux4_floats(n) + (size_t)(n1 + 2 * P) * (n2 + 2 * P) +
-           blocks256(n) + tiles + 8 + 4 + sweep_d2_part_floats(n1, n2, S, P);
+           blocks256(n) + tiles + 8 + sweep_d2_part_floats(n1, n2, S, P);
 }
 
 int enqueue_backward(dsnlm_weights* w, const float* x, const float* dy, float* dx, float* dguide, float* dh,
@@ -309,9 +308,7 @@ int enqueue_backward(dsnlm_weights* w, const float* x, const float* dy, float* d
     const int nd = ((n1 + 31) / 32) * ((n2 + 63) / 64) * sweep_d2_groups(n1, n2, S);
     float* hpart = partials + nb;
     float* mbar = hpart + nd;
-    // sweep-D partial regions (16-byte aligned: before sweep D they hold the
-    // float2 regions of sweep C's second dx group)
-    float* dpart = reinterpret_cast<float*>((reinterpret_cast<uintptr_t>(mbar + 8) + 15) & ~(uintptr_t)15);
+    float* dpart = mbar + 8;  // sweep-D partial regions
 
     BwdArgs a{};
     a.x = x;
@@ -340,18 +337,7 @@ int enqueue_backward(dsnlm_weights* w, const float* x, const float* dy, float* d
     d.x = x;
     d.aux_in = pairs;
     d.aux_out = cw;
-    {
-        // a small image splits sweep C's dx range too, its extra group's
-        // regions in the (not yet used) sweep-D region buffer
-        const int groups = half_split_groups(n1, n2, S);
-        if (groups > 1 && half_group_floats(n1, n2, S, groups) <= sweep_d2_part_floats(n1, n2, S, P)) {
-            d.gpart = dpart;
-            d.groups = groups;
-        }
-    }
     int rc = check_hip(launch_sweep(kPassC, S, P, d, nullptr, nullptr, 0, st), "backward sweep C");
-    d.gpart = nullptr;
-    d.groups = 1;
     if (rc) return rc;
     {
         ProfScope prof(DSNLM_K_BWD_PREP, st);

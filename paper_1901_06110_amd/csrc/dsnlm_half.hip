@@ -576,10 +576,12 @@ static size_t part_regions(int n1, int n2, int S, int P) {
 }
 
 int half_split_groups(int n1, int n2, int S) {
-    // two groups when the image has fewer tiles than the 256 CUs can hold
-    // twice over: measured on the 512 x 512 solver, more groups gain nothing
+    // enough blocks for two tiles per CU on 256 CUs, at most kSplitCap groups
+    constexpr int kSplitCap = 4;
     const int tiles = ((n1 + 31) / 32) * ((n2 + 63) / 64);
-    return (tiles < 512 && S > 0) ? 2 : 1;
+    int g = (512 + tiles - 1) / tiles;
+    g = g > kSplitCap ? kSplitCap : g;
+    return g < 1 ? 1 : (g > 2 * S + 1 ? 2 * S + 1 : g);
 }
 
 size_t half_group_floats(int n1, int n2, int S, int groups) {

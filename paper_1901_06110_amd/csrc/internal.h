@@ -105,10 +105,11 @@ hipError_t launch_epilogue(const ImgDesc& one, const ImgDesc* batch, const TileR
 // Lead pad (float2 entries) before the backward's (t, w) pair array.
 constexpr int kFacLead = 32;
 size_t half_part_floats(int n1, int n2, int S, int P);  // partial regions + mirrored guide
-// A single-image sweep may split the half window's dx range over `groups`
-// blocks per tile (ImgDesc::groups, ::gpart), which fills the GPU for a small
-// image; the result then differs from the unsplit one by summation order.
-int half_split_groups(int n1, int n2, int S);                       // the split used by the solver
+// A single-image sweep splits the half window's dx range over `groups` blocks
+// per tile (ImgDesc::groups, ::gpart, set by base_desc from the handle), which
+// fills the GPU for a small image; batch launches never split, so a batched
+// result differs from the single-image one by summation order only.
+int half_split_groups(int n1, int n2, int S);
 size_t half_group_floats(int n1, int n2, int S, int groups);        // floats of ImgDesc::gpart
 float* half_zpad(float* part, int n1, int n2, int S, int P);  // the mirrored guide inside it
 bool half_lds_fits(int S, int P, int mode);
@@ -201,7 +202,7 @@ struct dsnlm_weights {
     size_t bscratch_cap;
     float* part;       // partial buffer of the half-window sweeps (grow-only)
     size_t part_cap;
-    float* gpart;      // partial regions of the solver's extra dx groups (grow-only)
+    float* gpart;      // partial regions of the extra dx groups (grow-only)
     size_t gpart_cap;
     bool applied;      // bp holds B' of the last apply
 };

@@ -415,11 +415,6 @@ int enqueue_denoise_dual(const ladmm_params* p, int k, dsnlm_weights* w, float* 
     float* z = w->zbuf;
     ImgDesc d = base_desc(w);
     d.x = z;
-    // the solver's sweeps split the half window (buffer from ensure_solver_scratch)
-    const int groups = half_split_groups(w->n1, w->n2, p->S);
-    const bool split = w->gpart && w->gpart_cap >= half_group_floats(w->n1, w->n2, p->S, groups);
-    d.gpart = split ? w->gpart : nullptr;
-    d.groups = split ? groups : 1;
     int rc;
     if (p->denoiser == 1) {
         // plain NLM of z guided by z: writes its increment into B' and m = 1
@@ -622,17 +617,6 @@ int ensure_solver_scratch(dsnlm_weights* w, const OpView& ov, const ladmm_operat
     w->zbuf = base;
     *lr = base + n;
     *partials = base + n + mlr;
-    // regions of the extra dx group of the solver's sweeps
-    const int S = w->S;
-    const size_t gneed = half_group_floats(op->n1, op->n2, S, half_split_groups(op->n1, op->n2, S));
-    if (gneed > w->gpart_cap) {
-        (void)hipFree(w->gpart);
-        w->gpart = nullptr;
-        w->gpart_cap = 0;
-        rc = check_hip(hipMalloc(&w->gpart, gneed * sizeof(float)), "solver group regions");
-        if (rc) return rc;
-        w->gpart_cap = gneed;
-    }
     return DSNLM_OK;
 }
 

@@ -140,8 +140,9 @@ def test_full_size_512_matches_oracle():
 
 
 def test_batched_equals_per_image_and_oracle():
-    """One launch per sweep over uneven images gives exactly the per-image
-    result (same tiles, same accumulation order), and each image matches the
+    """One launch per sweep over uneven images gives the per-image result (same
+    tiles; a small single image splits each tile's shifts over several blocks,
+    so the two differ by summation order only), and each image matches the
     oracle with its own m and h."""
     M = _gpu()
     shapes = [(64, 128), (33, 17), (128, 64), (7, 200), (96, 96), (3, 50)]
@@ -155,20 +156,20 @@ def test_batched_equals_per_image_and_oracle():
     torch.cuda.synchronize()
     for (x, h), xt, y in zip(items, xs, ys):
         y1 = M.dsnlm_forward(xt, None, S, P, h)
-        assert torch.equal(y, y1)
+        assert float((y - y1).abs().max()) <= 2e-6
         yo = _oracle(x, x, S, P, h)[0]
         assert np.abs(y.cpu().numpy() - yo).max() <= TOL
     # a second call with a different batch re-uses the workspace
     ys2 = M.dsnlm_forward_batched([(xs[1], xs[1], 0.07), (xs[0], xs[0], 0.09)], S, P)
-    assert torch.equal(ys2[0], M.dsnlm_forward(xs[1], None, S, P, 0.07))
-    assert torch.equal(ys2[1], M.dsnlm_forward(xs[0], None, S, P, 0.09))
+    assert float((ys2[0] - M.dsnlm_forward(xs[1], None, S, P, 0.07)).abs().max()) <= 2e-6
+    assert float((ys2[1] - M.dsnlm_forward(xs[0], None, S, P, 0.09)).abs().max()) <= 2e-6
     assert M.dsnlm_forward_batched([], S, P) == []
 
 
 def test_batched_full_config_properties():
     """The 64-image batch the bench times (S = 10, P = 3): every output keeps
     the image sum and stays inside [min x, max x]; two sampled images match
-    the per-image launches bit for bit."""
+    the per-image launches up to summation order (2e-6)."""
     M = _gpu()
     batch = synth.config2_batch()
     xs = [_t(it.noisy) for it in batch]
@@ -180,4 +181,4 @@ def test_batched_full_config_properties():
         assert abs(float(yd.sum() - xd.sum())) <= 2e-6 * x.numel()
         assert float(y.min()) >= float(x.min()) - 1e-6 and float(y.max()) <= float(x.max()) + 1e-6
     for k in (0, 5):
-        assert torch.equal(ys[k], M.dsnlm_forward(xs[k], None, 10, 3, batch[k].h))
+        assert float((ys[k] - M.dsnlm_forward(xs[k], None, 10, 3, batch[k].h)).abs().max()) <= 2e-6
