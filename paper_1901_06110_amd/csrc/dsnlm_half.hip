@@ -247,6 +247,9 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
                 const int dy = dy0 + g;
                 if (dy <= S) {
                     float* V = Vb + (t & 1) * (TH * VW);
+                    // read here, so that the scalar load has returned by the
+                    // barrier and no wait for it holds up the LDS reads after it
+                    const float lg = hat.lg[dy + S] + hat.lg[dx + S];
                     // phase 1: vertical sliding box of (z(p) - z(p+d))^2
                     if (has1) {
                         float tq[NE];
@@ -278,7 +281,15 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
                             vv[4 * q + 3] = t4.w;
                         }
                     }
-                    const float lg = hat.lg[dy + S] + hat.lg[dx + S];
+                    // the partner entries, read before the weights so that
+                    // the exponentials cover the read latency (the entries
+                    // of one shift are distinct across the block)
+                    const int pr = own + dy * AW + dx;  // partner entry of output 0
+                    float4 pv[NC == 4 ? L : 1];
+                    if constexpr (NC == 4) {
+#pragma unroll
+                        for (int k = 0; k < L; ++k) pv[k] = reinterpret_cast<const float4*>(Acc)[pr + k];
+                    }
                     float hs = vv[0];
 #pragma unroll
                     for (int q = 1; q <= 2 * P; ++q) hs += vv[q];
@@ -300,7 +311,6 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
                             a[k] = ok ? a[k] : 0.f;
                         }
                     }
-                    const int pr = own + dy * AW + dx;  // partner entry of output 0
                     if constexpr (NC == 1) {
 #pragma unroll
                         for (int k = 0; k < L; ++k) {
@@ -311,7 +321,7 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
 #pragma unroll
                         for (int k = 0; k < L; ++k) {
                             float4* e = reinterpret_cast<float4*>(Acc) + pr + k;
-                            const float4 v = *e;
+                            const float4 v = pv[k];
                             acc0[k] = fmaf(a[k], v.x, acc0[k]);
                             acc1[k] = fmaf(a[k], v.y, acc1[k]);
                             reinterpret_cast<float2*>(e)[1] =
