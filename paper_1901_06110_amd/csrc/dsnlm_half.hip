@@ -231,13 +231,35 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
     constexpr int NV = ((L + 2 * P + 3) / 4) * 4;
     constexpr int GW = G::GWIN;
     constexpr int NW = NE + GW - 1;
+    // The shifted rows of a group of shifts (one dx, GW consecutive dy) are
+    // loaded one group ahead, so their latency is spent on the group before;
+    // pass A (registers capped) and patches above 7x7 (past 128 registers,
+    // one tile per CU) have none to spare and load each group's rows at its
+    // start.
+    constexpr bool PF = MODE != kPassA && P <= 3;
+    float nwin[PF ? NW : 1];
+    if constexpr (PF) {
+        const int zw = zbase + (dxlo > 0 ? 0 : 1) * W2 + dxlo;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) nwin[q] = __builtin_bit_cast(float, zload(zw + q * W2));
+    }
     int t = 0;
     for (int dx = -S; dx <= S; ++dx) {
         if (dx < dxlo || dx >= dxhi) continue;  // another group's (uniform)
         const int dylo = dx > 0 ? 0 : 1;  // the half window
         for (int dy0 = dylo; dy0 <= S; dy0 += GW) {
             float win[NW];
-            {
+            if constexpr (PF) {
+#pragma unroll
+                for (int q = 0; q < NW; ++q) win[q] = nwin[q];
+                // the next group; past the last one this is an unused read,
+                // inside the range-checked buffer
+                const int ndx = dy0 + GW <= S ? dx : dx + 1;
+                const int ndy0 = dy0 + GW <= S ? dy0 + GW : (ndx > 0 ? 0 : 1);
+                const int zw = zbase + ndy0 * W2 + ndx;
+#pragma unroll
+                for (int q = 0; q < NW; ++q) nwin[q] = __builtin_bit_cast(float, zload(zw + q * W2));
+            } else {
                 const int zw = zbase + dy0 * W2 + dx;
 #pragma unroll
                 for (int q = 0; q < NW; ++q) win[q] = __builtin_bit_cast(float, zload(zw + q * W2));
