@@ -8,7 +8,7 @@ both sides read is `synth`, which draws the seeded inputs.
 Modules
 -------
 dsnlm_ref  -- the doubly stochastic NLM denoiser (Section 3, eqs. NLM, S1-S3,
-              Algorithm 2), three independent routes.
+              Algorithm 2), two independent routes.
 ladmm_ref  -- forward models (Section 4.1 eq. dataterm, Section 4.2 eqs. obj and
               photongrad) and Algorithm 1 (Section 2).
 grad_ref   -- finite-difference and FP64-autograd reference gradients.

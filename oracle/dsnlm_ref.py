@@ -19,20 +19,21 @@ What is computed (Section 3 of the paper):
 * step S3: with m the largest row sum after S2, w <- w/m and then the diagonal
   w_ss <- 1 + w_ss - sum_r w_sr (the sum includes the diagonal term, which
   makes every row sum exactly one);
-* output W x.  Algorithm 2 computes the same product with three aggregation
-  loops over (pixel, window) pairs without storing W.
+* output W x.  Algorithm 2 computes the same product without storing W.
 
-Three independent routes are provided:
+Two independent routes are provided:
 
 dense_weights / dsnlm_dense -- build the n x n matrices of eqs. S1-S3 literally
-                               (tiny images only);
-dsnlm_alg2                  -- Algorithm 2's three loops in plain Python (tiny);
-dsnlm_shifts                -- Algorithm 2's three loops with the pixel loop
-                               vectorised (torch CPU float64, differentiable),
-                               the window loop kept as a Python loop over the
-                               (2S+1)^2 shifts, patch distances summed directly
-                               over the N_p^2 patch offsets (brute force, no
-                               box-sum trick).  This is the route used for GPU
+                               (tiny images only; patches cut from numpy's
+                               symmetric padding);
+dsnlm_shifts                -- the same matrices evaluated one window shift at
+                               a time: for a shift d the entries (s, s+d) of
+                               every matrix form one band, computed for all
+                               pixels s at once (torch CPU float64,
+                               differentiable), with the patch distances summed
+                               directly over the N_p^2 patch offsets (no
+                               box-sum trick) and the mirror indexing of
+                               sym_index.  This is the route used for GPU
                                parity and for the CPU baseline.
 """
 from __future__ import annotations
@@ -48,7 +49,6 @@ __all__ = [
     "hat",
     "dense_weights",
     "dsnlm_dense",
-    "dsnlm_alg2",
     "dsnlm_shifts",
     "check_args",
 ]
@@ -136,80 +136,7 @@ def dsnlm_dense(x, z, S: int, P: int, h: float) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# Route 2: Algorithm 2 in plain Python loops.
-# ---------------------------------------------------------------------------
-def _refl(k: int, n: int) -> int:
-    """Half-sample symmetric reflection of index k into [0, n) (|k| < 2n)."""
-    if k < 0:
-        return -k - 1
-    if k >= n:
-        return 2 * n - 1 - k
-    return k
-
-
-def _kernel_py(zl, n1, n2, i, j, r, q, P, h):
-    """k_{s,r} of eq. NLM for s = (i, j), r = (r, q), patches read from the
-    guide through the mirror reflection (written independently of np.pad)."""
-    Np = 2 * P + 1
-    d = 0.0
-    for ty in range(-P, P + 1):
-        for tx in range(-P, P + 1):
-            e = (zl[_refl(i + ty, n1)][_refl(j + tx, n2)]
-                 - zl[_refl(r + ty, n1)][_refl(q + tx, n2)])
-            d += e * e
-    return math.exp(-d / (2.0 * Np * Np * h * h))
-
-
-def dsnlm_alg2(x, z, S: int, P: int, h: float) -> np.ndarray:
-    """Algorithm 2 with its three aggregation loops written out (tiny images).
-
-    Loop 1 accumulates the image g of row sums of Lambda*k; loop 2 accumulates
-    (g_s g_r)^(-1/2) Lambda k per pixel and keeps the maximum m; loop 3 forms
-    w = m^-1 (g_s g_r)^(-1/2) Lambda k, accumulates w x_r and w, and finally adds
-    (1 - sum w) x_s.
-    """
-    x = np.asarray(x, dtype=np.float64)
-    z = np.asarray(z, dtype=np.float64)
-    n1, n2 = z.shape
-    check_args(n1, n2, S, P, h)
-    zl = z.tolist()
-    xl = x.tolist()
-
-    def window(i, j):
-        for r in range(max(0, i - S), min(n1, i + S + 1)):
-            for q in range(max(0, j - S), min(n2, j + S + 1)):
-                yield r, q
-
-    def lam(i, j, r, q):
-        return hat(i - r, S) * hat(j - q, S)
-
-    g = [[0.0] * n2 for _ in range(n1)]
-    for i in range(n1):
-        for j in range(n2):
-            for r, q in window(i, j):
-                g[i][j] += lam(i, j, r, q) * _kernel_py(zl, n1, n2, i, j, r, q, P, h)
-    m = 0.0
-    for i in range(n1):
-        for j in range(n2):
-            delta = 0.0
-            for r, q in window(i, j):
-                delta += (g[i][j] * g[r][q]) ** -0.5 * lam(i, j, r, q) * _kernel_py(zl, n1, n2, i, j, r, q, P, h)
-            m = max(m, delta)
-    y = [[0.0] * n2 for _ in range(n1)]
-    for i in range(n1):
-        for j in range(n2):
-            acc = 0.0
-            hs = 0.0
-            for r, q in window(i, j):
-                w = (g[i][j] * g[r][q]) ** -0.5 * lam(i, j, r, q) * _kernel_py(zl, n1, n2, i, j, r, q, P, h) / m
-                acc += w * xl[r][q]
-                hs += w
-            y[i][j] = acc + (1.0 - hs) * xl[i][j]
-    return np.asarray(y)
-
-
-# ---------------------------------------------------------------------------
-# Route 3: Algorithm 2 vectorised over pixels, loop over shifts (torch, FP64).
+# Route 2: the matrices of S1-S3 band by band (one band per window shift).
 # ---------------------------------------------------------------------------
 def _as_t(a) -> torch.Tensor:
     if isinstance(a, torch.Tensor):
@@ -223,12 +150,17 @@ def _shift_ranges(n: int, d: int):
 
 
 def dsnlm_shifts(x, z, S: int, P: int, h, want: str = "y") -> dict:
-    """DSG-NLM by Algorithm 2's three passes, pixels vectorised (torch FP64).
+    """y = W(z) x from the matrices of steps S1-S3, one window shift at a time
+    (torch FP64).
 
+    For a shift d = (dy, dx) the entries (s, s + d) of Lambda*K form one band
+    of the matrix; it is computed for every pixel s at once.  The row sums of
+    step S1 (omega), of step S2 (delta) and the product with the matrix of
+    step S3 are accumulated band by band.
     x, z: 2-D arrays or tensors (cast to float64; autograd flows through them
     and through h when they are tensors that require grad).
-    Returns a dict with y (= W x), omega (loop-1 image g), delta (loop-2 row
-    sums), m (their maximum), argmax (flat index of the first maximal delta,
+    Returns a dict with y (= W x), omega (row sums after S1), delta (row sums
+    after S2), m (their maximum), argmax (flat index of the first maximal delta,
     which is where the derivative of the max is routed; the paper does not
     differentiate, so ties are broken towards the lowest index).
     """
@@ -260,7 +192,7 @@ def dsnlm_shifts(x, z, S: int, P: int, h, want: str = "y") -> dict:
 
     shifts = [(dy, dx) for dy in range(-S, S + 1) for dx in range(-S, S + 1)]
 
-    # loop 1: g_s = sum_r Lambda k
+    # step S1 row sums: omega_s = sum_r Lambda k
     omega = torch.zeros((n1, n2), dtype=torch.float64)
     for dy, dx in shifts:
         wres = weight(dy, dx)
@@ -268,7 +200,7 @@ def dsnlm_shifts(x, z, S: int, P: int, h, want: str = "y") -> dict:
             continue
         (i0, i1, j0, j1), a = wres
         omega[i0:i1, j0:j1] += a
-    # loop 2: delta_s = sum_r (g_s g_r)^-1/2 Lambda k
+    # step S2 (column sums equal row sums by symmetry): delta_s = sum_r (omega_s omega_r)^-1/2 Lambda k
     delta = torch.zeros((n1, n2), dtype=torch.float64)
     for dy, dx in shifts:
         wres = weight(dy, dx)
@@ -284,7 +216,8 @@ def dsnlm_shifts(x, z, S: int, P: int, h, want: str = "y") -> dict:
     out = dict(omega=omega, delta=delta, m=m, argmax=am)
     if want == "weights":
         return out
-    # loop 3: y_s = sum_r w x_r + (1 - sum_r w) x_s, w = m^-1 (g_s g_r)^-1/2 Lambda k
+    # step S3: off-diagonal w = m^-1 (omega_s omega_r)^-1/2 Lambda k, diagonal 1 minus the rest of
+    # the row, so (W x)_s = sum_r w x_r + (1 - sum_r w) x_s with r = s inside both sums
     acc = torch.zeros((n1, n2), dtype=torch.float64)
     hs = torch.zeros((n1, n2), dtype=torch.float64)
     for dy, dx in shifts:

@@ -7,8 +7,8 @@ The paper does not differentiate its denoiser; the gradients here follow from
 the forward definition (Section 3, eqs. NLM and S1-S3) by the chain rule.
 Two independent references are provided:
 
-* `autograd_grads` -- torch CPU float64 autograd through the shift-loop route
-  of Algorithm 2 (dsnlm_ref.dsnlm_shifts); the derivative of the maximum row
+* `autograd_grads` -- torch CPU float64 autograd through the band-by-band
+  route of steps S1-S3 (dsnlm_ref.dsnlm_shifts); the derivative of the maximum row
   sum is routed to the first maximal pixel;
 * `central_fd`     -- central finite differences of the same FP64 forward.
 """
@@ -77,20 +77,6 @@ def spi_grad_torch(t, ones, K, eta, t_min=1e-6):
     K0 = K - K1
     a = eta * t / K
     return (eta / K) * (K0 - K1 * torch.exp(-a) / (-torch.expm1(-a)))
-
-
-def sr_forward_torch(x, taps, factor, boundary="symmetric"):
-    from .ladmm_ref import pad_index
-    taps = torch.as_tensor(np.asarray(taps, dtype=np.float64))
-    n1, n2 = x.shape
-    size = taps.numel()
-    r = (size - 1) // 2
-    xp = x[torch.as_tensor(pad_index(n1, r, boundary))][:, torch.as_tensor(pad_index(n2, r, boundary))]
-    out = torch.zeros((n1, n2), dtype=torch.float64)
-    for a in range(size):
-        for b in range(size):
-            out = out + taps[a] * taps[b] * xp[a:a + n1, b:b + n2]
-    return out[::factor, ::factor]
 
 
 def unrolled_ladmm_torch(x0, grad_f, *, alpha, rho, lam, S, P, iters, freeze_after, lo=0.0, hi=1.0,

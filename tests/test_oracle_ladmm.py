@@ -37,6 +37,41 @@ def test_periodic_norm_closed_form():
     assert abs(pw - expect) <= 1e-9
 
 
+def test_gaussian_taps_width():
+    """The sampled Gaussian of Section 4.1 (9 taps, sigma_b = 1) has discrete
+    variance sum k^2 b_k = sigma_b^2 up to its truncated tails: by Poisson
+    summation a unit-spaced sampled Gaussian with sigma >= 1 keeps its
+    variance within ~2e-7, and the taps beyond |k| = 4 carry ~1e-4 of it.
+    A kernel written with k^2 / sigma^2 instead of k^2 / (2 sigma^2) has
+    variance 1/2 and fails."""
+    for sigma in (1.0, 1.5):
+        size = 9 if sigma == 1.0 else 15
+        b = L.gaussian_taps(size, sigma)
+        k = np.arange(size) - (size - 1) // 2
+        assert abs(b.sum() - 1.0) <= 1e-15
+        assert np.abs(b - b[::-1]).max() == 0.0
+        var = float((k * k * b).sum())
+        assert abs(var - sigma * sigma) <= 2e-3 * sigma * sigma
+    # without truncation (sigma = 1, |k| <= 40) Poisson summation gives the
+    # variance sigma^2 (1 - 8 pi^2 sigma^2 exp(-2 pi^2 sigma^2)) to the next
+    # alias term, exp(-8 pi^2) ~ 1e-34
+    b = L.gaussian_taps(81, 1.0)
+    k = np.arange(81) - 40
+    expect = 1.0 - 8 * math.pi ** 2 * math.exp(-2 * math.pi ** 2)
+    assert abs(float((k * k * b).sum()) - expect) <= 1e-12
+
+
+@pytest.mark.parametrize("boundary,expect", [("symmetric", 0.3321609007), ("periodic", 0.2501035003)])
+def test_sr_operator_norm_values(boundary, expect):
+    """||A||_2^2 of the super-resolution operator of Section 4.1 (9 x 9
+    Gaussian, sigma_b = 1, decimation by 2 at phase 0), as measured
+    independently for the workload's description: 0.3321609007 with the
+    half-sample mirror boundary, 0.2501035003 periodic, the same at n = 32
+    and 64."""
+    A = L.sr_dense((32, 32), L.gaussian_taps(9, 1.0), 2, boundary)
+    assert abs(np.linalg.norm(A, 2) ** 2 - expect) <= 1e-9
+
+
 def test_symmetric_norm_power_iteration_vs_svd():
     A = L.sr_dense((24, 24), TAPS, 2, "symmetric")
     svd = np.linalg.norm(A, 2) ** 2
