@@ -33,7 +33,10 @@
  *   Supported: 0 <= S <= 24, 0 <= P <= 5; dsnlm_build_weights, dsnlm_apply,
  *   dsnlm_forward and dsnlm_forward_brute also take 5 < P <= 15 (patch sides
  *   up to 31, Table 1's range) through slower full-window passes; the other
- *   entry points return DSNLM_EUNSUPPORTED for P > 5.
+ *   entry points return DSNLM_EUNSUPPORTED for P > 5.  Images are limited
+ *   to 2^28 pixels, and so is the image padded by S + P on every side
+ *   (the kernels index elements with 32-bit offsets): larger ones return
+ *   DSNLM_EUNSUPPORTED before anything is launched.
  * The weights are Lambda_{s,r} k_{s,r} with the separable hat
  * Lambda = (1 - |r1-s1|/(S+1)) (1 - |r2-s2|/(S+1)) (step S1), normalised
  * symmetrically by the row sums (step S2) and scaled by the largest

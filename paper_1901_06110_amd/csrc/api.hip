@@ -37,8 +37,10 @@ int check_denoiser_args_p(int n1, int n2, int S, int P, float h, const char* who
     if (!std::isfinite(h) || !(h > 0.f)) return fail(DSNLM_EINVAL, w + ": h must be finite and > 0");
     if (S > kMaxS || P > pmax)
         return fail(DSNLM_EUNSUPPORTED, w + ": this entry point supports S <= 24 and P <= " + std::to_string(pmax));
-    if ((long long)n1 * n2 > (1LL << 31) - 1)
-        return fail(DSNLM_EUNSUPPORTED, w + ": images above 2^31-1 pixels are not supported");
+    const long long m = (long long)S + P;
+    if ((long long)n1 * n2 > kMaxPixels || ((long long)n1 + 2 * m) * ((long long)n2 + 2 * m) > kMaxPixels)
+        return fail(DSNLM_EUNSUPPORTED,
+                    w + ": the image, or the image padded by S + P on each side, exceeds 2^28 pixels");
     return DSNLM_OK;
 }
 

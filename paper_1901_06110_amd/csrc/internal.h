@@ -13,6 +13,11 @@ namespace dsnlm {
 constexpr int kMaxS = 24;
 constexpr int kMaxP = 5;       // the register-resident sweeps (every entry point)
 constexpr int kMaxPWide = 15;  // forward, build, apply and brute force (dsnlm_wide.hip)
+// Largest image, and largest guide padded by S + P on every side, in pixels.
+// The kernels form element offsets in 32-bit ints and scale them by at most 4
+// (float4 records, byte offsets of buffer loads), so 2^28 keeps every such
+// offset below 2^31.
+constexpr long long kMaxPixels = 1LL << 28;
 
 // log2 of one factor of the separable hat of step S1, for offsets -S..S.
 struct HatTable {

@@ -67,3 +67,20 @@ def test_unsupported_sizes_reported(lib):
     fake = C.c_void_p(0x1000)
     assert lib.dsnlm_build_weights(fake, 64, 64, 25, 1, 0.1, None, C.byref(hp)) == -5
     assert lib.dsnlm_build_weights(fake, 64, 64, 3, 16, 0.1, None, C.byref(hp)) == -5
+
+
+def test_images_past_the_32bit_offsets_refused(lib):
+    """An image of more than 2^28 pixels (or one whose guide padded by S + P
+    exceeds that) is refused on the host, single-image and batched, before
+    any device work: the kernels form element offsets in 32-bit ints."""
+    from paper_1901_06110_amd import _lib
+    hp = C.c_void_p()
+    fake = C.c_void_p(0x1000)
+    assert lib.dsnlm_build_weights(fake, 16385, 16384, 1, 1, 0.1, None, C.byref(hp)) == -5
+    assert lib.dsnlm_forward(fake, C.c_void_p(0x2000), C.c_void_p(1 << 40), 16384, 16384, 10, 3, 0.1,
+                             None, None) == -5
+    assert b"2^28" in lib.dsnlm_last_error()
+    arr = (_lib.DsnlmImage * 1)()
+    arr[0] = _lib.DsnlmImage(0x1000, 0x1000, 1 << 40, 1 << 15, 1 << 14, 0.1)
+    assert lib.dsnlm_forward_batched(arr, 1, 10, 3, None) == -5
+    assert not hp.value
