@@ -146,6 +146,15 @@ typedef struct {
  * (they share the workspace). */
 int dsnlm_forward_batched(const dsnlm_image* imgs, int count, int S, int P, void* stream);
 
+/* State of image `image` (0-based) of the LAST dsnlm_forward_batched call:
+ * device pointers to its c (row sums of step S1 to the power -1/2) and delta
+ * (row sums after step S2) inside the library's batch workspace (valid until
+ * the next batched call), and, copied to the host, its m and the flat index
+ * of the first pixel attaining it (this copy synchronises the stream).  Any
+ * output may be NULL.  DSNLM_EINVAL if there is no such image. */
+int dsnlm_batched_state(int image, float* m, int* argmax, const float** c, const float** delta,
+                        void* stream);
+
 /* Vector-Jacobian products of the LAST dsnlm_forward_batched call (same
  * images, same order; its inputs must be unchanged): per image, dy is the
  * cotangent of y and dx = W dy, dguide, dh (device scalar) are written; each

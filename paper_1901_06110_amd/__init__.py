@@ -17,6 +17,7 @@ from .api import (  # noqa: F401
     dsnlm_nlm,
     dsnlm_forward_brute,
     dsnlm_backward_batched,
+    dsnlm_batched_state,
     ladmm_apply_forward,
     ladmm_gradient,
     ladmm_operator_norm2,

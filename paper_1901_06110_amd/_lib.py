@@ -100,6 +100,7 @@ def _load():
         "dsnlm_weights_array": (vp, [vp, i]),
         "dsnlm_forward_batched": (i, [C.POINTER(DsnlmImage), i, i, i, vp]),
         "dsnlm_backward_batched": (i, [C.POINTER(DsnlmImageGrad), i, vp]),
+        "dsnlm_batched_state": (i, [i, C.POINTER(f), C.POINTER(i), pp, pp, vp]),
         "ladmm_step": (i, [C.POINTER(LadmmOperator), C.POINTER(LadmmParams), i, pp, vp, vp, vp, vp]),
         "ladmm_solve": (i, [C.POINTER(LadmmOperator), C.POINTER(LadmmParams), vp, vp, vp, vp, vp, vp]),
         "ladmm_apply_forward": (i, [C.POINTER(LadmmOperator), vp, vp, vp]),
@@ -145,7 +146,7 @@ EXPORTED = [
     "dsnlm_profile_enable", "dsnlm_profile_query", "dsnlm_profile_reset",
     "dsnlm_tune_set", "dsnlm_tune_get", "dsnlm_tune", "dsnlm_peak_probe",
     "ladmm_step_backward", "ladmm_solve_backward", "dsnlm_backward_batched", "dsnlm_nlm",
-    "dsnlm_forward_brute", "admm_cg_solve",
+    "dsnlm_forward_brute", "admm_cg_solve", "dsnlm_batched_state",
 ]
 
 K_PASS_A, K_PASS_B, K_APPLY, K_EPILOGUE, K_BWD_PREP, K_PASS_C, K_PASS_D, K_BWD_TAIL, K_LADMM, K_HALF_AUX = range(10)

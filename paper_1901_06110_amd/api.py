@@ -176,6 +176,21 @@ def dsnlm_forward_batched(images: Sequence, S: int, P: int, outs=None):
     return ys
 
 
+def dsnlm_batched_state(image: int):
+    """(m, argmax, c, delta) of one image of the last dsnlm_forward_batched
+    call; c and delta are copies of the library's device arrays.
+    Synchronises the stream."""
+    shape = tuple(_LAST_BATCH[image][1].shape)
+    m = C.c_float()
+    am = C.c_int()
+    cp = C.c_void_p()
+    dp = C.c_void_p()
+    _lib.check(_lib.get().dsnlm_batched_state(int(image), C.byref(m), C.byref(am), C.byref(cp), C.byref(dp),
+                                              _stream()))
+    return (float(m.value), int(am.value), _wrap_device(cp.value, shape).clone(),
+            _wrap_device(dp.value, shape).clone())
+
+
 def dsnlm_backward_batched(dys: Sequence, need_dx: bool = True, need_dguide: bool = True,
                            need_dh: bool = True):
     """Vector-Jacobian products of the last dsnlm_forward_batched call.

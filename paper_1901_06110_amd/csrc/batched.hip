@@ -167,6 +167,28 @@ extern "C" int dsnlm_forward_batched(const dsnlm_image* imgs, int count, int S, 
     return rc;
 }
 
+extern "C" int dsnlm_batched_state(int image, float* m, int* argmax, const float** c, const float** delta,
+                                   void* stream) {
+    std::lock_guard<std::mutex> lk(g_ws.mu);
+    if (image < 0 || image >= (int)g_ws.last_descs.size())
+        return fail(DSNLM_EINVAL, "dsnlm_batched_state: no such image in the last dsnlm_forward_batched");
+    const ImgDesc& d = g_ws.last_descs[image];
+    if (c) *c = d.c;
+    if (delta) *delta = d.delta;
+    if (!m && !argmax) return DSNLM_OK;
+    unsigned long long key = 0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int rc = check_hip(hipMemcpyAsync(&key, d.key, sizeof(key), hipMemcpyDeviceToHost, st), "copy key");
+    if (!rc) rc = check_hip(hipStreamSynchronize(st), "synchronise");
+    if (rc) return rc;
+    const unsigned bits = (unsigned)(key >> 32);
+    float mv;
+    std::memcpy(&mv, &bits, sizeof(mv));
+    if (m) *m = mv;
+    if (argmax) *argmax = (int)(~(unsigned)(key & 0xffffffffu));
+    return DSNLM_OK;
+}
+
 extern "C" int dsnlm_backward_batched(const dsnlm_image_grad* grads, int count, void* stream) {
     if (count < 0 || (count > 0 && !grads)) return fail(DSNLM_EINVAL, "dsnlm_backward_batched: bad arguments");
     std::lock_guard<std::mutex> lk(g_ws.mu);

@@ -114,11 +114,12 @@ def test_backward_c3_batch_shape_runs_and_is_deterministic():
             assert torch.equal(u, v)
 
 
-@pytest.mark.parametrize("S,P", [(7, 3), (4, 1), (10, 2), (16, 3)])
+@pytest.mark.parametrize("S,P", [(7, 3), (4, 1), (10, 2), (10, 3), (16, 3)])
 def test_batched_backward_matches_fp64_autograd(S, P):
     """One batched forward and backward over images of uneven sizes (several
     tiles and ragged tails): every image's gradients against the FP64
-    autograd reference, and against the single-image backward."""
+    autograd reference, and against the single-image backward.  S = 10,
+    P = 3 is the instance the bench's forward+backward times."""
     M = _M()
     shapes = [(32, 32, 0.1), (29, 71, 0.08), (70, 45, 0.12), (12, 12, 0.15)]
     imgs, refs = [], []

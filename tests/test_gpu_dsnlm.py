@@ -182,3 +182,35 @@ def test_batched_full_config_properties():
         assert float(y.min()) >= float(x.min()) - 1e-6 and float(y.max()) <= float(x.max()) + 1e-6
     for k in (0, 5):
         assert float((ys[k] - M.dsnlm_forward(xs[k], None, 10, 3, batch[k].h)).abs().max()) <= 2e-6
+
+
+def test_batched_bench_instance_matches_oracle():
+    """The batched kernels at the configuration the bench times (S = 10,
+    P = 3, h = 1.2 sigma_n, one launch per sweep over uneven images), on
+    shapes of that workload the oracle can afford plus a ragged one: every
+    pixel of every image, and each image's delta, m, argmax and c, against
+    the FP64 oracle (Algorithm 2; steps S1-S3)."""
+    M = _gpu()
+    shapes = [(64, 128), (128, 128), (128, 256), (192, 384), (256, 256), (100, 150)]
+    rng = np.random.default_rng(4242)
+    items = []
+    for k, (a, b) in enumerate(shapes):
+        sig = float(rng.uniform(0.02, 0.1))
+        _, x = synth.piecewise_smooth(a, b, 2100 + k, sig)
+        items.append((x, 1.2 * sig))
+    S, P = 10, 3
+    print(f"batched S=10 P=3 vs oracle: {shapes}", flush=True)
+    xs = [_t(x) for x, _ in items]
+    ys = M.dsnlm_forward_batched([(x, x, h) for x, (_, h) in zip(xs, items)], S, P)
+    torch.cuda.synchronize()
+    for k, ((x, h), y) in enumerate(zip(items, ys)):
+        yo, mo, amo, om, dl = _oracle(x, x, S, P, h)
+        err = np.abs(y.cpu().numpy() - yo).max()
+        assert err <= TOL, (k, err)
+        m, am, c, delta = M.dsnlm_batched_state(k)
+        assert abs(m - mo) <= 1e-5 * mo, (k, m, mo)
+        d = np.sort(dl.ravel())
+        if d[-1] - d[-2] > 1e-4 * d[-1]:
+            assert am == amo, (k, am, amo)
+        assert np.abs(delta.cpu().numpy() - dl).max() <= 2e-5
+        assert np.abs(c.cpu().numpy() / om ** -0.5 - 1).max() <= 2e-5
