@@ -226,10 +226,23 @@ int ladmm_step(const ladmm_operator* op, const ladmm_params* p, int k, dsnlm_wei
 /* Run p->iters iterations from (x, v, u) (device, in place).  residuals:
  * NULL or device [iters][2]: RMS of x - v and of rho (v_k - v_{k-1}) per
  * iteration.  checkpoints: NULL or device [iters][4][n1*n2]: x, v, u and the
- * denoiser input x + u after each iteration.  The iterations after the
- * weights freeze are captured once in a HIP graph and replayed.
- * Returns DSNLM_ENONFINITE (after the run) if a residual is not finite;
- * this check synchronises the stream when residuals is non-NULL. */
+ * denoiser input x + u after each iteration.
+ * All iterations (adaptive and frozen) are captured into one HIP graph the
+ * first time a combination of image size, operator kind, scalars and taps,
+ * params, and whether residuals and checkpoints are requested is seen on the
+ * current device, and the graph is replayed by later calls with the same
+ * combination (other buffers included).  The graph works on copies the
+ * library keeps for that combination -- x, v, u, the observation (y or
+ * ones), residuals, checkpoints -- which are copied from the caller's buffers
+ * before each replay and back after it (device-to-device copies).  Up to 4
+ * combinations are kept, each with its own weights and buffers (about 25 MiB
+ * at 512 x 512, S = 10, without checkpoints), least recently used dropped
+ * first.  The work runs on a library stream of the device that waits for the
+ * work already on `stream`, and `stream` waits for it, so ordering is as if it
+ * ran on `stream`.  Returns without synchronising when residuals is NULL; with
+ * residuals it synchronises and returns DSNLM_ENONFINITE if one is not
+ * finite.  `stream` must not be under
+ * capture (DSNLM_EINVAL): the call captures its own graph. */
 int ladmm_solve(const ladmm_operator* op, const ladmm_params* p, float* x, float* v, float* u,
                 float* residuals, float* checkpoints, void* stream);
 
@@ -255,7 +268,10 @@ int admm_cg_solve(const ladmm_operator* op, const ladmm_params* p, int cg_iters,
  * float[2], incremented by the explicit derivative with respect to rho and by
  * the derivative with respect to the bandwidth h.  The weights are rebuilt
  * from the guide (checkpointing: nothing per iteration is kept besides the
- * states).  Synchronous (frees its scratch). */
+ * states).  Returns without synchronising.  The library's reverse-pass
+ * workspace of the device (grow-only; allocated on first use and when a
+ * larger image arrives) is shared with ladmm_solve_backward, so calls of the
+ * two on one device must not overlap in time. */
 int ladmm_step_backward(const ladmm_operator* op, const ladmm_params* p, int k, const float* guide,
                         const float* x_prev, const float* v_prev, const float* u_prev,
                         const float* x_k, const float* z_k, float* xbar, float* vbar, float* ubar,
@@ -264,13 +280,19 @@ int ladmm_step_backward(const ladmm_operator* op, const ladmm_params* p, int k, 
 /* All iterations in reverse from the checkpoints written by ladmm_solve
  * ([iters][4][n1*n2]: x, v, u, z after each iteration) and the initial state
  * (x0, v0, u0).  xbar, vbar, ubar: adjoints of the final (x, v, u) on entry,
- * of (x0, v0, u0) on return.  dparams as in ladmm_step_backward (the caller
- * zeroes it).  With h <= 0 in the params (h = sqrt(lambda / rho)), the
- * derivatives follow as dL/dlambda = dparams[1] h / (2 lambda) and
- * dL/drho = dparams[0] - dparams[1] h / (2 rho).  Synchronous. */
+ * of (x0, v0, u0) on return.  dinit: NULL or device n1*n2, set to
+ * xbar + vbar, the adjoint of the initial image when the iterations start from
+ * x0 = v0 (u0 fixed), as Algorithm 1 does.  dparams: device float[4],
+ * overwritten: [0] the explicit derivative with respect to rho (x-steps),
+ * [1] the derivative with respect to the bandwidth h, [2] dL/dlambda,
+ * [3] dL/drho.  With h <= 0 in the params (h = sqrt(lambda / rho)),
+ * [2] = [1] h / (2 lambda) and [3] = [0] - [1] h / (2 rho); with h > 0,
+ * [2] = 0 and [3] = [0].  The weights of the frozen iterations are built once
+ * from z_{freeze_after}; each reverse step re-applies them to its z_k.
+ * Returns without synchronising; workspace as for ladmm_step_backward. */
 int ladmm_solve_backward(const ladmm_operator* op, const ladmm_params* p, const float* x0,
                          const float* v0, const float* u0, const float* checkpoints, float* xbar,
-                         float* vbar, float* ubar, float* dparams, void* stream);
+                         float* vbar, float* ubar, float* dinit, float* dparams, void* stream);
 
 /* out = A x (super-resolution operator only; out is the low-resolution
  * grid) -- used to synthesise observations and by tests. */
@@ -326,7 +348,8 @@ int dsnlm_tune(const float* guide, int n1, int n2, int S, int P, float h, int re
 /* Measured peak of one rate on the current device, used as a roofline
  * denominator: kind 0 = FP32 FMA throughput in FLOP/s (2 per FMA, non-packed
  * VALU), 1 = v_exp_f32 throughput in exp/s, 2 = HBM copy bandwidth in bytes/s
- * (1 GiB read + 1 GiB written per launch).  Synchronous; allocates 2 GiB for
+ * (1 GiB read + 1 GiB written per launch), 3 = LDS read bandwidth in bytes/s
+ * summed over the chip (conflict-free 16-byte reads).  Synchronous; allocates 2 GiB for
  * kind 2. */
 int dsnlm_peak_probe(int kind, double* rate, void* stream);
 

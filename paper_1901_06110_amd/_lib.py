@@ -108,7 +108,7 @@ def _load():
         "ladmm_step_backward": (i, [C.POINTER(LadmmOperator), C.POINTER(LadmmParams), i, vp, vp, vp, vp, vp,
                                     vp, vp, vp, vp, vp, vp, vp]),
         "ladmm_solve_backward": (i, [C.POINTER(LadmmOperator), C.POINTER(LadmmParams), vp, vp, vp, vp, vp,
-                                     vp, vp, vp, vp]),
+                                     vp, vp, vp, vp, vp]),
         "ladmm_gradient": (i, [C.POINTER(LadmmOperator), vp, vp, vp]),
         "ladmm_operator_norm2": (i, [C.POINTER(LadmmOperator), i, C.POINTER(f), vp]),
         "dsnlm_tune_set": (i, [i, i, i, i]),

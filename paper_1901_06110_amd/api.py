@@ -333,14 +333,17 @@ def ladmm_operator_norm2(op: SROperator, iters: int = 200) -> float:
     return float(val.value)
 
 
-def ladmm_solve_backward(op, params: LadmmParams, x0, v0, u0, checkpoints, xbar, vbar, ubar):
+def ladmm_solve_backward(op, params: LadmmParams, x0, v0, u0, checkpoints, xbar, vbar, ubar,
+                         dinit: Optional[torch.Tensor] = None):
     """Reverse pass through ladmm_solve's iterations (checkpoints from the
     forward).  xbar/vbar/ubar are updated in place to the adjoints of the
-    initial state; returns dparams = [explicit d/drho, d/dh] on the device."""
+    initial state; dinit (if given) receives xbar + vbar, the adjoint of an
+    initial image used as both x0 and v0.  Returns dparams on the device:
+    [explicit d/drho, d/dh, dL/dlambda, dL/drho]."""
     o = op.c_struct()
     p = params.c_struct()
-    dparams = torch.zeros(2, dtype=torch.float32, device=x0.device)
+    dparams = torch.empty(4, dtype=torch.float32, device=x0.device)
     _lib.check(_lib.get().ladmm_solve_backward(C.byref(o), C.byref(p), _p(x0), _p(v0), _p(u0),
-                                               _p(checkpoints), _p(xbar), _p(vbar), _p(ubar),
+                                               _p(checkpoints), _p(xbar), _p(vbar), _p(ubar), _p(dinit),
                                                _p(dparams), _stream()))
     return dparams

@@ -79,12 +79,11 @@ class UnrolledLADMM(torch.autograd.Function):
         vb = torch.zeros_like(xb)
         ub = torch.zeros_like(xb)
         zeros = torch.zeros_like(x0)
-        dp = api.ladmm_solve_backward(ctx.op, p, x0, x0, zeros, ck, xb, vb, ub).double()
-        h = (p.lam / p.rho) ** 0.5
-        dlam = dp[1] * h / (2 * p.lam)
-        drho = dp[0] - dp[1] * h / (2 * p.rho)
-        gx0 = xb + vb  # v0 = x0
-        return gx0, dlam.float(), drho.float(), None, None
+        gx0 = torch.empty_like(x0)
+        # the library returns the initial image's adjoint (v0 = x0) and dL/dlambda,
+        # dL/drho through the coupled bandwidth
+        dp = api.ladmm_solve_backward(ctx.op, p, x0, x0, zeros, ck, xb, vb, ub, dinit=gx0)
+        return gx0, dp[2], dp[3], None, None
 
 
 def unrolled_ladmm(x0, lam, rho, op, params):

@@ -16,6 +16,8 @@
 // then one block), so repeated runs give identical bits.
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <new>
 #include <vector>
 
 #include "internal.h"
@@ -620,6 +622,152 @@ int ensure_solver_scratch(dsnlm_weights* w, const OpView& ov, const ladmm_operat
     return DSNLM_OK;
 }
 
+// ---- ladmm_solve's cache.  A solve is captured once into a HIP graph (all
+// iterations, the adaptive ones included) for each distinct set of arguments
+// (operator, parameters, state and output buffers, device) and replayed by
+// later calls with the same arguments.  The graph runs on a library stream of
+// the device, joined to the caller's stream by events; each entry owns its
+// weights handle and solver scratch.
+
+// Every iteration of a solve on stream st (ckpt/res: per-iteration slices).
+int enqueue_solve(const ladmm_operator* op, const OpView& ov, const ladmm_params* p, float h, dsnlm_weights* w,
+                  float* x, float* v, float* u, float* residuals, float* checkpoints, hipStream_t st) {
+    float *lr, *partials;
+    int rc = ensure_solver_scratch(w, ov, op, &lr, &partials);
+    const size_t n = (size_t)op->n1 * op->n2;
+    for (int k = 1; k <= p->iters && !rc; ++k)
+        rc = enqueue_step(op, ov, p, h, k, w, x, v, u, lr, partials,
+                          residuals ? residuals + 2 * (size_t)(k - 1) : nullptr,
+                          checkpoints ? checkpoints + 4 * n * (size_t)(k - 1) : nullptr, st);
+    return rc;
+}
+
+struct SolveKey {
+    int device;
+    ladmm_operator op;  // sizes and scalars only: the pointers are left null
+    Taps taps;
+    ladmm_params p;
+    int want_res, want_ckpt;
+};
+
+// The graph of an entry reads and writes the entry's own copies of the state,
+// the observation and the outputs, so one entry serves every call with the
+// same sizes and parameters; the caller's buffers are copied in before and
+// out after each replay (plain stream copies outside the graph).
+struct SolveEntry {
+    SolveKey key;
+    dsnlm_weights* w = nullptr;
+    float* buf = nullptr;          // x, v, u | observation y or counts | residuals | checkpoints
+    float *x, *v, *u, *res, *ckpt;
+    const float* y;
+    const unsigned char* ones;
+    hipGraphExec_t exec = nullptr;  // null: the solve is enqueued step by step
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    unsigned long long used = 0;
+};
+
+constexpr int kSolveCacheSize = 4;
+constexpr int kSolveDevices = 64;
+
+struct SolveCache {
+    std::mutex mu;
+    std::vector<SolveEntry*> entries;
+    hipStream_t stream[kSolveDevices] = {};
+    unsigned long long tick = 0;
+};
+SolveCache g_solves;
+
+void drop_entry(SolveEntry* e) {
+    (void)hipStreamSynchronize(g_solves.stream[e->key.device]);
+    if (e->exec) (void)hipGraphExecDestroy(e->exec);
+    if (e->ev_in) (void)hipEventDestroy(e->ev_in);
+    if (e->ev_out) (void)hipEventDestroy(e->ev_out);
+    (void)hipFree(e->buf);
+    dsnlm_weights_destroy(e->w);
+    delete e;
+}
+
+// Find or create the entry of `key` (caller holds g_solves.mu); a new entry
+// gets its handle, scratch and, when capture succeeds, its graph.
+int solve_entry(const SolveKey& key, const ladmm_operator* op, const OpView& ov, float h, SolveEntry** out) {
+    const int dev = key.device;
+    if (dev < 0 || dev >= kSolveDevices) return fail(DSNLM_EUNSUPPORTED, "ladmm_solve: device index too large");
+    for (SolveEntry* e : g_solves.entries)
+        if (std::memcmp(&e->key, &key, sizeof(key)) == 0) {
+            e->used = ++g_solves.tick;
+            *out = e;
+            return DSNLM_OK;
+        }
+    int rc;
+    if (!g_solves.stream[dev]) {
+        rc = check_hip(hipStreamCreateWithFlags(&g_solves.stream[dev], hipStreamNonBlocking), "ladmm_solve: stream");
+        if (rc) return rc;
+    }
+    if ((int)g_solves.entries.size() >= kSolveCacheSize) {
+        auto lru = g_solves.entries.begin();
+        for (auto it = g_solves.entries.begin(); it != g_solves.entries.end(); ++it)
+            if ((*it)->used < (*lru)->used) lru = it;
+        drop_entry(*lru);
+        g_solves.entries.erase(lru);
+    }
+    SolveEntry* e = new (std::nothrow) SolveEntry{};
+    if (!e) return fail(DSNLM_ENOMEM, "ladmm_solve: host allocation failed");
+    e->key = key;
+    const ladmm_params* p = &key.p;
+    const size_t n = (size_t)op->n1 * op->n2;
+    const size_t nobs = op->kind == LADMM_OP_SR ? (size_t)ov.g.m1 * ov.g.m2 : (n + 3) / 4;  // floats
+    const size_t nres = key.want_res ? 2 * (size_t)p->iters : 0;
+    const size_t nck = key.want_ckpt ? 4 * n * (size_t)p->iters : 0;
+    const size_t r64 = 64;
+    auto up = [&](size_t f) { return (f + r64 - 1) / r64 * r64; };
+    rc = check_hip(hipMalloc(&e->buf, (3 * up(n) + up(nobs) + up(nres) + up(nck)) * sizeof(float)),
+                   "ladmm_solve: state buffers");
+    if (rc) {
+        delete e;
+        return rc;
+    }
+    e->x = e->buf;
+    e->v = e->x + up(n);
+    e->u = e->v + up(n);
+    float* obs = e->u + up(n);
+    e->y = op->kind == LADMM_OP_SR ? obs : nullptr;
+    e->ones = op->kind == LADMM_OP_SPI ? reinterpret_cast<const unsigned char*>(obs) : nullptr;
+    e->res = key.want_res ? obs + up(nobs) : nullptr;
+    e->ckpt = key.want_ckpt ? obs + up(nobs) + up(nres) : nullptr;
+    ladmm_operator iop = *op;  // the operator as the graph sees it
+    iop.y = e->y;
+    iop.ones = e->ones;
+    rc = prepare_handle(op->n1, op->n2, p->S, p->P, h, &e->w);
+    float *lr, *partials;
+    if (!rc) rc = ensure_solver_scratch(e->w, ov, op, &lr, &partials);
+    if (!rc) rc = check_hip(prepare_sweeps(p->S, p->P), "sweep attributes");
+    if (!rc) rc = check_hip(hipEventCreateWithFlags(&e->ev_in, hipEventDisableTiming), "ladmm_solve: event");
+    if (!rc) rc = check_hip(hipEventCreateWithFlags(&e->ev_out, hipEventDisableTiming), "ladmm_solve: event");
+    if (rc) {
+        drop_entry(e);
+        return rc;
+    }
+    hipStream_t is = g_solves.stream[dev];
+    if (hipStreamBeginCapture(is, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        rc = enqueue_solve(&iop, ov, p, h, e->w, e->x, e->v, e->u, e->res, e->ckpt, is);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(is, &graph);
+        if (!rc && ec == hipSuccess && graph &&
+            hipGraphInstantiate(&e->exec, graph, nullptr, nullptr, 0) != hipSuccess)
+            e->exec = nullptr;
+        if (graph) (void)hipGraphDestroy(graph);
+        if (rc) {
+            drop_entry(e);
+            return rc;
+        }
+    }
+    (void)hipGetLastError();  // a failed capture leaves the step-by-step path
+    e->used = ++g_solves.tick;
+    g_solves.entries.push_back(e);
+    *out = e;
+    return DSNLM_OK;
+}
+
 }  // namespace
 
 // out = A^T A x for the super-resolution operator (lr: low-resolution scratch).
@@ -687,63 +835,77 @@ int ladmm_solve(const ladmm_operator* op, const ladmm_params* p, float* x, float
     if (!x || !v || !u) return fail(DSNLM_EINVAL, "ladmm_solve: null pointer");
     if (p->iters == 0) return DSNLM_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    dsnlm_weights* w = nullptr;
-    rc = prepare_handle(op->n1, op->n2, p->S, p->P, h, &w);
-    if (rc) return rc;
-    float *lr, *partials;
-    rc = ensure_solver_scratch(w, ov, op, &lr, &partials);
-    if (rc) {
-        dsnlm_weights_destroy(w);
-        return rc;
-    }
-    rc = check_hip(prepare_sweeps(p->S, p->P), "sweep attributes");
-    if (rc) {
-        dsnlm_weights_destroy(w);
-        return rc;
-    }
-    const size_t n = (size_t)op->n1 * op->n2;
-    auto res_at = [&](int k) { return residuals ? residuals + 2 * (size_t)(k - 1) : nullptr; };
-    auto ck_at = [&](int k) { return checkpoints ? checkpoints + 4 * n * (size_t)(k - 1) : nullptr; };
-    int k = 1;
-    // plain NLM is rebuilt every iteration (no frozen phase to capture)
-    const int adaptive_end = (p->freeze_after < p->iters && p->denoiser != 1) ? p->freeze_after : p->iters;
-    for (; k <= adaptive_end && !rc; ++k)
-        rc = enqueue_step(op, ov, p, h, k, w, x, v, u, lr, partials, res_at(k), ck_at(k), st);
-    if (!rc && k <= p->iters) {
-        // frozen iterations: capture them once into a graph and launch it
+    if (st) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        bool use_graph = st != nullptr && hipStreamIsCapturing(st, &cs) == hipSuccess &&
-                         cs == hipStreamCaptureStatusNone;
-        if (use_graph && hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-            (void)hipGetLastError();
-            use_graph = false;
-        }
-        int k0 = k;
-        for (; k <= p->iters && !rc; ++k)
-            rc = enqueue_step(op, ov, p, h, k, w, x, v, u, lr, partials, res_at(k), ck_at(k), st);
-        if (use_graph) {
-            hipGraph_t graph = nullptr;
-            hipError_t e = hipStreamEndCapture(st, &graph);
-            if (!rc) rc = check_hip(e, "end capture");
-            hipGraphExec_t exec = nullptr;
-            if (!rc) rc = check_hip(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate");
-            if (!rc) rc = check_hip(hipGraphLaunch(exec, st), "graph launch");
-            // the executable graph must outlive its launch
-            if (exec) {
-                (void)hipStreamSynchronize(st);
-                (void)hipGraphExecDestroy(exec);
-            }
-            if (graph) (void)hipGraphDestroy(graph);
-        }
-        (void)k0;
+        rc = check_hip(hipStreamIsCapturing(st, &cs), "ladmm_solve: capture status");
+        if (rc) return rc;
+        if (cs != hipStreamCaptureStatusNone)
+            return fail(DSNLM_EINVAL, "ladmm_solve: the stream is being captured (the solve captures its own graph)");
     }
-    if (!rc) rc = check_hip(hipStreamSynchronize(st), "solve synchronise");
-    dsnlm_weights_destroy(w);
+    int dev = 0;
+    rc = check_hip(hipGetDevice(&dev), "ladmm_solve: hipGetDevice");
+    if (rc) return rc;
+    SolveKey key;
+    std::memset(&key, 0, sizeof(key));
+    key.device = dev;
+    // field by field, so that the caller's struct padding never enters the key
+    key.op.kind = op->kind;
+    key.op.n1 = op->n1;
+    key.op.n2 = op->n2;
+    key.op.blur_size = op->blur_size;
+    key.op.factor = op->factor;
+    key.op.boundary = op->boundary;
+    key.op.K = op->K;
+    key.op.eta = op->eta;
+    key.op.t_min = op->t_min;
+    key.taps = ov.taps;  // the taps by value (the pointer is the caller's host array)
+    key.p = *p;
+    key.want_res = residuals != nullptr;
+    key.want_ckpt = checkpoints != nullptr;
+    std::lock_guard<std::mutex> lk(g_solves.mu);
+    SolveEntry* e = nullptr;
+    rc = solve_entry(key, op, ov, h, &e);
+    if (rc) return rc;
+    hipStream_t is = g_solves.stream[dev];
+    // the internal stream runs after the caller's prior work, and the
+    // caller's later work after the solve
+    rc = check_hip(hipEventRecord(e->ev_in, st), "ladmm_solve: record");
+    if (!rc) rc = check_hip(hipStreamWaitEvent(is, e->ev_in, 0), "ladmm_solve: wait");
+    const size_t n = (size_t)op->n1 * op->n2, nb = n * sizeof(float);
+    auto copy = [&](void* dst, const void* src, size_t bytes) {
+        if (!rc) rc = check_hip(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, is), "ladmm_solve: copy");
+    };
+    copy(e->x, x, nb);
+    copy(e->v, v, nb);
+    copy(e->u, u, nb);
+    if (op->kind == LADMM_OP_SR)
+        copy(const_cast<float*>(e->y), op->y, (size_t)ov.g.m1 * ov.g.m2 * sizeof(float));
+    else
+        copy(const_cast<unsigned char*>(e->ones), op->ones, n);
+    if (!rc) {
+        if (e->exec) {
+            rc = check_hip(hipGraphLaunch(e->exec, is), "ladmm_solve: graph launch");
+        } else {
+            ladmm_operator iop = *op;
+            iop.y = e->y;
+            iop.ones = e->ones;
+            rc = enqueue_solve(&iop, ov, p, h, e->w, e->x, e->v, e->u, e->res, e->ckpt, is);
+        }
+    }
+    copy(x, e->x, nb);
+    copy(v, e->v, nb);
+    copy(u, e->u, nb);
+    if (residuals) copy(residuals, e->res, 2 * (size_t)p->iters * sizeof(float));
+    if (checkpoints) copy(checkpoints, e->ckpt, 4 * nb * (size_t)p->iters);
+    if (!rc) rc = check_hip(hipEventRecord(e->ev_out, is), "ladmm_solve: record");
+    if (!rc) rc = check_hip(hipStreamWaitEvent(st, e->ev_out, 0), "ladmm_solve: wait");
     if (rc) return rc;
     if (residuals) {
+        // the documented synchronisation: residuals are checked on the host
         std::vector<float> host(2 * (size_t)p->iters);
-        rc = check_hip(hipMemcpy(host.data(), residuals, host.size() * sizeof(float), hipMemcpyDeviceToHost),
+        rc = check_hip(hipMemcpyAsync(host.data(), residuals, host.size() * sizeof(float), hipMemcpyDeviceToHost, st),
                        "copy residuals");
+        if (!rc) rc = check_hip(hipStreamSynchronize(st), "ladmm_solve: synchronise");
         if (rc) return rc;
         for (float r : host)
             if (!std::isfinite(r)) return fail(DSNLM_ENONFINITE, "ladmm_solve: non-finite residual");

@@ -17,6 +17,8 @@
 // z's adjoint at iteration k0.  Reductions are fixed-order (per-block
 // partials, then one block), so runs are bit-reproducible.
 #include <cmath>
+#include <mutex>
+#include <string>
 
 #include "internal.h"
 
@@ -25,6 +27,8 @@ namespace dsnlm {
 int check_denoiser_args(int n1, int n2, int S, int P, float h, const char* who);
 int prepare_handle(int n1, int n2, int S, int P, float h, dsnlm_weights** out);
 ImgDesc base_desc(const dsnlm_weights* w);
+// SR helper from ladmm.hip: out = A^T A x (lr: low-resolution scratch).
+int sr_apply_AtA(const ladmm_operator* op, const float* x, float* lr, float* out, hipStream_t st);
 
 namespace {
 
@@ -130,10 +134,182 @@ __global__ void __launch_bounds__(256) k_axpy1(float* __restrict__ acc, const fl
     if (i < n) acc[i] += g[i];
 }
 
-}  // namespace
+// v[0 .. n) = 0 (a kernel rather than a memset, so the sequence stays
+// capturable into a graph)
+__global__ void __launch_bounds__(256) k_zero(float* __restrict__ v, int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) v[i] = 0.f;
+}
 
-// SR helpers from ladmm.hip: r = A x (y null) and g = A^T r.
-int sr_apply_AtA(const ladmm_operator* op, const float* x, float* lr, float* out, hipStream_t st);
+// The end of the reverse pass: the adjoint of the initial image when
+// Algorithm 1 starts from x0 = v0 (dinit = xbar + vbar), and the parameter
+// derivatives.  dparams: [0] explicit d/drho, [1] d/dh on entry; [2] d/dlambda
+// and [3] d/drho on return, through h = sqrt(lambda / rho) when coupled.
+__global__ void __launch_bounds__(256) k_rev_final(const float* __restrict__ xb, const float* __restrict__ vb,
+                                                  float* __restrict__ dinit, int n, float* __restrict__ dparams,
+                                                  float h, float lambda, float rho, int coupled) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (dinit && i < n) dinit[i] = xb[i] + vb[i];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const float drho_x = dparams[0], dh = dparams[1];
+        dparams[2] = coupled ? dh * h / (2.0f * lambda) : 0.f;
+        dparams[3] = coupled ? drho_x - dh * h / (2.0f * rho) : drho_x;
+    }
+}
+
+// Reverse-pass workspace of one device (grow-only, reused by every call):
+// the weights rebuilt for adaptive iterations, the frozen weights, and the
+// per-step scratch.
+struct RevWorkspace {
+    dsnlm_weights* wa = nullptr;
+    dsnlm_weights* wf = nullptr;
+    float* scratch = nullptr;
+    size_t cap = 0;
+};
+constexpr int kRevDevices = 64;
+std::mutex g_rev_mu;
+RevWorkspace g_rev[kRevDevices];
+
+// Scratch layout: y | vt | zb | gb | qb | hq | gacc | lr | partials | dh
+struct RevScratch {
+    float *y, *vt, *zb, *gb, *qb, *hq, *lr, *partials, *dh, *gacc;
+};
+
+int rev_scratch(RevWorkspace& ws, size_t n, size_t mlr, RevScratch* r) {
+    const size_t need = 7 * n + mlr + nblk(n) + 64;
+    if (ws.cap < need) {
+        if (ws.scratch) {
+            (void)hipDeviceSynchronize();  // a previous call may still read it
+            (void)hipFree(ws.scratch);
+        }
+        ws.scratch = nullptr;
+        ws.cap = 0;
+        int rc = check_hip(hipMalloc(&ws.scratch, need * sizeof(float)), "reverse-pass scratch");
+        if (rc) return rc;
+        ws.cap = need;
+    }
+    float* b = ws.scratch;
+    r->y = b;
+    r->vt = b + n;
+    r->zb = b + 2 * n;
+    r->gb = b + 3 * n;
+    r->qb = b + 4 * n;
+    r->hq = b + 5 * n;
+    r->gacc = b + 6 * n;
+    r->lr = b + 7 * n;
+    r->partials = r->lr + mlr;
+    r->dh = r->partials + nblk(n);
+    return DSNLM_OK;
+}
+
+// A handle of the workspace for an n1 x n2 image (one of another size is
+// dropped after the device has finished with it).
+int rev_handle(dsnlm_weights** w, int n1, int n2) {
+    if (*w && ((*w)->n1 != n1 || (*w)->n2 != n2)) {
+        (void)hipDeviceSynchronize();
+        dsnlm_weights_destroy(*w);
+        *w = nullptr;
+    }
+    return DSNLM_OK;
+}
+
+int check_rev_args(const ladmm_operator* op, const ladmm_params* p, const char* who, float* h_out) {
+    std::string w(who);
+    if (!op || !p) return fail(DSNLM_EINVAL, w + ": null pointer");
+    if (p->denoiser != 0) return fail(DSNLM_EUNSUPPORTED, w + ": DSG-NLM denoiser only");
+    const int n1 = op->n1, n2 = op->n2;
+    if (n1 < 1 || n2 < 1) return fail(DSNLM_EINVAL, w + ": bad image size");
+    if (!(p->lambda > 0.f) || !(p->rho > 0.f) || !(p->gamma > 0.f) || !(p->lo < p->hi) || p->freeze_after < 1)
+        return fail(DSNLM_EINVAL, w + ": bad parameters");
+    const float h = p->h > 0.f ? p->h : std::sqrt(p->lambda / p->rho);
+    int rc = check_denoiser_args(n1, n2, p->S, p->P, h, who);
+    if (rc) return rc;
+    if (op->kind == LADMM_OP_SR) {
+        if (!op->taps || op->blur_size < 1 || op->blur_size > 31 || op->blur_size % 2 == 0 || op->factor < 1 ||
+            op->factor > 8 || (op->blur_size - 1) / 2 >= (n1 < n2 ? n1 : n2))
+            return fail(DSNLM_EINVAL, w + ": bad super-resolution operator");
+    } else if (op->kind == LADMM_OP_SPI) {
+        if (!op->ones || op->K < 1 || !(op->eta > 0.f) || !(op->t_min > 0.f))
+            return fail(DSNLM_EINVAL, w + ": bad single-photon operator");
+    } else {
+        return fail(DSNLM_EINVAL, w + ": unknown operator kind");
+    }
+    *h_out = h;
+    return DSNLM_OK;
+}
+
+// One reverse step k (see the top of the file).  w holds the weights of the
+// iteration: rebuilt here from `guide` when `rebuild`, else the frozen weights
+// already built (only the apply for z_k is redone, which the backward needs).
+// `adaptive`: the guide of iteration k is z_k itself, so its adjoint joins z's.
+int enqueue_rev_step(const ladmm_operator* op, const ladmm_params* p, float h, int k, dsnlm_weights** w,
+                     bool rebuild, bool adaptive, const float* guide, const float* x_prev, const float* v_prev,
+                     const float* u_prev, const float* x_k, const float* z_k, float* xbar, float* vbar,
+                     float* ubar, const float* gacc_join, float* gacc_add, float* dparams, const RevScratch& r,
+                     hipStream_t st) {
+    const int n1 = op->n1, n2 = op->n2;
+    const size_t n = (size_t)n1 * n2;
+    void* stream = st;
+    int rc = rebuild ? dsnlm_forward(guide, z_k, r.y, n1, n2, p->S, p->P, h, stream, w)
+                     : dsnlm_apply(*w, z_k, r.y, stream);
+    if (!rc) {
+        hipLaunchKernelGGL(k_vt, dim3(nblk(n)), dim3(256), 0, st, vbar, ubar, r.vt, (int)n);
+        rc = check_hip(hipGetLastError(), "reverse step");
+    }
+    if (!rc) rc = dsnlm_apply_backward(*w, z_k, r.vt, r.zb, r.gb, r.dh, stream);
+    if (rc) return rc;
+    const float alpha = 1.0f / p->gamma;
+    RevArgs a{};
+    a.x = x_prev;
+    a.v = v_prev;
+    a.u = u_prev;
+    a.xk = x_k;
+    a.zb = r.zb;
+    a.gb = adaptive ? r.gb : nullptr;
+    a.gacc = gacc_join;
+    a.ones = op->kind == LADMM_OP_SPI ? op->ones : nullptr;
+    a.xb = xbar;
+    a.vb = vbar;
+    a.ub = ubar;
+    a.qb = r.qb;
+    a.partials = r.partials;
+    a.n = (int)n;
+    a.alpha = alpha;
+    a.rho = p->rho;
+    a.mu = 1.0f / (alpha + p->rho);
+    a.lo = p->lo;
+    a.hi = p->hi;
+    a.spi = op->kind == LADMM_OP_SPI;
+    if (a.spi) {
+        a.eta_over_K = op->eta / (float)op->K;
+        a.K = (float)op->K;
+        a.t_min = op->t_min;
+    }
+    ProfScope prof(DSNLM_K_LADMM, st);
+    if (gacc_add) hipLaunchKernelGGL(k_axpy1, dim3(nblk(n)), dim3(256), 0, st, gacc_add, r.gb, (int)n);
+    hipLaunchKernelGGL(k_rev, dim3(nblk(n)), dim3(256), 0, st, a);
+    rc = check_hip(hipGetLastError(), "reverse step");
+    if (!rc && !a.spi) {
+        rc = sr_apply_AtA(op, r.qb, r.lr, r.hq, st);
+        if (!rc) {
+            hipLaunchKernelGGL(k_rev_sr, dim3(nblk(n)), dim3(256), 0, st, r.qb, r.hq, xbar, (int)n, a.mu, alpha);
+            rc = check_hip(hipGetLastError(), "reverse step");
+        }
+    }
+    if (!rc) {
+        hipLaunchKernelGGL(k_accum_params, dim3(1), dim3(256), 0, st, r.partials, nblk(n), r.dh, dparams);
+        rc = check_hip(hipGetLastError(), "reverse step");
+    }
+    return rc;
+}
+
+size_t lr_floats(const ladmm_operator* op) {
+    return op->kind == LADMM_OP_SR
+               ? (size_t)((op->n1 + op->factor - 1) / op->factor) * ((op->n2 + op->factor - 1) / op->factor)
+               : 0;
+}
+
+}  // namespace
 
 }  // namespace dsnlm
 
@@ -143,140 +319,78 @@ extern "C" int ladmm_step_backward(const ladmm_operator* op, const ladmm_params*
                                    const float* x_prev, const float* v_prev, const float* u_prev,
                                    const float* x_k, const float* z_k, float* xbar, float* vbar, float* ubar,
                                    float* gacc, float* dparams, void* stream) {
-    if (!op || !p || !guide || !x_prev || !v_prev || !u_prev || !x_k || !z_k || !xbar || !vbar || !ubar ||
-        !dparams)
+    if (!guide || !x_prev || !v_prev || !u_prev || !x_k || !z_k || !xbar || !vbar || !ubar || !dparams)
         return fail(DSNLM_EINVAL, "ladmm_step_backward: null pointer");
     if (k < 1) return fail(DSNLM_EINVAL, "ladmm_step_backward: k is 1-based");
-    if (p->denoiser != 0) return fail(DSNLM_EUNSUPPORTED, "ladmm_step_backward: DSG-NLM denoiser only");
+    float h;
+    int rc = check_rev_args(op, p, "ladmm_step_backward", &h);
+    if (rc) return rc;
     if (k > p->freeze_after && !gacc)
         return fail(DSNLM_EINVAL, "ladmm_step_backward: frozen iterations need the guide-adjoint accumulator");
-    const int n1 = op->n1, n2 = op->n2;
-    if (n1 < 1 || n2 < 1) return fail(DSNLM_EINVAL, "ladmm_step_backward: bad image size");
-    const float h = p->h > 0.f ? p->h : std::sqrt(p->lambda / p->rho);
-    int rc = check_denoiser_args(n1, n2, p->S, p->P, h, "ladmm_step_backward");
+    int dev = 0;
+    rc = check_hip(hipGetDevice(&dev), "ladmm_step_backward: hipGetDevice");
     if (rc) return rc;
-    if (!(p->lambda > 0.f) || !(p->rho > 0.f) || !(p->gamma > 0.f) || !(p->lo < p->hi))
-        return fail(DSNLM_EINVAL, "ladmm_step_backward: bad parameters");
-    if (op->kind == LADMM_OP_SR) {
-        if (!op->taps || op->blur_size < 1 || op->blur_size > 31 || op->blur_size % 2 == 0 || op->factor < 1 ||
-            op->factor > 8 || (op->blur_size - 1) / 2 >= (n1 < n2 ? n1 : n2))
-            return fail(DSNLM_EINVAL, "ladmm_step_backward: bad super-resolution operator");
-    } else if (op->kind == LADMM_OP_SPI) {
-        if (!op->ones || op->K < 1 || !(op->eta > 0.f) || !(op->t_min > 0.f))
-            return fail(DSNLM_EINVAL, "ladmm_step_backward: bad single-photon operator");
-    } else {
-        return fail(DSNLM_EINVAL, "ladmm_step_backward: unknown operator kind");
-    }
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const size_t n = (size_t)n1 * n2;
-    dsnlm_weights* w = nullptr;
-    float* scratch = nullptr;
-    const size_t mlr = op->kind == LADMM_OP_SR
-                           ? (size_t)((n1 + op->factor - 1) / op->factor) * ((n2 + op->factor - 1) / op->factor)
-                           : 0;
-    // layout: y | vt | zb | gb | qb | hq | lr | partials | dh
-    const size_t need = 6 * n + mlr + nblk(n) + 8;
-    rc = check_hip(hipMalloc(&scratch, need * sizeof(float)), "ladmm_step_backward scratch");
+    if (dev < 0 || dev >= kRevDevices) return fail(DSNLM_EUNSUPPORTED, "ladmm_step_backward: device index too large");
+    std::lock_guard<std::mutex> lk(g_rev_mu);
+    RevWorkspace& ws = g_rev[dev];
+    RevScratch r;
+    rc = rev_scratch(ws, (size_t)op->n1 * op->n2, lr_floats(op), &r);
+    if (!rc) rc = rev_handle(&ws.wa, op->n1, op->n2);
     if (rc) return rc;
-    float* y = scratch;
-    float* vt = y + n;
-    float* zb = vt + n;
-    float* gb = zb + n;
-    float* qb = gb + n;
-    float* hq = qb + n;
-    float* lr = hq + n;
-    float* partials = lr + mlr;
-    float* dh = partials + nblk(n);
-    // recompute the forward denoiser of iteration k: W(guide) applied to z_k
-    rc = dsnlm_forward(guide, z_k, y, n1, n2, p->S, p->P, h, stream, &w);
-    if (!rc) {
-        hipLaunchKernelGGL(k_vt, dim3(nblk(n)), dim3(256), 0, st, vbar, ubar, vt, (int)n);
-        rc = check_hip(hipGetLastError(), "reverse step");
-    }
     const bool adaptive = k <= p->freeze_after;
-    if (!rc) rc = dsnlm_apply_backward(w, z_k, vt, zb, gb, dh, stream);
-    if (!rc) {
-        const float alpha = 1.0f / p->gamma;
-        RevArgs a{};
-        a.x = x_prev;
-        a.v = v_prev;
-        a.u = u_prev;
-        a.xk = x_k;
-        a.zb = zb;
-        a.gb = adaptive ? gb : nullptr;
-        a.gacc = (k == p->freeze_after) ? gacc : nullptr;
-        a.ones = op->kind == LADMM_OP_SPI ? op->ones : nullptr;
-        a.xb = xbar;
-        a.vb = vbar;
-        a.ub = ubar;
-        a.qb = qb;
-        a.partials = partials;
-        a.n = (int)n;
-        a.alpha = alpha;
-        a.rho = p->rho;
-        a.mu = 1.0f / (alpha + p->rho);
-        a.lo = p->lo;
-        a.hi = p->hi;
-        a.spi = op->kind == LADMM_OP_SPI;
-        if (a.spi) {
-            a.eta_over_K = op->eta / (float)op->K;
-            a.K = (float)op->K;
-            a.t_min = op->t_min;
-        }
-        ProfScope prof(DSNLM_K_LADMM, st);
-        if (!adaptive) hipLaunchKernelGGL(k_axpy1, dim3(nblk(n)), dim3(256), 0, st, gacc, gb, (int)n);
-        hipLaunchKernelGGL(k_rev, dim3(nblk(n)), dim3(256), 0, st, a);
-        rc = check_hip(hipGetLastError(), "reverse step");
-        if (!rc && !a.spi) {
-            rc = sr_apply_AtA(op, qb, lr, hq, st);
-            if (!rc) {
-                hipLaunchKernelGGL(k_rev_sr, dim3(nblk(n)), dim3(256), 0, st, qb, hq, xbar, (int)n, a.mu, alpha);
-                rc = check_hip(hipGetLastError(), "reverse step");
-            }
-        }
-        if (!rc) {
-            hipLaunchKernelGGL(k_accum_params, dim3(1), dim3(256), 0, st, partials, nblk(n), dh, dparams);
-            rc = check_hip(hipGetLastError(), "reverse step");
-        }
-    }
-    // free only after the queued work has consumed the scratch and the handle
-    hipError_t e = hipStreamSynchronize(st);
-    if (!rc) rc = check_hip(e, "reverse step synchronise");
-    (void)hipFree(scratch);
-    dsnlm_weights_destroy(w);
-    return rc;
+    // the weights are rebuilt from the guide (their input z_k while adaptive)
+    return enqueue_rev_step(op, p, h, k, &ws.wa, true, adaptive, guide, x_prev, v_prev, u_prev, x_k, z_k, xbar, vbar, ubar,
+                            k == p->freeze_after ? gacc : nullptr, adaptive ? nullptr : gacc, dparams, r,
+                            static_cast<hipStream_t>(stream));
 }
 
 extern "C" int ladmm_solve_backward(const ladmm_operator* op, const ladmm_params* p, const float* x0,
                                     const float* v0, const float* u0, const float* checkpoints, float* xbar,
-                                    float* vbar, float* ubar, float* dparams, void* stream) {
-    if (!op || !p || !x0 || !v0 || !u0 || !checkpoints || !xbar || !vbar || !ubar || !dparams)
+                                    float* vbar, float* ubar, float* dinit, float* dparams, void* stream) {
+    if (!x0 || !v0 || !u0 || !checkpoints || !xbar || !vbar || !ubar || !dparams)
         return fail(DSNLM_EINVAL, "ladmm_solve_backward: null pointer");
-    if (p->iters < 1) return DSNLM_OK;
-    if (p->freeze_after < 1) return fail(DSNLM_EINVAL, "ladmm_solve_backward: freeze_after must be >= 1");
-    if (p->denoiser != 0) return fail(DSNLM_EUNSUPPORTED, "ladmm_solve_backward: DSG-NLM denoiser only");
+    float h;
+    int rc = check_rev_args(op, p, "ladmm_solve_backward", &h);
+    if (rc) return rc;
+    if (p->iters < 0) return fail(DSNLM_EINVAL, "ladmm_solve_backward: iters must be >= 0");
+    int dev = 0;
+    rc = check_hip(hipGetDevice(&dev), "ladmm_solve_backward: hipGetDevice");
+    if (rc) return rc;
+    if (dev < 0 || dev >= kRevDevices) return fail(DSNLM_EUNSUPPORTED, "ladmm_solve_backward: device index too large");
     const size_t n = (size_t)op->n1 * op->n2;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    float* gacc = nullptr;
-    int rc = DSNLM_OK;
-    if (p->iters > p->freeze_after) {
-        rc = check_hip(hipMalloc(&gacc, n * sizeof(float)), "guide adjoint");
-        if (!rc) rc = check_hip(hipMemsetAsync(gacc, 0, n * sizeof(float), st), "guide adjoint");
-        if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_rev_mu);
+    RevWorkspace& ws = g_rev[dev];
+    RevScratch r;
+    rc = rev_scratch(ws, n, lr_floats(op), &r);
+    if (!rc) rc = rev_handle(&ws.wa, op->n1, op->n2);
+    if (!rc) rc = rev_handle(&ws.wf, op->n1, op->n2);
+    if (rc) return rc;
+    {
+        ProfScope prof(DSNLM_K_LADMM, st);
+        hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, st, dparams, 4);
+        if (p->iters > p->freeze_after) hipLaunchKernelGGL(k_zero, dim3(nblk(n)), dim3(256), 0, st, r.gacc, (int)n);
+        rc = check_hip(hipGetLastError(), "ladmm_solve_backward: clear");
     }
     auto ck = [&](int k, int which) { return checkpoints + (4 * (size_t)(k - 1) + which) * n; };
     const int k0 = p->freeze_after < p->iters ? p->freeze_after : p->iters;
+    // the frozen weights W(z_k0) serve every k > k0: built once
+    if (!rc && p->iters > k0)
+        rc = dsnlm_build_weights(ck(k0, 3), op->n1, op->n2, p->S, p->P, h, stream, &ws.wf);
     for (int k = p->iters; k >= 1 && !rc; --k) {
         const float* xp = k > 1 ? ck(k - 1, 0) : x0;
         const float* vp = k > 1 ? ck(k - 1, 1) : v0;
         const float* up = k > 1 ? ck(k - 1, 2) : u0;
-        const float* guide = k <= k0 ? ck(k, 3) : ck(k0, 3);
-        rc = ladmm_step_backward(op, p, k, guide, xp, vp, up, ck(k, 0), ck(k, 3), xbar, vbar, ubar, gacc, dparams,
-                                 stream);
+        const bool adaptive = k <= k0;
+        rc = enqueue_rev_step(op, p, h, k, adaptive ? &ws.wa : &ws.wf, adaptive, adaptive, ck(k, 3), xp, vp, up, ck(k, 0),
+                              ck(k, 3), xbar, vbar, ubar, k == k0 && p->iters > k0 ? r.gacc : nullptr,
+                              adaptive ? nullptr : r.gacc, dparams, r, st);
     }
-    if (gacc) {
-        (void)hipStreamSynchronize(st);
-        (void)hipFree(gacc);
+    if (!rc) {
+        ProfScope prof(DSNLM_K_LADMM, st);
+        hipLaunchKernelGGL(k_rev_final, dim3(nblk(n)), dim3(256), 0, st, xbar, vbar, dinit, (int)n, dparams, h,
+                           p->lambda, p->rho, p->h > 0.f ? 0 : 1);
+        rc = check_hip(hipGetLastError(), "ladmm_solve_backward: final");
     }
     return rc;
 }
