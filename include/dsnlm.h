@@ -88,6 +88,28 @@ int dsnlm_apply(const dsnlm_weights* w, const float* x, float* y, void* stream);
 int dsnlm_forward(const float* guide, const float* x, float* y, int n1, int n2,
                   int S, int P, float h, void* stream, dsnlm_weights** out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as dsnlm_forward with out = NULL -- y = W(guide) x, the same
+ * kernels, bit-identical results -- but it allocates nothing (no hipMalloc,
+ * no hipFree, no allocating library call) and does not synchronise.  Its
+ * intermediates (c, delta, B', m, the partial regions, the mirrored guide)
+ * live in a fixed scratch array of dsnlm_forward_noalloc_limit() bytes
+ * (48 MiB) that each device holds from its first call until the process ends.
+ * Arguments as for dsnlm_forward; P <= 5.  An image whose intermediates
+ * (dsnlm_forward_noalloc_bytes) exceed the limit returns DSNLM_EUNSUPPORTED
+ * before anything is launched (1024 x 1024 at S = 10, P = 3 needs 31 MiB).
+ * Every call on a device shares that device's scratch, which keeps the last
+ * call's contents: calls that overlap in time on one device (different
+ * streams, or host threads) race and give wrong results; calls ordered on
+ * one stream are safe. */
+int dsnlm_forward_noalloc(const float* guide, const float* x, float* y, int n1, int n2, int S, int P,
+                          float h, void* stream);
+/* Scratch bytes of the array above, and bytes an n1 x n2 image at S, P
+ * would use of it (0 for arguments outside the supported range).  Host-only. */
+size_t dsnlm_forward_noalloc_limit(void);
+size_t dsnlm_forward_noalloc_bytes(int n1, int n2, int S, int P);
+
 /* Plain NLM, eq. NLM of Section 3 (the row-stochastic filter DSG-NLM is
  * derived from): y_s = sum_r k_{s,r} x_r / sum_r k_{s,r}, k the same kernel of
  * the guide's patches (no hat), r over the border-cut window, r = s included.

@@ -92,6 +92,9 @@ def _load():
         "dsnlm_build_weights": (i, [vp, i, i, i, i, f, vp, pp]),
         "dsnlm_apply": (i, [vp, vp, vp, vp]),
         "dsnlm_forward": (i, [vp, vp, vp, i, i, i, i, f, vp, pp]),
+        "dsnlm_forward_noalloc": (i, [vp, vp, vp, i, i, i, i, f, vp]),
+        "dsnlm_forward_noalloc_limit": (C.c_size_t, []),
+        "dsnlm_forward_noalloc_bytes": (C.c_size_t, [i, i, i, i]),
         "dsnlm_nlm": (i, [vp, vp, vp, i, i, i, i, f, vp, pp]),
         "dsnlm_forward_brute": (i, [vp, vp, vp, i, i, i, i, f, vp, pp]),
         "dsnlm_apply_backward": (i, [vp, vp, vp, vp, vp, vp, vp]),
@@ -147,6 +150,7 @@ EXPORTED = [
     "dsnlm_tune_set", "dsnlm_tune_get", "dsnlm_tune", "dsnlm_peak_probe",
     "ladmm_step_backward", "ladmm_solve_backward", "dsnlm_backward_batched", "dsnlm_nlm",
     "dsnlm_forward_brute", "admm_cg_solve", "dsnlm_batched_state",
+    "dsnlm_forward_noalloc", "dsnlm_forward_noalloc_limit", "dsnlm_forward_noalloc_bytes",
 ]
 
 K_PASS_A, K_PASS_B, K_APPLY, K_EPILOGUE, K_BWD_PREP, K_PASS_C, K_PASS_D, K_BWD_TAIL, K_LADMM, K_HALF_AUX = range(10)

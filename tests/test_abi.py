@@ -84,3 +84,19 @@ def test_images_past_the_32bit_offsets_refused(lib):
     arr[0] = _lib.DsnlmImage(0x1000, 0x1000, 1 << 40, 1 << 15, 1 << 14, 0.1)
     assert lib.dsnlm_forward_batched(arr, 1, 10, 3, None) == -5
     assert not hp.value
+
+
+def test_noalloc_forward_refuses_past_its_scratch(lib):
+    """The allocation-free forward serves images whose intermediates fit its
+    fixed scratch and refuses larger ones on the host, before any device call."""
+    limit = lib.dsnlm_forward_noalloc_limit()
+    assert limit == 48 << 20
+    assert 0 < lib.dsnlm_forward_noalloc_bytes(1024, 1024, 10, 3) <= limit
+    assert lib.dsnlm_forward_noalloc_bytes(2048, 2048, 10, 3) > limit
+    assert lib.dsnlm_forward_noalloc_bytes(64, 64, 10, 6) == 0
+    fake = C.c_void_p(0x1000)
+    assert lib.dsnlm_forward_noalloc(fake, fake, C.c_void_p(1 << 40), 2048, 2048, 10, 3, 0.1, None) == -5
+    assert b"scratch" in lib.dsnlm_last_error()
+    assert lib.dsnlm_forward_noalloc(fake, fake, C.c_void_p(1 << 40), 64, 64, 10, 6, 0.1, None) == -5
+    assert lib.dsnlm_forward_noalloc(fake, fake, fake, 64, 64, 10, 3, 0.1, None) == -1  # y aliases x
+    assert lib.dsnlm_forward_noalloc(None, fake, C.c_void_p(1 << 40), 64, 64, 10, 3, 0.1, None) == -1
