@@ -178,9 +178,11 @@ int dsnlm_apply(const dsnlm_weights* wc, const float* x, float* y, void* stream)
     ImgDesc d = base_desc(w);
     d.x = x;
     d.y = y;
+    // on the half-window path the gather writes y = x + B'/m itself (m is known)
+    const bool fused = sweep_takes_half(kApply, w->S, w->P, d);
     int rc = check_hip(launch_sweep(kApply, w->S, w->P, d, nullptr, nullptr, 0, st), "apply sweep");
     if (rc) return rc;
-    rc = check_hip(launch_epilogue(d, nullptr, nullptr, 0, w->S, w->P, st), "epilogue");
+    if (!fused) rc = check_hip(launch_epilogue(d, nullptr, nullptr, 0, w->S, w->P, st), "epilogue");
     if (rc) return rc;
     w->applied = true;
     return DSNLM_OK;

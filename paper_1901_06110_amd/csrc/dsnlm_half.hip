@@ -32,6 +32,9 @@ namespace dsnlm {
 
 namespace {
 
+// largest number of dx groups a single-image half-window sweep is split into
+constexpr int kHalfSplitCap = 4;
+
 template <int P, int S_CLASS, int GW_ = 11>
 struct HGeo {
     static constexpr int TH = 32, TW = 64;   // s-tile (the forward tiling)
@@ -147,31 +150,48 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
     float* Vb = lds;
     float* Acc = lds + 2 * TH * VW;  // partner region, NC floats per entry
 
-    // ---- the partner region: factors (c, c x) or (t, w) and zeroed sums
-    for (int idx = tid; idx < AH * AWr; idx += NT) {
-        const int r = idx / AWr, q = idx - r * AWr;
-        if constexpr (NC == 1) {
+    // ---- the partner region: factors (c, c x) or (t, w) and zeroed sums.
+    // The loop has a compile-time trip count (the region of the largest S of
+    // the class), so every thread issues all its loads before the first wait.
+    constexpr int NINIT = ((TH + S_CLASS) * (TW + 2 * S_CLASS) + NT - 1) / NT;
+    if constexpr (NC == 1) {
+        for (int idx = tid; idx < AH * AWr; idx += NT) {
+            const int r = idx / AWr, q = idx - r * AWr;
             Acc[r * AW + q] = 0.f;
-        } else {
-            const int gi = ti0 + r, gj = tj0 - S + q;
-            const bool in = (unsigned)gi < (unsigned)n1 && (unsigned)gj < (unsigned)n2;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (in) {
-                const size_t p = (size_t)gi * n2 + gj;
-                if constexpr (MODE == kPassC) {
-                    const float2 tw = reinterpret_cast<const float2*>(d.aux_in)[p];
-                    v.x = tw.x;
-                    v.y = tw.y;
-                } else if constexpr (MODE == kNLM) {
-                    v.x = 1.f;
-                    v.y = d.x[p];
-                } else {
-                    const float cc = d.c[p];
-                    v.x = cc;
-                    v.y = (MODE == kPassBBuild) ? 0.f : cc * d.x[p];
+        }
+    } else {
+        float2 fv[NINIT];
+        int slot[NINIT];
+#pragma unroll
+        for (int it = 0; it < NINIT; ++it) {
+            const int idx = tid + it * NT;
+            fv[it] = make_float2(0.f, 0.f);
+            slot[it] = -1;
+            if (idx < AH * AWr) {
+                const int r = idx / AWr, q = idx - r * AWr;
+                slot[it] = r * AW + q;
+                const int gi = ti0 + r, gj = tj0 - S + q;
+                if ((unsigned)gi < (unsigned)n1 && (unsigned)gj < (unsigned)n2) {
+                    const size_t p = (size_t)gi * n2 + gj;
+                    if constexpr (MODE == kPassC) {
+                        fv[it] = reinterpret_cast<const float2*>(d.aux_in)[p];
+                    } else if constexpr (MODE == kNLM) {
+                        fv[it] = make_float2(1.f, d.x[p]);
+                    } else if constexpr (MODE == kPassBBuild) {
+                        fv[it] = make_float2(d.c[p], 0.f);
+                    } else {
+                        fv[it] = make_float2(d.c[p], d.x[p]);  // c x formed below
+                    }
                 }
             }
-            reinterpret_cast<float4*>(Acc)[r * AW + q] = v;
+        }
+#pragma unroll
+        for (int it = 0; it < NINIT; ++it) {
+            if (slot[it] >= 0) {
+                float2 f = fv[it];
+                if constexpr (MODE == kPassBApply || MODE == kApply) f.y = f.x * f.y;
+                reinterpret_cast<float4*>(Acc)[slot[it]] = make_float4(f.x, f.y, 0.f, 0.f);
+            }
         }
     }
     if constexpr (MODE == kPassA) {
@@ -423,33 +443,59 @@ k_half_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __r
     const int tx = tj0 / TW;
     const size_t ntl = (size_t)((n1 + TH - 1) / TH) * ntx;
     unsigned long long best = 0ull;
-    for (int e = threadIdx.x; e < TH * TW; e += 256) {
-        const int li = e / TW, lj = e - li * TW;
+    // a single-image launch splits the tile's rows over gridDim.z blocks
+    const int rows = TH / (int)gridDim.z, li0 = (int)blockIdx.z * rows;
+    float m = 1.f;
+    if constexpr (MODE == kApply) m = __uint_as_float((unsigned)(*d.key >> 32));  // the built weights' m
+    float rp = 0.f, rd = 0.f;  // fused dual half: residual sums of this thread
+    for (int e = threadIdx.x; e < rows * TW; e += 256) {
+        const int li = li0 + e / TW, lj = e % TW;
         const int gi = ti0 + li, gj = tj0 + lj;
         if (gi >= n1 || gj >= n2) continue;
         float s0 = 0.f, s1 = 0.f;
-        auto add = [&](int tile, int r, int q) {
-            const size_t o = (size_t)tile * reg + (size_t)r * AWr + q;
-            for (int g = 0; g < ngrp; ++g) {  // the dx groups, in order
-                const float* src = g == 0 ? d.part : d.gpart + (g - 1) * ntl * reg * NP;
-                if constexpr (NP == 1) {
-                    s0 += src[o];
-                } else {
-                    const float2 v = reinterpret_cast<const float2*>(src)[o];
-                    s0 += v.x;
-                    s1 += v.y;
+        // the regions covering the pixel (own, left, right, above, above-left,
+        // above-right) and the dx groups of each: all loads are issued first,
+        // then added in that fixed order (regions, and groups within each)
+        const bool left = tx > 0 && lj < S, right = tx + 1 < ntx && lj >= TW - S;
+        const bool above = ti0 > 0 && li < S;
+        const int up = lt - ntx;
+        size_t off[6];
+        bool ok[6];
+        off[0] = (size_t)lt * reg + (size_t)li * AWr + lj + S;
+        off[1] = (size_t)(lt - 1) * reg + (size_t)li * AWr + lj + TW + S;
+        off[2] = (size_t)(lt + 1) * reg + (size_t)li * AWr + lj - TW + S;
+        off[3] = (size_t)up * reg + (size_t)(li + TH) * AWr + lj + S;
+        off[4] = (size_t)(up - 1) * reg + (size_t)(li + TH) * AWr + lj + TW + S;
+        off[5] = (size_t)(up + 1) * reg + (size_t)(li + TH) * AWr + lj - TW + S;
+        ok[0] = true;
+        ok[1] = left;
+        ok[2] = right;
+        ok[3] = above;
+        ok[4] = above && left;
+        ok[5] = above && right;
+        constexpr int GMAX = kHalfSplitCap;
+        float2 val[6][GMAX];
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+#pragma unroll
+            for (int g = 0; g < GMAX; ++g) {
+                val[r][g] = make_float2(0.f, 0.f);
+                if (ok[r] && g < ngrp) {
+                    const float* src = g == 0 ? d.part : d.gpart + (g - 1) * ntl * reg * NP;
+                    if constexpr (NP == 1) val[r][g].x = src[off[r]];
+                    else val[r][g] = reinterpret_cast<const float2*>(src)[off[r]];
                 }
             }
-        };
-        const bool left = tx > 0 && lj < S, right = tx + 1 < ntx && lj >= TW - S;
-        add(lt, li, lj + S);
-        if (left) add(lt - 1, li, lj + TW + S);
-        if (right) add(lt + 1, li, lj - TW + S);
-        if (ti0 > 0 && li < S) {
-            const int up = lt - ntx;
-            add(up, li + TH, lj + S);
-            if (left) add(up - 1, li + TH, lj + TW + S);
-            if (right) add(up + 1, li + TH, lj - TW + S);
+        }
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+#pragma unroll
+            for (int g = 0; g < GMAX; ++g) {
+                if (ok[r] && g < ngrp) {
+                    s0 += val[r][g].x;
+                    if constexpr (NP == 2) s1 += val[r][g].y;
+                }
+            }
         }
         const size_t p = (size_t)gi * n2 + gj;
         if constexpr (MODE == kPassA) {
@@ -471,7 +517,20 @@ k_half_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __r
             if constexpr (MODE == kPassBApply || MODE == kApply) {
                 const float xs = d.x[p];
                 s1 += cs * xs;
-                d.bp[p] = cs * (s1 - xs * s0);
+                const float bp = cs * (s1 - xs * s0);
+                d.bp[p] = bp;
+                if constexpr (MODE == kApply) {
+                    const float vn = xs + bp / m;  // y = W x
+                    if (d.y) d.y[p] = vn;
+                    if (d.lu) {
+                        // Algorithm 1, dual half: u <- u + x - v, v <- W z
+                        const float xv = d.lx[p], vo = d.lv[p];
+                        d.lu[p] = d.lu[p] + xv - vn;
+                        d.lv[p] = vn;
+                        rp = fmaf(xv - vn, xv - vn, rp);
+                        rd = fmaf(vn - vo, vn - vo, rd);
+                    }
+                }
             }
             if constexpr (MODE == kPassBApply || MODE == kPassBBuild) {
                 const float dl = cs * s0;
@@ -479,6 +538,27 @@ k_half_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __r
                 const unsigned long long kk =
                     ((unsigned long long)__float_as_uint(dl) << 32) | (unsigned long long)(~(unsigned)p);
                 best = kk > best ? kk : best;
+            }
+        }
+    }
+    if constexpr (MODE == kApply) {
+        if (d.lres) {
+            // fixed-order block sums of the residual terms (wave, then block)
+            __shared__ float wsum[2][4];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                rp += __shfl_xor(rp, off, 64);
+                rd += __shfl_xor(rd, off, 64);
+            }
+            if ((threadIdx.x & 63) == 0) {
+                wsum[0][threadIdx.x >> 6] = rp;
+                wsum[1][threadIdx.x >> 6] = rd;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const int b = ((int)blockIdx.z * (int)gridDim.y + (int)blockIdx.y) * (int)gridDim.x + (int)blockIdx.x;
+                d.lres[2 * b] = (wsum[0][0] + wsum[0][1]) + (wsum[0][2] + wsum[0][3]);
+                d.lres[2 * b + 1] = (wsum[1][0] + wsum[1][1]) + (wsum[1][2] + wsum[1][3]);
             }
         }
     }
@@ -534,7 +614,8 @@ hipError_t launch_half_one(int S, const ImgDesc& one, const ImgDesc* batch, cons
     hipError_t ea = half_attr<P, S_CLASS, MODE, BATCH>();
     if (ea != hipSuccess) return ea;
     const dim3 grid = BATCH ? dim3(ntiles) : dim3((one.n2 + G::TW - 1) / G::TW, (one.n1 + G::TH - 1) / G::TH);
-    const int ngrp = (BATCH || one.groups < 2 || !one.gpart) ? 1 : std::min(one.groups, 2 * S + 1);
+    const int ngrp =
+        (BATCH || one.groups < 2 || !one.gpart) ? 1 : std::min(std::min(one.groups, 2 * S + 1), kHalfSplitCap);
     const dim3 sgrid(grid.x, grid.y, ngrp);
     HatTable hat = make_hat(S);
     if constexpr (MODE == kNLM)
@@ -557,7 +638,8 @@ hipError_t launch_half_one(int S, const ImgDesc& one, const ImgDesc* batch, cons
         if (e != hipSuccess) return e;
     }
     ProfScope prof(DSNLM_K_HALF_AUX, st);
-    hipLaunchKernelGGL((k_half_gather<MODE, BATCH>), grid, dim3(256), 0, st, one, batch, tiles, S, ngrp);
+    const dim3 ggrid(grid.x, grid.y, BATCH ? 1 : kGatherSplit);
+    hipLaunchKernelGGL((k_half_gather<MODE, BATCH>), ggrid, dim3(256), 0, st, one, batch, tiles, S, ngrp);
     return hipGetLastError();
 }
 
@@ -608,8 +690,8 @@ static size_t part_regions(int n1, int n2, int S, int P) {
 }
 
 int half_split_groups(int n1, int n2, int S) {
-    // enough blocks for two tiles per CU on 256 CUs, at most kSplitCap groups
-    constexpr int kSplitCap = 4;
+    // enough blocks for two tiles per CU on 256 CUs, at most kHalfSplitCap groups
+    constexpr int kSplitCap = kHalfSplitCap;
     const int tiles = ((n1 + 31) / 32) * ((n2 + 63) / 64);
     int g = (512 + tiles - 1) / tiles;
     g = g > kSplitCap ? kSplitCap : g;

@@ -419,7 +419,10 @@ k_epilogue(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __rest
         tj0 = blockIdx.x * TW;
     }
     const float m = __uint_as_float((unsigned)(*d.key >> 32));
-    for (int idx = threadIdx.x; idx < TH * TW; idx += 256) {
+    // a single-image launch splits the tile's rows over gridDim.z blocks
+    const int rows = TH / (int)gridDim.z;
+    ti0 += (int)blockIdx.z * rows;
+    for (int idx = threadIdx.x; idx < rows * TW; idx += 256) {
         const int gi = ti0 + idx / TW, gj = tj0 + idx % TW;
         if (gi < d.n1 && gj < d.n2) {
             const size_t p = (size_t)gi * d.n2 + gj;
@@ -577,11 +580,16 @@ hipError_t launch_sweep(int mode, int S, int P, const ImgDesc& one, const ImgDes
                      : mode == kApply ? DSNLM_K_APPLY
                                       : DSNLM_K_PASS_C;
     if (P > kMaxP) return batch ? hipErrorInvalidValue : launch_wide(mode, S, P, one, st);
-    if (one.part && half_mode_ok(mode) && sweep_variant(mode, S, P) == kHalfVariant && half_lds_fits(S, P, mode))
+    if (sweep_takes_half(mode, S, P, one))
         return launch_half(mode, S, P, one, batch, tiles, ntiles, st);  // times its kernels itself
     ProfScope prof(kind, st);
     if (batch) return dispatch_p<true>(mode, S, P, one, batch, tiles, ntiles, st);
     return dispatch_p<false>(mode, S, P, one, batch, tiles, ntiles, st);
+}
+
+bool sweep_takes_half(int mode, int S, int P, const ImgDesc& one) {
+    return P <= kMaxP && one.part && half_mode_ok(mode) && sweep_variant(mode, S, P) == kHalfVariant &&
+           half_lds_fits(S, P, mode);
 }
 
 hipError_t launch_epilogue(const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
@@ -594,7 +602,7 @@ hipError_t launch_epilogue(const ImgDesc& one, const ImgDesc* batch, const TileR
         hipLaunchKernelGGL((k_epilogue<TH, TW, true>), dim3(ntiles), dim3(256), 0, st, one, batch,
                            tiles);
     } else {
-        dim3 grid((one.n2 + TW - 1) / TW, (one.n1 + TH - 1) / TH);
+        dim3 grid((one.n2 + TW - 1) / TW, (one.n1 + TH - 1) / TH, kGatherSplit);
         hipLaunchKernelGGL((k_epilogue<TH, TW, false>), grid, dim3(256), 0, st, one, batch, tiles);
     }
     return hipGetLastError();

@@ -52,7 +52,21 @@ struct ImgDesc {
     float kappa;           // 1 / (2 (2P+1)^2 h^2)
     float h;
     int tile_base;         // first entry of this image in a batch tile list
+    // Algorithm 1's dual half fused into the gather of a frozen apply
+    // (single image, half-window path): with lu set, the gather also forms
+    // v_new = x + B'/m (x = the denoiser input), u <- u + lx - v_new,
+    // v <- v_new and per-block partial sums of (lx - v_new)^2 and
+    // (v_new - v_old)^2 into lres (2 floats per gather block).
+    const float* lx;
+    float* lv;
+    float* lu;
+    float* lres;
 };
+
+// A single-image gather (and epilogue) splits each 32 x 64 tile's rows over
+// this many blocks, so that a small image still spreads over the CUs.
+constexpr int kGatherSplit = 4;
+inline int gather_blocks(int n1, int n2) { return ((n1 + 31) / 32) * ((n2 + 63) / 64) * kGatherSplit; }
 
 // Per-pixel float4 factors of sweep D are stored with this many zero-cost pad
 // pixels before and after each image, so that a thread's run of partners
@@ -119,6 +133,10 @@ size_t half_group_floats(int n1, int n2, int S, int groups);        // floats of
 float* half_zpad(float* part, int n1, int n2, int S, int P);  // the mirrored guide inside it
 bool half_lds_fits(int S, int P, int mode);
 bool half_mode_ok(int mode);
+// Whether launch_sweep runs `mode` on the half-window path for this
+// descriptor (whose gather of kApply then also writes y = x + B'/m when
+// d.y is set, and Algorithm 1's dual half when d.lu is set).
+bool sweep_takes_half(int mode, int S, int P, const ImgDesc& one);
 hipError_t launch_half(int mode, int S, int P, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
                        int ntiles, hipStream_t st);
 hipError_t prepare_half(int S, int P);

@@ -58,7 +58,10 @@ __device__ __forceinline__ int src_index(int k, int n) {
 }
 
 // r = A x - y on the low-resolution grid (y may be null: r = A x).
-template <int BOUNDARY>
+// BS > 0 fixes the blur size and F the factor at compile time (the loops
+// unroll, so all BS^2 loads of a sample are in flight together); BS = 0 takes
+// both from g.  Both forms add in the same order.
+template <int BOUNDARY, int BS, int F>
 __global__ void __launch_bounds__(256)
 k_sr_forward(const float* __restrict__ x, const float* __restrict__ y, float* __restrict__ r,
              SRGeom g, Taps taps) {
@@ -66,15 +69,30 @@ k_sr_forward(const float* __restrict__ x, const float* __restrict__ y, float* __
     if (idx >= g.m1 * g.m2) return;
     const int I = idx / g.m2, J = idx - I * g.m2;
     float acc = 0.f;
-    for (int a = 0; a < g.bs; ++a) {
-        const int i = src_index<BOUNDARY>(g.f * I + a - g.R, g.n1);
-        const float* row = x + (size_t)i * g.n2;
-        float ra = 0.f;
-        for (int b = 0; b < g.bs; ++b) {
-            const int j = src_index<BOUNDARY>(g.f * J + b - g.R, g.n2);
-            ra = fmaf(taps.t[b], row[j], ra);
+    if constexpr (BS > 0) {
+        constexpr int R = (BS - 1) / 2;
+        int jj[BS];
+#pragma unroll
+        for (int b = 0; b < BS; ++b) jj[b] = src_index<BOUNDARY>(F * J + b - R, g.n2);
+#pragma unroll
+        for (int a = 0; a < BS; ++a) {
+            const float* row = x + (size_t)src_index<BOUNDARY>(F * I + a - R, g.n1) * g.n2;
+            float ra = 0.f;
+#pragma unroll
+            for (int b = 0; b < BS; ++b) ra = fmaf(taps.t[b], row[jj[b]], ra);
+            acc = fmaf(taps.t[a], ra, acc);
         }
-        acc = fmaf(taps.t[a], ra, acc);
+    } else {
+        for (int a = 0; a < g.bs; ++a) {
+            const int i = src_index<BOUNDARY>(g.f * I + a - g.R, g.n1);
+            const float* row = x + (size_t)i * g.n2;
+            float ra = 0.f;
+            for (int b = 0; b < g.bs; ++b) {
+                const int j = src_index<BOUNDARY>(g.f * J + b - g.R, g.n2);
+                ra = fmaf(taps.t[b], row[j], ra);
+            }
+            acc = fmaf(taps.t[a], ra, acc);
+        }
     }
     r[idx] = y ? acc - y[idx] : acc;
 }
@@ -94,37 +112,68 @@ __device__ __forceinline__ int preimages(int i, int n, int R, int* out) {
     return c;
 }
 
+// The low-resolution samples I = lo..hi whose blur footprint covers padded
+// position p: 0 <= p - f I + R <= bs - 1, clamped to the grid [0, m).
+__device__ __forceinline__ void footprint(int p, int f, int R, int bs, int m, int* lo, int* hi) {
+    int l = p + R - (bs - 1);
+    l = l <= 0 ? 0 : (l + f - 1) / f;
+    int h = p + R;
+    h = h < 0 ? -1 : h / f;
+    *lo = l;
+    *hi = h > m - 1 ? m - 1 : h;
+}
+
 // (A^T r)(i, j): gather over the low-resolution samples whose footprint covers
-// a preimage of (i, j).
-template <int BOUNDARY>
+// a preimage of (i, j).  BS > 0: blur size BS and factor F fixed at compile
+// time, with at most ceil(BS / F) samples per axis and preimage (loops
+// unrolled, same order of additions as the general form).
+template <int BOUNDARY, int BS, int F>
 __device__ __forceinline__ float sr_adjoint_at(const float* __restrict__ r, int i, int j,
                                                const SRGeom& g, const Taps& taps) {
+    constexpr int NS = BS > 0 ? (BS + F - 1) / F : 1;
+    const int f = BS > 0 ? F : g.f, bs = BS > 0 ? BS : g.bs, R = (bs - 1) / 2;
     int pi[3], pj[3];
-    const int ci = preimages<BOUNDARY>(i, g.n1, g.R, pi);
-    const int cj = preimages<BOUNDARY>(j, g.n2, g.R, pj);
+    const int ci = preimages<BOUNDARY>(i, g.n1, R, pi);
+    const int cj = preimages<BOUNDARY>(j, g.n2, R, pj);
     float acc = 0.f;
     for (int a = 0; a < ci; ++a) {
         const int ip = pi[a];
-        // I with 0 <= ip - f I + R <= bs - 1
-        int Ilo = ip + g.R - (g.bs - 1);
-        Ilo = Ilo <= 0 ? 0 : (Ilo + g.f - 1) / g.f;
-        int Ihi = ip + g.R;
-        Ihi = Ihi < 0 ? -1 : Ihi / g.f;
-        if (Ihi > g.m1 - 1) Ihi = g.m1 - 1;
-        for (int I = Ilo; I <= Ihi; ++I) {
-            const float ta = taps.t[ip - g.f * I + g.R];
-            const float* rr = r + (size_t)I * g.m2;
-            float rowacc = 0.f;
-            for (int b = 0; b < cj; ++b) {
-                const int jp = pj[b];
-                int Jlo = jp + g.R - (g.bs - 1);
-                Jlo = Jlo <= 0 ? 0 : (Jlo + g.f - 1) / g.f;
-                int Jhi = jp + g.R;
-                Jhi = Jhi < 0 ? -1 : Jhi / g.f;
-                if (Jhi > g.m2 - 1) Jhi = g.m2 - 1;
-                for (int J = Jlo; J <= Jhi; ++J) rowacc = fmaf(taps.t[jp - g.f * J + g.R], rr[J], rowacc);
+        int Ilo, Ihi;
+        footprint(ip, f, R, bs, g.m1, &Ilo, &Ihi);
+        if constexpr (BS > 0) {
+#pragma unroll
+            for (int t = 0; t < NS; ++t) {
+                const int I = Ilo + t;
+                if (I <= Ihi) {
+                    const float ta = taps.t[ip - F * I + R];
+                    const float* rr = r + (size_t)I * g.m2;
+                    float rowacc = 0.f;
+                    for (int b = 0; b < cj; ++b) {
+                        const int jp = pj[b];
+                        int Jlo, Jhi;
+                        footprint(jp, F, R, BS, g.m2, &Jlo, &Jhi);
+#pragma unroll
+                        for (int q = 0; q < NS; ++q) {
+                            const int J = Jlo + q;
+                            if (J <= Jhi) rowacc = fmaf(taps.t[jp - F * J + R], rr[J], rowacc);
+                        }
+                    }
+                    acc = fmaf(ta, rowacc, acc);
+                }
             }
-            acc = fmaf(ta, rowacc, acc);
+        } else {
+            for (int I = Ilo; I <= Ihi; ++I) {
+                const float ta = taps.t[ip - f * I + R];
+                const float* rr = r + (size_t)I * g.m2;
+                float rowacc = 0.f;
+                for (int b = 0; b < cj; ++b) {
+                    const int jp = pj[b];
+                    int Jlo, Jhi;
+                    footprint(jp, f, R, bs, g.m2, &Jlo, &Jhi);
+                    for (int J = Jlo; J <= Jhi; ++J) rowacc = fmaf(taps.t[jp - f * J + R], rr[J], rowacc);
+                }
+                acc = fmaf(ta, rowacc, acc);
+            }
         }
     }
     return acc;
@@ -136,7 +185,53 @@ struct StepScalars {
 
 // x <- clip(mu (alpha x + rho (v - u) - A^T r)); z = x + u.
 // With step == 0 it only writes g = A^T r into xo (gradient / adjoint).
-template <int BOUNDARY>
+// Tap b[F t + ph] for a per-lane phase ph in [0, F) (0 past the kernel's end):
+// every index is a compile-time constant, so the taps stay in scalar registers.
+template <int BS, int F>
+__device__ __forceinline__ float phase_tap(const Taps& taps, int t, int ph) {
+    float v = taps.t[F * t];
+#pragma unroll
+    for (int e = 1; e < F; ++e)
+        if (ph == e) v = F * t + e < BS ? taps.t[F * t + e] : 0.f;
+    return v;
+}
+
+// (A^T r)(i, j) for a pixel with no mirrored or wrapped copy inside any
+// footprint (R <= i < n1 - R, R <= j < n2 - R): the samples of an axis are
+// I = (i + R) / F - t, t = 0 .. ceil(BS / F) - 1, with tap b[(i + R) % F + F t]
+// (zero where that passes the kernel); they all lie inside the grid.
+template <int BS, int F>
+__device__ __forceinline__ float sr_adjoint_interior(const float* __restrict__ r, int i, int j, const SRGeom& g,
+                                                     const Taps& taps) {
+    constexpr int R = (BS - 1) / 2, NS = (BS + F - 1) / F;
+    const int qi = i + R, qj = j + R;
+    const int phi = qi % F, phj = qj % F;
+    const int I0 = qi / F, J0 = qj / F;
+    float tb[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) tb[q] = phase_tap<BS, F>(taps, q, phj);
+    float rv[NS][NS];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        const int I = I0 - t > 0 ? I0 - t : 0;  // a zero tap's sample is clamped into the grid
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const int J = J0 - q > 0 ? J0 - q : 0;
+            rv[t][q] = r[(size_t)I * g.m2 + J];
+        }
+    }
+    float acc = 0.f;
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        float rowacc = 0.f;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) rowacc = fmaf(tb[q], rv[t][q], rowacc);
+        acc = fmaf(phase_tap<BS, F>(taps, t, phi), rowacc, acc);
+    }
+    return acc;
+}
+
+template <int BOUNDARY, int BS, int F>
 __global__ void __launch_bounds__(256)
 k_sr_adjoint_step(const float* __restrict__ r, float* __restrict__ x, const float* __restrict__ v,
                   const float* __restrict__ u, float* __restrict__ z, SRGeom g, Taps taps,
@@ -144,7 +239,16 @@ k_sr_adjoint_step(const float* __restrict__ r, float* __restrict__ x, const floa
     const int idx = blockIdx.x * 256 + threadIdx.x;
     if (idx >= g.n1 * g.n2) return;
     const int i = idx / g.n2, j = idx - i * g.n2;
-    const float grad = sr_adjoint_at<BOUNDARY>(r, i, j, g, taps);
+    float grad;
+    if constexpr (BS > 0) {
+        constexpr int R = (BS - 1) / 2;
+        if (i >= R && i < g.n1 - R && j >= R && j < g.n2 - R)
+            grad = sr_adjoint_interior<BS, F>(r, i, j, g, taps);
+        else
+            grad = sr_adjoint_at<BOUNDARY, BS, F>(r, i, j, g, taps);
+    } else {
+        grad = sr_adjoint_at<BOUNDARY, BS, F>(r, i, j, g, taps);
+    }
     if (!step) {
         x[idx] = grad;
         return;
@@ -153,6 +257,35 @@ k_sr_adjoint_step(const float* __restrict__ r, float* __restrict__ x, const floa
     xn = fminf(fmaxf(xn, s.lo), s.hi);
     x[idx] = xn;
     z[idx] = xn + u[idx];
+}
+
+// Launch the forward blur/decimation (r = A x - y) and the adjoint step on
+// st, with the compile-time form for the 9-tap, factor-2 operator of Section
+// 4.1 and the general form otherwise.
+void launch_sr_forward(const SRGeom& g, const Taps& taps, int boundary, const float* x, const float* y,
+                       float* r, hipStream_t st) {
+    const dim3 grid((g.m1 * g.m2 + 255) / 256);
+    const bool fixed = g.bs == 9 && g.f == 2;
+    if (boundary == 0) {
+        if (fixed) hipLaunchKernelGGL((k_sr_forward<0, 9, 2>), grid, dim3(256), 0, st, x, y, r, g, taps);
+        else hipLaunchKernelGGL((k_sr_forward<0, 0, 0>), grid, dim3(256), 0, st, x, y, r, g, taps);
+    } else {
+        if (fixed) hipLaunchKernelGGL((k_sr_forward<1, 9, 2>), grid, dim3(256), 0, st, x, y, r, g, taps);
+        else hipLaunchKernelGGL((k_sr_forward<1, 0, 0>), grid, dim3(256), 0, st, x, y, r, g, taps);
+    }
+}
+
+void launch_sr_adjoint(const SRGeom& g, const Taps& taps, int boundary, const float* r, float* x,
+                       const float* v, const float* u, float* z, const StepScalars& s, int step, hipStream_t st) {
+    const dim3 grid((g.n1 * g.n2 + 255) / 256);
+    const bool fixed = g.bs == 9 && g.f == 2;
+    if (boundary == 0) {
+        if (fixed) hipLaunchKernelGGL((k_sr_adjoint_step<0, 9, 2>), grid, dim3(256), 0, st, r, x, v, u, z, g, taps, s, step);
+        else hipLaunchKernelGGL((k_sr_adjoint_step<0, 0, 0>), grid, dim3(256), 0, st, r, x, v, u, z, g, taps, s, step);
+    } else {
+        if (fixed) hipLaunchKernelGGL((k_sr_adjoint_step<1, 9, 2>), grid, dim3(256), 0, st, r, x, v, u, z, g, taps, s, step);
+        else hipLaunchKernelGGL((k_sr_adjoint_step<1, 0, 0>), grid, dim3(256), 0, st, r, x, v, u, z, g, taps, s, step);
+    }
 }
 
 struct SPIScalars {
@@ -190,49 +323,60 @@ k_spi_step(float* __restrict__ x, const float* __restrict__ v, const float* __re
 }
 
 // v_new = z + B'/m (denoiser output); u <- u + x - v_new; v <- v_new; per-block
-// partial sums of (x - v_new)^2 and (v_new - v_old)^2.
+// partial sums of (x - v_new)^2 and (v_new - v_old)^2.  The blocks follow the
+// single-image gather's geometry (a 32 x 64 tile's rows split over gridDim.z
+// blocks), so both leave the same number of partials per iteration.
 __global__ void __launch_bounds__(256)
 k_ladmm_epilogue(const float* __restrict__ z, const float* __restrict__ bp,
                  const unsigned long long* __restrict__ key, const float* __restrict__ x,
-                 float* __restrict__ v, float* __restrict__ u, int n, float* __restrict__ partials) {
-    const int idx = blockIdx.x * 256 + threadIdx.x;
+                 float* __restrict__ v, float* __restrict__ u, int n1, int n2, float* __restrict__ partials) {
+    constexpr int TH = 32, TW = 64;
     const float m = __uint_as_float((unsigned)(*key >> 32));
+    const int rows = TH / (int)gridDim.z;
+    const int i0 = (int)blockIdx.y * TH + (int)blockIdx.z * rows, j0 = (int)blockIdx.x * TW;
     float p = 0.f, d = 0.f;
-    if (idx < n) {
+    for (int e = threadIdx.x; e < rows * TW; e += 256) {
+        const int gi = i0 + e / TW, gj = j0 + e % TW;
+        if (gi >= n1 || gj >= n2) continue;
+        const size_t idx = (size_t)gi * n2 + gj;
         const float vn = z[idx] + bp[idx] / m;
         const float xv = x[idx];
         const float vo = v[idx];
         u[idx] = u[idx] + xv - vn;
         v[idx] = vn;
-        p = (xv - vn) * (xv - vn);
-        d = (vn - vo) * (vn - vo);
+        p = fmaf(xv - vn, xv - vn, p);
+        d = fmaf(vn - vo, vn - vo, d);
     }
     if (!partials) return;
-    __shared__ float sp[256], sd[256];
-    sp[threadIdx.x] = p;
-    sd[threadIdx.x] = d;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            sp[threadIdx.x] += sp[threadIdx.x + w];
-            sd[threadIdx.x] += sd[threadIdx.x + w];
-        }
-        __syncthreads();
+    __shared__ float wsum[2][4];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        p += __shfl_xor(p, off, 64);
+        d += __shfl_xor(d, off, 64);
     }
+    if ((threadIdx.x & 63) == 0) {
+        wsum[0][threadIdx.x >> 6] = p;
+        wsum[1][threadIdx.x >> 6] = d;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        partials[2 * blockIdx.x] = sp[0];
-        partials[2 * blockIdx.x + 1] = sd[0];
+        const int b = ((int)blockIdx.z * (int)gridDim.y + (int)blockIdx.y) * (int)gridDim.x + (int)blockIdx.x;
+        partials[2 * b] = (wsum[0][0] + wsum[0][1]) + (wsum[0][2] + wsum[0][3]);
+        partials[2 * b + 1] = (wsum[1][0] + wsum[1][1]) + (wsum[1][2] + wsum[1][3]);
     }
 }
 
-// out[0] = sqrt(sum_p / n), out[1] = rho sqrt(sum_d / n); fixed order.
+// Iteration blockIdx.x: out[2k] = sqrt(sum_p / n), out[2k+1] = rho sqrt(sum_d / n)
+// from its nblk partial pairs at partials + k * stride; fixed order.
 __global__ void __launch_bounds__(256)
-k_residual_final(const float* __restrict__ partials, int nblk, int n, float rho, float* __restrict__ out) {
+k_residual_final(const float* __restrict__ partials, size_t stride, int nblk, int n, float rho,
+                 float* __restrict__ out) {
+    const float* pk = partials + blockIdx.x * stride;
     __shared__ double sp[256], sd[256];
     double p = 0.0, d = 0.0;
     for (int b = threadIdx.x; b < nblk; b += 256) {
-        p += partials[2 * b];
-        d += partials[2 * b + 1];
+        p += pk[2 * b];
+        d += pk[2 * b + 1];
     }
     sp[threadIdx.x] = p;
     sd[threadIdx.x] = d;
@@ -245,8 +389,8 @@ k_residual_final(const float* __restrict__ partials, int nblk, int n, float rho,
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        out[0] = (float)sqrt(sp[0] / n);
-        out[1] = (float)(rho * sqrt(sd[0] / n));
+        out[2 * blockIdx.x] = (float)sqrt(sp[0] / n);
+        out[2 * blockIdx.x + 1] = (float)(rho * sqrt(sd[0] / n));
     }
 }
 
@@ -408,16 +552,28 @@ float* scratch_floats(dsnlm_weights* w, size_t n, int* rc) {
     return w->scratch;
 }
 
+// Floats per iteration slot of the residual partials: two per gather (or
+// epilogue) block, and at least one per 256 pixels (the CG solver's dot
+// products use slot 0).
+size_t partial_stride(int n1, int n2) {
+    const size_t a = 2 * (size_t)gather_blocks(n1, n2), b = (size_t)blocks((size_t)n1 * n2);
+    return ((a > b ? a : b) + 63) & ~(size_t)63;
+}
+
 // The denoising and dual halves of an iteration (shared by Algorithm 1 and
 // the standard ADMM comparator): v = D(z) with z = x + u already in w->zbuf,
-// u <- u + x - v, residuals and checkpoints.
+// u <- u + x - v, and checkpoints.  With want_res the iteration's residual
+// partials go to `partials` (gather_blocks pairs, reduced by the caller).
+// A frozen iteration on the half-window path does the dual half inside the
+// apply's gather (m is known), so no separate update kernel runs.
 int enqueue_denoise_dual(const ladmm_params* p, int k, dsnlm_weights* w, float* x, float* v, float* u,
-                         float* partials, float* res, float* ckpt, hipStream_t st) {
+                         float* partials, bool want_res, float* ckpt, hipStream_t st) {
     const int n = w->n1 * w->n2;
     float* z = w->zbuf;
     ImgDesc d = base_desc(w);
     d.x = z;
     int rc;
+    bool fused = false;
     if (p->denoiser == 1) {
         // plain NLM of z guided by z: writes its increment into B' and m = 1
         rc = check_hip(hipMemcpyAsync(w->guide, z, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st),
@@ -433,15 +589,21 @@ int enqueue_denoise_dual(const ladmm_params* p, int k, dsnlm_weights* w, float* 
         if (!rc) rc = check_hip(launch_sweep(kPassA, p->S, p->P, d, nullptr, nullptr, 0, st), "pass A");
         if (!rc) rc = check_hip(launch_sweep(kPassBApply, p->S, p->P, d, nullptr, nullptr, 0, st), "pass B");
     } else {
+        fused = sweep_takes_half(kApply, p->S, p->P, d);
+        if (fused) {
+            d.lx = x;
+            d.lv = v;
+            d.lu = u;
+            d.lres = want_res ? partials : nullptr;
+        }
         rc = check_hip(launch_sweep(kApply, p->S, p->P, d, nullptr, nullptr, 0, st), "apply sweep");
     }
     if (rc) return rc;
-    {
+    if (!fused) {
         ProfScope prof(DSNLM_K_LADMM, st);
-        hipLaunchKernelGGL(k_ladmm_epilogue, dim3(blocks(n)), dim3(256), 0, st, z, w->bp, w->key, x, v, u, n,
-                           res ? partials : nullptr);
-        if (res)
-            hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(256), 0, st, partials, blocks(n), n, p->rho, res);
+        const dim3 grid((w->n2 + 63) / 64, (w->n1 + 31) / 32, kGatherSplit);
+        hipLaunchKernelGGL(k_ladmm_epilogue, grid, dim3(256), 0, st, z, w->bp, w->key, x, v, u, w->n1, w->n2,
+                           want_res ? partials : nullptr);
         rc = check_hip(hipGetLastError(), "dual update");
         if (rc) return rc;
     }
@@ -456,12 +618,22 @@ int enqueue_denoise_dual(const ladmm_params* p, int k, dsnlm_weights* w, float* 
     return rc;
 }
 
+// Reduce the residual partials of `iters` consecutive slots into res
+// ([iters][2]).
+int enqueue_residuals(const float* partials, int n1, int n2, int iters, float rho, float* res, hipStream_t st) {
+    ProfScope prof(DSNLM_K_LADMM, st);
+    hipLaunchKernelGGL(k_residual_final, dim3(iters), dim3(256), 0, st, partials, partial_stride(n1, n2),
+                       gather_blocks(n1, n2), n1 * n2, rho, res);
+    return check_hip(hipGetLastError(), "residual reduction");
+}
+
 // Enqueue iteration k of Algorithm 1.  lr: scratch for the low-resolution
-// residual (SR); partials: scratch for residual partials or null; res: device
-// [2] or null; ckpt: device [4][n] or null.
+// residual (SR); partials: this iteration's slot of residual partials (written
+// when want_res); ckpt: device [4][n] or null.
 int enqueue_step(const ladmm_operator* op, const OpView& ov, const ladmm_params* p, float h, int k,
                  dsnlm_weights* w, float* x, float* v, float* u, float* lr, float* partials,
-                 float* res, float* ckpt, hipStream_t st) {
+                 bool want_res, float* ckpt, hipStream_t st) {
+    (void)h;
     const int n = op->n1 * op->n2;
     const float alpha = 1.0f / p->gamma;
     StepScalars s{alpha, p->rho, 1.0f / (alpha + p->rho), p->lo, p->hi};
@@ -469,23 +641,15 @@ int enqueue_step(const ladmm_operator* op, const OpView& ov, const ladmm_params*
     {
         ProfScope prof(DSNLM_K_LADMM, st);
         if (op->kind == LADMM_OP_SR) {
-            const int mlr = ov.g.m1 * ov.g.m2;
-            if (op->boundary == 0) {
-                hipLaunchKernelGGL(k_sr_forward<0>, dim3(blocks(mlr)), dim3(256), 0, st, x, op->y, lr, ov.g, ov.taps);
-                hipLaunchKernelGGL(k_sr_adjoint_step<0>, dim3(blocks(n)), dim3(256), 0, st, lr, x, v, u, z, ov.g,
-                                   ov.taps, s, 1);
-            } else {
-                hipLaunchKernelGGL(k_sr_forward<1>, dim3(blocks(mlr)), dim3(256), 0, st, x, op->y, lr, ov.g, ov.taps);
-                hipLaunchKernelGGL(k_sr_adjoint_step<1>, dim3(blocks(n)), dim3(256), 0, st, lr, x, v, u, z, ov.g,
-                                   ov.taps, s, 1);
-            }
+            launch_sr_forward(ov.g, ov.taps, op->boundary, x, op->y, lr, st);
+            launch_sr_adjoint(ov.g, ov.taps, op->boundary, lr, x, v, u, z, s, 1, st);
         } else {
             hipLaunchKernelGGL(k_spi_step, dim3(blocks(n)), dim3(256), 0, st, x, v, u, z, op->ones, n, ov.q, s, 1);
         }
         int rc = check_hip(hipGetLastError(), "x-step");
         if (rc) return rc;
     }
-    return enqueue_denoise_dual(p, k, w, x, v, u, partials, res, ckpt, st);
+    return enqueue_denoise_dual(p, k, w, x, v, u, partials, want_res, ckpt, st);
 }
 
 // ---- standard plug-and-play ADMM with a conjugate-gradient inversion (the
@@ -596,29 +760,24 @@ void enqueue_AtA(const ladmm_operator* op, const OpView& ov, const float* x, flo
                  hipStream_t st) {
     const int n = op->n1 * op->n2, mlr = ov.g.m1 * ov.g.m2;
     StepScalars s{};
-    if (op->boundary == 0) {
-        hipLaunchKernelGGL(k_sr_forward<0>, dim3(blocks(mlr)), dim3(256), 0, st, x, nullptr, lr, ov.g, ov.taps);
-        hipLaunchKernelGGL(k_sr_adjoint_step<0>, dim3(blocks(n)), dim3(256), 0, st, lr, out, nullptr, nullptr,
-                           nullptr, ov.g, ov.taps, s, 0);
-    } else {
-        hipLaunchKernelGGL(k_sr_forward<1>, dim3(blocks(mlr)), dim3(256), 0, st, x, nullptr, lr, ov.g, ov.taps);
-        hipLaunchKernelGGL(k_sr_adjoint_step<1>, dim3(blocks(n)), dim3(256), 0, st, lr, out, nullptr, nullptr,
-                           nullptr, ov.g, ov.taps, s, 0);
-    }
+    launch_sr_forward(ov.g, ov.taps, op->boundary, x, nullptr, lr, st);
+    launch_sr_adjoint(ov.g, ov.taps, op->boundary, lr, out, nullptr, nullptr, nullptr, s, 0, st);
 }
 
-// Solver scratch layout inside the handle: [z: n][lr: m][partials: 2*blocks(n)]
-int ensure_solver_scratch(dsnlm_weights* w, const OpView& ov, const ladmm_operator* op, float** lr,
+// Solver scratch layout inside the handle: [z: n][lr: m][partials: slots x
+// partial_stride] (one slot of residual partials per iteration of a solve).
+int ensure_solver_scratch(dsnlm_weights* w, const OpView& ov, const ladmm_operator* op, int slots, float** lr,
                           float** partials) {
     const size_t n = (size_t)op->n1 * op->n2;
     const size_t mlr = op->kind == LADMM_OP_SR ? (size_t)ov.g.m1 * ov.g.m2 : 0;
-    const size_t need = n + mlr + 2 * (size_t)blocks(n) + 64;
+    const size_t lead = (n + mlr + 63) & ~(size_t)63;
+    const size_t need = lead + (size_t)(slots < 1 ? 1 : slots) * partial_stride(op->n1, op->n2) + 64;
     int rc;
     float* base = scratch_floats(w, need, &rc);
     if (!base) return rc;
     w->zbuf = base;
     *lr = base + n;
-    *partials = base + n + mlr;
+    *partials = base + lead;
     return DSNLM_OK;
 }
 
@@ -633,12 +792,14 @@ int ensure_solver_scratch(dsnlm_weights* w, const OpView& ov, const ladmm_operat
 int enqueue_solve(const ladmm_operator* op, const OpView& ov, const ladmm_params* p, float h, dsnlm_weights* w,
                   float* x, float* v, float* u, float* residuals, float* checkpoints, hipStream_t st) {
     float *lr, *partials;
-    int rc = ensure_solver_scratch(w, ov, op, &lr, &partials);
+    int rc = ensure_solver_scratch(w, ov, op, residuals ? p->iters : 1, &lr, &partials);
     const size_t n = (size_t)op->n1 * op->n2;
+    const size_t stride = partial_stride(op->n1, op->n2);
     for (int k = 1; k <= p->iters && !rc; ++k)
-        rc = enqueue_step(op, ov, p, h, k, w, x, v, u, lr, partials,
-                          residuals ? residuals + 2 * (size_t)(k - 1) : nullptr,
-                          checkpoints ? checkpoints + 4 * n * (size_t)(k - 1) : nullptr, st);
+        rc = enqueue_step(op, ov, p, h, k, w, x, v, u, lr, partials + (residuals ? (k - 1) * stride : 0),
+                          residuals != nullptr, checkpoints ? checkpoints + 4 * n * (size_t)(k - 1) : nullptr, st);
+    // every iteration's residual norms in one fixed-order reduction at the end
+    if (!rc && residuals) rc = enqueue_residuals(partials, op->n1, op->n2, p->iters, p->rho, residuals, st);
     return rc;
 }
 
@@ -739,7 +900,7 @@ int solve_entry(const SolveKey& key, const ladmm_operator* op, const OpView& ov,
     iop.ones = e->ones;
     rc = prepare_handle(op->n1, op->n2, p->S, p->P, h, &e->w);
     float *lr, *partials;
-    if (!rc) rc = ensure_solver_scratch(e->w, ov, op, &lr, &partials);
+    if (!rc) rc = ensure_solver_scratch(e->w, ov, op, key.want_res ? p->iters : 1, &lr, &partials);
     if (!rc) rc = check_hip(prepare_sweeps(p->S, p->P), "sweep attributes");
     if (!rc) rc = check_hip(hipEventCreateWithFlags(&e->ev_in, hipEventDisableTiming), "ladmm_solve: event");
     if (!rc) rc = check_hip(hipEventCreateWithFlags(&e->ev_out, hipEventDisableTiming), "ladmm_solve: event");
@@ -775,17 +936,9 @@ int sr_apply_AtA(const ladmm_operator* op, const float* x, float* lr, float* out
     OpView ov;
     int rc = check_operator(op, false, "sr_apply_AtA", &ov);
     if (rc) return rc;
-    const int n = op->n1 * op->n2, mlr = ov.g.m1 * ov.g.m2;
     StepScalars s{};
-    if (op->boundary == 0) {
-        hipLaunchKernelGGL(k_sr_forward<0>, dim3(blocks(mlr)), dim3(256), 0, st, x, nullptr, lr, ov.g, ov.taps);
-        hipLaunchKernelGGL(k_sr_adjoint_step<0>, dim3(blocks(n)), dim3(256), 0, st, lr, out, nullptr, nullptr, nullptr,
-                           ov.g, ov.taps, s, 0);
-    } else {
-        hipLaunchKernelGGL(k_sr_forward<1>, dim3(blocks(mlr)), dim3(256), 0, st, x, nullptr, lr, ov.g, ov.taps);
-        hipLaunchKernelGGL(k_sr_adjoint_step<1>, dim3(blocks(n)), dim3(256), 0, st, lr, out, nullptr, nullptr, nullptr,
-                           ov.g, ov.taps, s, 0);
-    }
+    launch_sr_forward(ov.g, ov.taps, op->boundary, x, nullptr, lr, st);
+    launch_sr_adjoint(ov.g, ov.taps, op->boundary, lr, out, nullptr, nullptr, nullptr, s, 0, st);
     return check_hip(hipGetLastError(), "A^T A");
 }
 
@@ -818,9 +971,9 @@ int ladmm_step(const ladmm_operator* op, const ladmm_params* p, int k, dsnlm_wei
         if (rc) return rc;
     }
     float *lr, *partials;
-    rc = ensure_solver_scratch(*w, ov, op, &lr, &partials);
+    rc = ensure_solver_scratch(*w, ov, op, 1, &lr, &partials);
     if (rc) return rc;
-    return enqueue_step(op, ov, p, h, k, *w, x, v, u, lr, partials, nullptr, nullptr,
+    return enqueue_step(op, ov, p, h, k, *w, x, v, u, lr, partials, false, nullptr,
                         static_cast<hipStream_t>(stream));
 }
 
@@ -922,10 +1075,7 @@ int ladmm_apply_forward(const ladmm_operator* op, const float* x, float* out, vo
     hipStream_t st = static_cast<hipStream_t>(stream);
     ProfScope prof(DSNLM_K_LADMM, st);
     const int mlr = ov.g.m1 * ov.g.m2;
-    if (op->boundary == 0)
-        hipLaunchKernelGGL(k_sr_forward<0>, dim3(blocks(mlr)), dim3(256), 0, st, x, nullptr, out, ov.g, ov.taps);
-    else
-        hipLaunchKernelGGL(k_sr_forward<1>, dim3(blocks(mlr)), dim3(256), 0, st, x, nullptr, out, ov.g, ov.taps);
+    launch_sr_forward(ov.g, ov.taps, op->boundary, x, nullptr, out, st);
     return check_hip(hipGetLastError(), "ladmm_apply_forward");
 }
 
@@ -949,15 +1099,8 @@ int ladmm_gradient(const ladmm_operator* op, const float* x, float* g, void* str
     {
         ProfScope prof(DSNLM_K_LADMM, st);
         const int mlr = ov.g.m1 * ov.g.m2;
-        if (op->boundary == 0) {
-            hipLaunchKernelGGL(k_sr_forward<0>, dim3(blocks(mlr)), dim3(256), 0, st, x, op->y, lr, ov.g, ov.taps);
-            hipLaunchKernelGGL(k_sr_adjoint_step<0>, dim3(blocks(n)), dim3(256), 0, st, lr, g, nullptr, nullptr,
-                               nullptr, ov.g, ov.taps, s, 0);
-        } else {
-            hipLaunchKernelGGL(k_sr_forward<1>, dim3(blocks(mlr)), dim3(256), 0, st, x, op->y, lr, ov.g, ov.taps);
-            hipLaunchKernelGGL(k_sr_adjoint_step<1>, dim3(blocks(n)), dim3(256), 0, st, lr, g, nullptr, nullptr,
-                               nullptr, ov.g, ov.taps, s, 0);
-        }
+        launch_sr_forward(ov.g, ov.taps, op->boundary, x, op->y, lr, st);
+        launch_sr_adjoint(ov.g, ov.taps, op->boundary, lr, g, nullptr, nullptr, nullptr, s, 0, st);
         rc = check_hip(hipGetLastError(), "ladmm_gradient");
     }
     hipError_t e = hipStreamSynchronize(st);
@@ -991,15 +1134,8 @@ int ladmm_operator_norm2(const ladmm_operator* op, int iters, float* out, void* 
         hipLaunchKernelGGL(k_dot2_final, dim3(1), dim3(256), 0, st, part, blocks(n), red);
         hipLaunchKernelGGL(k_normalize, dim3(blocks(n)), dim3(256), 0, st, v, red, n);
         for (int it = 0; it < iters; ++it) {
-            if (op->boundary == 0) {
-                hipLaunchKernelGGL(k_sr_forward<0>, dim3(blocks(mlr)), dim3(256), 0, st, v, nullptr, lr, ov.g, ov.taps);
-                hipLaunchKernelGGL(k_sr_adjoint_step<0>, dim3(blocks(n)), dim3(256), 0, st, lr, g, nullptr, nullptr,
-                                   nullptr, ov.g, ov.taps, s, 0);
-            } else {
-                hipLaunchKernelGGL(k_sr_forward<1>, dim3(blocks(mlr)), dim3(256), 0, st, v, nullptr, lr, ov.g, ov.taps);
-                hipLaunchKernelGGL(k_sr_adjoint_step<1>, dim3(blocks(n)), dim3(256), 0, st, lr, g, nullptr, nullptr,
-                                   nullptr, ov.g, ov.taps, s, 0);
-            }
+            launch_sr_forward(ov.g, ov.taps, op->boundary, v, nullptr, lr, st);
+            launch_sr_adjoint(ov.g, ov.taps, op->boundary, lr, g, nullptr, nullptr, nullptr, s, 0, st);
             hipLaunchKernelGGL(k_dot2, dim3(blocks(n)), dim3(256), 0, st, v, g, n, part);
             hipLaunchKernelGGL(k_dot2_final, dim3(1), dim3(256), 0, st, part, blocks(n), red);
             hipLaunchKernelGGL(k_scale_into, dim3(blocks(n)), dim3(256), 0, st, g, red, v, n);
@@ -1037,7 +1173,7 @@ extern "C" int admm_cg_solve(const ladmm_operator* op, const ladmm_params* p, in
     rc = prepare_handle(op->n1, op->n2, p->S, p->P, h, &w);
     if (rc) return rc;
     float *lr, *partials;
-    rc = ensure_solver_scratch(w, ov, op, &lr, &partials);
+    rc = ensure_solver_scratch(w, ov, op, 1, &lr, &partials);
     const size_t n = (size_t)op->n1 * op->n2;
     const int nb = blocks(n);
     // CG vectors: A^T y, r, p, q (n each) and the device scalars
@@ -1055,13 +1191,7 @@ extern "C" int admm_cg_solve(const ladmm_operator* op, const ladmm_params* p, in
     {
         ProfScope prof(DSNLM_K_LADMM, st);
         StepScalars s{};
-        if (op->boundary == 0) {
-            hipLaunchKernelGGL(k_sr_adjoint_step<0>, dim3(nb), dim3(256), 0, st, op->y, aty, nullptr, nullptr,
-                               nullptr, ov.g, ov.taps, s, 0);
-        } else {
-            hipLaunchKernelGGL(k_sr_adjoint_step<1>, dim3(nb), dim3(256), 0, st, op->y, aty, nullptr, nullptr,
-                               nullptr, ov.g, ov.taps, s, 0);
-        }
+        launch_sr_adjoint(ov.g, ov.taps, op->boundary, op->y, aty, nullptr, nullptr, nullptr, s, 0, st);
         rc = check_hip(hipGetLastError(), "A^T y");
     }
     for (int k = 1; k <= p->iters && !rc; ++k) {
@@ -1082,9 +1212,9 @@ extern "C" int admm_cg_solve(const ladmm_operator* op, const ladmm_params* p, in
             hipLaunchKernelGGL(k_add, dim3(nb), dim3(256), 0, st, x, u, w->zbuf, (int)n);
             rc = check_hip(hipGetLastError(), "conjugate gradients");
         }
-        if (!rc)
-            rc = enqueue_denoise_dual(p, k, w, x, v, u, partials,
-                                      residuals ? residuals + 2 * (size_t)(k - 1) : nullptr, nullptr, st);
+        if (!rc) rc = enqueue_denoise_dual(p, k, w, x, v, u, partials, residuals != nullptr, nullptr, st);
+        if (!rc && residuals)
+            rc = enqueue_residuals(partials, op->n1, op->n2, 1, p->rho, residuals + 2 * (size_t)(k - 1), st);
     }
     if (!rc) rc = check_hip(hipStreamSynchronize(st), "admm_cg_solve synchronise");
     (void)hipFree(cgbuf);
