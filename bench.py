@@ -1,15 +1,19 @@
 """Benchmark of the DSG-NLM forward on one MI355X.
 
 Workload: 64 synthetic piecewise-smooth images of uneven sizes (sides from
-{128, ..., 1024}, square or 2:1, about 17 Mpx in total), search half-width
+{128, ..., 1024}, square or 2:1, about 20 Mpx in total), search half-width
 S = 10 (21 x 21 window), patch half-width P = 3 (7 x 7 patches), h = 1.2
 sigma_n per image, FP32.  One step = the DSG-NLM forward y = W(x) x of every
-image of the batch (inputs resident in HBM).
+image of the batch (inputs resident in HBM), batched launches.
 
 Prints one JSON line: Mpixel/s of the forward, the dominant kernel's roofline
 fraction (its device time measured with HIP events on its launch stream), the
-forward+backward / forward time ratio, and the FP64 oracle timed on the host
-cores over a bounded sample of the same workload.
+same images with one launch sequence per image, the forward+backward /
+forward time ratio with the backward sweeps' roofline fractions, the
+differentiated 8 x 256^2 batch, the 512^2 super-resolution solve, the
+unrolled single-photon solve with its reverse pass (16 x 256^2), and the FP64
+oracle timed on the host (one thread and all cores) over a bounded sample of
+the same workload.
 """
 from __future__ import annotations
 
@@ -38,6 +42,13 @@ EXP_SLOTS_FALLBACK = 4.0
 #   pass A adds 2 (omega at s and at s + d); pass B adds 4 (two FMAs at each)
 VALU_PASS_A = 9
 VALU_PASS_B = 11
+# Backward, per evaluated pair: sweep C is pass B's form with the backward's
+# partner factors (11); sweep D recomputes the weight (7) and adds the pair's
+# weight adjoint from both sides (4), D-bar = -kappa a (sum) (2), the h-bar
+# partial (1), the separable box adjoint of D-bar (4) and the guide-gradient
+# terms at both patch positions (2): 20.
+VALU_SWEEP_C = 11
+VALU_SWEEP_D = 20
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_half_b_batched64_S10P3.md")
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_1901_06110_amd", "csrc", "dsnlm_half.hip")
 
@@ -69,33 +80,95 @@ def window_pairs(n1: int, n2: int, S: int) -> int:
     return axis(n1) * axis(n2)
 
 
-def cpu_baseline(images, S, P, budget_s: float = 20.0):
-    """FP64 oracle (shift-loop route) on crops of the first images until about
-    budget_s seconds of host time have been spent."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(images, S, P, budget_s: float = 10.0):
+    """FP64 oracle (shift-loop route, torch CPU) on crops of the batch's images
+    until about budget_s seconds of host time have been spent, once with one
+    thread and once with every core this process may run on."""
     import torch
     from oracle import dsnlm_ref
-    crop = 192
-    done_px = 0
-    t0 = time.perf_counter()
-    used = 0
-    for it in images:
-        x = it.noisy[:crop, :crop]
-        dsnlm_ref.dsnlm_shifts(x, x, S, P, it.h)
-        done_px += x.size
-        used += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return dict(value=done_px / dt / 1e6, unit="Mpixel/s", cores=torch.get_num_threads(),
-                kind="oracle",
-                sample=f"{used} crops of up to {crop}x{crop} px from the batch, S={S}, P={P}, "
-                       f"{done_px} px in {dt:.1f} s (FP64 shift loop, torch CPU)")
+    crop = 160
+    cores = len(os.sched_getaffinity(0))
+    prev = torch.get_num_threads()
+
+    def run(threads):
+        torch.set_num_threads(threads)
+        done_px, used = 0, 0
+        t0 = time.perf_counter()
+        for it in images:
+            x = it.noisy[:crop, :crop]
+            dsnlm_ref.dsnlm_shifts(x, x, S, P, it.h)
+            done_px += x.size
+            used += 1
+            if time.perf_counter() - t0 >= budget_s:
+                break
+        dt = time.perf_counter() - t0
+        return done_px / dt / 1e6, used, done_px, dt
+
+    try:
+        v1, u1, px1, dt1 = run(1)
+        vn, un, pxn, dtn = run(cores)
+    finally:
+        torch.set_num_threads(prev)
+    return dict(value=vn, unit="Mpixel/s", cores=cores, kind="oracle",
+                sample=f"crops of up to {crop}x{crop} px from the batch, S={S}, P={P} (FP64 shift loop, "
+                       f"torch CPU): {un} crops, {pxn} px in {dtn:.1f} s on {cores} threads; "
+                       f"{u1} crops, {px1} px in {dt1:.1f} s on 1 thread",
+                single_thread_value=v1, cpu_model=_cpu_model())
 
 
-def fwd_bwd_ratio(M, xs, hs, S, P, steps):
-    """Time the batched forward alone and the batched forward + backward
-    (input, guide and h gradients of every image); return the ratio."""
+def _device_time(fn, steps):
+    """Average device milliseconds of fn() over `steps` runs (HIP events on
+    the current stream, one warm-up run first)."""
     import torch
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def _kernel_ms(lib, kinds, fn, reps):
+    """Per-kind device milliseconds (and launches) of fn() per call, from the
+    library's own HIP events on each kernel's launch stream."""
+    import ctypes as C
+    import torch
+    lib.dsnlm_profile_reset()
+    lib.dsnlm_profile_enable(1)
+    try:
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        out = {}
+        for name, kind in kinds:
+            t = C.c_double()
+            n = C.c_int()
+            lib.dsnlm_profile_query(kind, C.byref(t), C.byref(n))
+            out[name] = (t.value / reps, n.value / reps)
+    finally:
+        lib.dsnlm_profile_enable(0)
+    return out
+
+
+def fwd_bwd_ratio(M, lib, xs, hs, S, P, steps, half_pairs, exp_slots):
+    """Time the batched forward alone and the batched forward + backward
+    (input, guide and h gradients of every image); the ratio, and the
+    backward sweeps' and the whole step's fractions of the VALU roofline."""
+    from paper_1901_06110_amd import _lib
     imgs = [(x, x, h) for x, h in zip(xs, hs)]
     outs = M.dsnlm_forward_batched(imgs, S, P)
     ybars = [2.0 * (y - x) for x, y in zip(xs, outs)]
@@ -107,29 +180,132 @@ def fwd_bwd_ratio(M, xs, hs, S, P, steps):
         fwd()
         M.dsnlm_backward_batched(ybars)
 
-    def timed(fn):
-        fn()
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(steps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / steps
-
-    tf = timed(fwd)
-    tfb = timed(fwd_bwd)
+    tf = _device_time(fwd, steps)
+    tfb = _device_time(fwd_bwd, steps)
+    km = _kernel_ms(lib, [("sweep_c", _lib.K_PASS_C), ("sweep_d", _lib.K_PASS_D)], fwd_bwd, 2)
+    ops = lambda valu: (valu + exp_slots) * half_pairs  # lane-op slots per launch
+    frac = lambda valu, ms: ops(valu) / (ms * 1e-3) / VALU_LANE_OPS_PER_S
+    total_ops = ops(VALU_PASS_A) + ops(VALU_PASS_B) + ops(VALU_SWEEP_C) + ops(VALU_SWEEP_D)
     return {"fwd_ms": tf, "fwd_bwd_ms": tfb, "ratio": tfb / tf,
             "fwd_bwd_mpx_s": sum(x.numel() for x in xs) / (tfb * 1e-3) / 1e6,
-            "note": "batched launches, %d images, S=%d, P=%d; backward = d/dx, d/dguide, d/dh"
-                    % (len(xs), S, P)}
+            "fwd_bwd_roofline_frac": total_ops / (tfb * 1e-3) / VALU_LANE_OPS_PER_S,
+            "sweep_c_ms": km["sweep_c"][0], "sweep_d_ms": km["sweep_d"][0],
+            "sweep_c_roofline_frac": frac(VALU_SWEEP_C, km["sweep_c"][0]),
+            "sweep_d_roofline_frac": frac(VALU_SWEEP_D, km["sweep_d"][0]),
+            "ops_per_pair": {"pass_a": VALU_PASS_A, "pass_b": VALU_PASS_B, "sweep_c": VALU_SWEEP_C,
+                             "sweep_d": VALU_SWEEP_D, "exp_slots_each": exp_slots},
+            "note": "batched launches, %d images, S=%d, P=%d; backward = d/dx, d/dguide, d/dh; "
+                    "roofline on the non-packed VALU peak, half-window pair counts" % (len(xs), S, P)}
+
+
+def per_image_timing(M, xs, hs, ys_batched, S, P, steps):
+    """The same images denoised by one dsnlm_forward per image (handles
+    reused, so no allocation in the timed region), against the batched
+    launches; with the largest difference between the two outputs."""
+    import torch
+    ys = [torch.empty_like(x) for x in xs]
+    handles = []
+    for x, y, h in zip(xs, ys, hs):
+        _, w = M.dsnlm_forward(x, None, S, P, h, y=y, keep=True)
+        handles.append(w)
+
+    def step():
+        for x, y, h, w in zip(xs, ys, hs, handles):
+            M.dsnlm_forward(x, None, S, P, h, y=y, weights=w)
+
+    ms = _device_time(step, steps)
+    diff = max(float((a - b).abs().max()) for a, b in zip(ys, ys_batched))
+    return {"ms_per_step": ms, "mpx_s": sum(x.numel() for x in xs) / (ms * 1e-3) / 1e6,
+            "max_abs_diff_vs_batched": diff,
+            "note": "one dsnlm_forward launch sequence per image (small images split each tile's dx "
+                    "range over blocks, so the two forms agree up to FP32 summation order)"}
+
+
+def differentiated_batch_timing(M, steps):
+    """8 images of 256 x 256, S = 7, P = 3, h = 0.1: batched forward and the
+    gradients of ||W(g, h) x - x_clean||^2 with respect to x, the guide and h."""
+    import torch
+    import synth
+    S, P, h = 7, 3, 0.1
+    pairs = synth.config3_batch()
+    xs = [torch.as_tensor(n).cuda() for _, n in pairs]
+    cl = [torch.as_tensor(c).cuda() for c, _ in pairs]
+    imgs = [(x, x, h) for x in xs]
+    outs = M.dsnlm_forward_batched(imgs, S, P)
+
+    def fwd():
+        M.dsnlm_forward_batched(imgs, S, P, outs=outs)
+
+    def fwd_bwd():
+        fwd()
+        M.dsnlm_backward_batched([2.0 * (y - c) for y, c in zip(outs, cl)])
+
+    tf = _device_time(fwd, steps)
+    tfb = _device_time(fwd_bwd, steps)
+    px = sum(x.numel() for x in xs)
+    return {"images": len(xs), "n": 256, "S": S, "P": P, "h": h, "fwd_ms": tf, "fwd_bwd_ms": tfb,
+            "ratio": tfb / tf, "fwd_bwd_mpx_s": px / (tfb * 1e-3) / 1e6}
+
+
+def unrolled_spi_timing(M, reps=2):
+    """Single-photon imaging, 16 images of 256 x 256 (K = 16 binary frames,
+    eta = 4), 30 unrolled iterations of Algorithm 1 (weights frozen after 5),
+    S = 7, P = 2, coupled bandwidth sqrt(lambda / rho): per image, the solve
+    with per-iteration checkpoints and the reverse pass to dL/dlambda,
+    dL/drho and the initial image's adjoint, L = ||x_30 - x_clean||^2."""
+    import numpy as np
+    import torch
+    import synth
+    K, eta, lam, rho, S, P, iters, k0 = 16, 4.0, 1e-2, 1.0, 7, 2, 30, 5
+    batch = synth.config4_batch(count=16, n=256, K=K)
+    probs, items = [], []
+    for clean, uni in batch:
+        c = torch.as_tensor(clean).cuda()
+        # the sensor of the configuration: frame k of pixel i reads 1 with
+        # probability 1 - exp(-eta x_i / K); the uniforms are the seeded draws
+        p1 = 1.0 - torch.exp(-eta * c / K)
+        ones = (torch.as_tensor(uni).cuda() < p1[..., None]).sum(-1).to(torch.uint8)
+        k0s = (K - ones.double()).clamp(min=1) / K
+        x0 = (-(K / eta) * torch.log(k0s)).clamp(0, 1).float().contiguous()  # per-pixel ML start
+        items.append((c, ones.contiguous(), x0))
+    prm = M.LadmmParams(lam=lam, rho=rho, gamma=1.0 / (eta * eta), S=S, P=P, h=0.0, iters=iters,
+                        freeze_after=k0)
+    n = 256
+    ck = torch.empty((iters, 4, n, n), dtype=torch.float32, device="cuda")
+
+    def one(c, ones, x0):
+        op = M.SPIOperator(n1=n, n2=n, ones=ones, K=K, eta=eta)
+        x, v, u = x0.clone(), x0.clone(), torch.zeros_like(x0)
+        M.ladmm_solve(op, prm, x, v, u, checkpoints=ck)
+        xb = 2.0 * (x - c)
+        vb = torch.zeros_like(xb)
+        ub = torch.zeros_like(xb)
+        gx0 = torch.empty_like(x0)
+        dp = M.ladmm_solve_backward(op, prm, x0, x0, torch.zeros_like(x0), ck, xb, vb, ub, dinit=gx0)
+        return dp
+
+    def all_images():
+        return [one(*it) for it in items]
+
+    fwd_only = lambda: [M.ladmm_solve(M.SPIOperator(n1=n, n2=n, ones=o, K=K, eta=eta), prm,
+                                      x0.clone(), x0.clone(), torch.zeros_like(x0), checkpoints=ck)
+                        for _, o, x0 in items]
+    t_fb = _device_time(all_images, reps)
+    t_f = _device_time(fwd_only, reps)
+    dps = torch.stack(all_images()).cpu().numpy()
+    return {"images": 16, "n": n, "iters": iters, "freeze_after": k0, "S": S, "P": P,
+            "ms_forward_with_checkpoints": t_f, "ms_forward_backward": t_fb,
+            "ms_per_image_forward_backward": t_fb / 16,
+            "dlambda_finite": bool(np.isfinite(dps[:, 2]).all()), "drho_finite": bool(np.isfinite(dps[:, 3]).all()),
+            "note": "images one after another (the unrolled solver is single-image); each forward "
+                    "writes (x, v, u, z) after every iteration; the reverse pass rebuilds the "
+                    "frozen weights once per image"}
 
 
 def ladmm_sr_timing(M, S, P):
     """2x super-resolution of a 512x512 synthetic image: 50 iterations of
-    Algorithm 1, weights rebuilt for 5 iterations then frozen (graph-captured)."""
+    Algorithm 1, weights rebuilt for 5 iterations then frozen; the whole solve
+    is one captured HIP graph (captured on the first call, replayed after)."""
     import numpy as np
     import torch
     import synth
@@ -146,25 +322,26 @@ def ladmm_sr_timing(M, S, P):
                         freeze_after=cfg["freeze_after"], iters=cfg["iters"])
     res = torch.zeros((cfg["iters"], 2), device="cuda")
     st = torch.cuda.Stream()
-    times = []
-    for rep in range(3):
+    times, times_nores = [], []
+    for rep in range(4):
         x, v, u = x0.clone(), x0.clone(), torch.zeros_like(x0)
         torch.cuda.synchronize()
         with torch.cuda.stream(st):
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(st)
-            M.ladmm_solve(op, prm, x, v, u, residuals=res)
+            M.ladmm_solve(op, prm, x, v, u, residuals=res if rep < 2 else None)
             e1.record(st)
         torch.cuda.synchronize()
-        times.append(e0.elapsed_time(e1))
+        (times if rep < 2 else times_nores).append(e0.elapsed_time(e1))
     err0 = float(torch.sqrt(torch.mean((x0 - xc) ** 2)))
     err = float(torch.sqrt(torch.mean((x - xc) ** 2)))
-    return {"ms_per_solve": min(times), "iters": cfg["iters"], "freeze_after": cfg["freeze_after"],
+    return {"ms_per_solve": min(times_nores), "ms_per_solve_with_residuals": min(times),
+            "iters": cfg["iters"], "freeze_after": cfg["freeze_after"],
             "rmse_bicubic": err0, "rmse_ladmm": err,
             "final_primal_residual": float(res[-1, 0]), "final_dual_residual": float(res[-1, 1]),
-            "note": "includes weight rebuilds (5), frozen applies (45), graph capture and one "
-                    "host synchronisation per solve"}
+            "note": "5 weight rebuilds and 45 frozen applies in one graph replay, state copied in "
+                    "and out on the device; with residuals the call also synchronises and checks them"}
 
 
 def main():
@@ -175,8 +352,8 @@ def main():
     ap.add_argument("--mode", choices=["batched", "perimage"], default="batched")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--count", type=int, default=64)
-    ap.add_argument("--no-ladmm", action="store_true", help="skip the LADMM solve timing")
-    ap.add_argument("--no-fb", action="store_true", help="skip the forward+backward timing")
+    ap.add_argument("--no-ladmm", action="store_true", help="skip the LADMM solve timings")
+    ap.add_argument("--no-fb", action="store_true", help="skip the forward+backward timings")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path "
@@ -198,6 +375,7 @@ def main():
     hs = [it.h for it in images]
     total_px = sum(x.numel() for x in xs)
     pairs = sum(window_pairs(x.shape[0], x.shape[1], S) for x in xs)
+    half_pairs = (pairs - total_px) / 2  # pairs the sweeps evaluate
 
     if args.mode == "batched":
         def step():
@@ -227,22 +405,12 @@ def main():
     ms = ev0.elapsed_time(ev1) / args.steps
 
     # per-kernel device time of the sweeps, on their launch stream
-    lib.dsnlm_profile_reset()
-    lib.dsnlm_profile_enable(1)
     prof_steps = max(2, min(args.steps, 5))
-    for _ in range(prof_steps):
-        step()
-    torch.cuda.synchronize()
-    import ctypes as C
-    tot = {}
-    for name, kind in [("pass_a", _lib.K_PASS_A), ("pass_b", _lib.K_PASS_B),
-                       ("prep_and_gather", _lib.K_HALF_AUX), ("epilogue", _lib.K_EPILOGUE)]:
-        t = C.c_double()
-        n = C.c_int()
-        lib.dsnlm_profile_query(kind, C.byref(t), C.byref(n))
-        tot[name] = (t.value, n.value)
-    lib.dsnlm_profile_enable(0)
+    km = _kernel_ms(lib, [("pass_a", _lib.K_PASS_A), ("pass_b", _lib.K_PASS_B),
+                          ("prep_and_gather", _lib.K_HALF_AUX), ("epilogue", _lib.K_EPILOGUE)],
+                    step, prof_steps)
     # ---- measured peak rates of this device (context for the roofline)
+    import ctypes as C
     probes = {}
     for kind, name in [(0, "fp32_fma_flop_s"), (1, "exp_per_s"), (2, "hbm_copy_bytes_s")]:
         r = C.c_double()
@@ -252,21 +420,27 @@ def main():
         probes["exp_cost_in_fma_slots"] = probes["fp32_fma_flop_s"] / 2 / probes["exp_per_s"]
 
     exp_slots = probes.get("exp_cost_in_fma_slots", EXP_SLOTS_FALLBACK)
-    pb_ms, pb_n = tot["pass_b"]
-    launches_per_step = pb_n / prof_steps
-    pb_avg_ms = pb_ms / max(pb_n, 1)
+    pb_avg_ms, launches_per_step = km["pass_b"][0] / max(km["pass_b"][1], 1), km["pass_b"][1]
     ops_pair_b = VALU_PASS_B + exp_slots
     ops_pair_a = VALU_PASS_A + exp_slots
-    half_pairs = (pairs - total_px) / 2  # pairs the sweeps evaluate
     ops_per_launch = ops_pair_b * half_pairs / launches_per_step
     achieved = ops_per_launch / (pb_avg_ms * 1e-3) / 1e12
     peak = VALU_LANE_OPS_PER_S / 1e12
 
-    # ---- forward + backward vs forward, per-image launches over the batch
-    fb = None if args.no_fb else fwd_bwd_ratio(M, xs, hs, S, P, steps=max(1, min(args.steps, 3)))
+    # ---- the same images, one launch sequence per image
+    per_image = None
+    if args.mode == "batched":
+        M.dsnlm_forward_batched(list(zip(xs, xs, hs)), S, P, outs=ys)
+        per_image = per_image_timing(M, xs, hs, ys, S, P, steps=max(1, min(args.steps, 3)))
 
-    # ---- linearized PnP-ADMM super-resolution solve (512x512, 50 iterations)
+    # ---- forward + backward vs forward, batched, and the differentiated 8-image case
+    fb = None if args.no_fb else fwd_bwd_ratio(M, lib, xs, hs, S, P, max(1, min(args.steps, 3)),
+                                               half_pairs, exp_slots)
+    diff8 = None if args.no_fb else differentiated_batch_timing(M, max(1, min(args.steps, 5)))
+
+    # ---- linearized PnP-ADMM: 512x512 super-resolution, unrolled single-photon imaging
     lad = ladmm_sr_timing(M, S, P) if not args.no_ladmm else None
+    spi = unrolled_spi_timing(M) if not (args.no_ladmm or args.no_fb) else None
 
     out = {
         "metric": "DSG-NLM Mpixel/s @21x21 search, 7x7 patch (forward)",
@@ -300,11 +474,14 @@ def main():
             "pairs_evaluated_per_launch": half_pairs / launches_per_step,
             "avg_launch_ms": pb_avg_ms,
         },
-        "kernel_ms_per_step": {k: v[0] / prof_steps for k, v in tot.items()},
+        "kernel_ms_per_step": {k: v[0] for k, v in km.items()},
         "measured_peaks": probes,
+        "per_image": per_image,
         "fwd_bwd_over_fwd": fb["ratio"] if fb else None,
         "fwd_bwd": fb,
+        "differentiated_8x256": diff8,
         "ladmm_sr_512": lad,
+        "unrolled_spi_16x256": spi,
         "forward_roofline_frac": (ops_pair_a + ops_pair_b) * half_pairs / (ms * 1e-3) / VALU_LANE_OPS_PER_S,
         "wall_s_timed": wall,
     }
