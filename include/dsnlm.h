@@ -354,17 +354,33 @@ int dsnlm_profile_query(int kind, double* total_ms, int* launches);
 int dsnlm_profile_reset(void);
 
 /* ----------------------------------------------------------------------- */
-/* Autotuning of the window sweeps.  Every sweep kind has several compiled   */
-/* schedules ("variants"); a table keyed by (kind, S <= 12 or not, P) picks  */
-/* the one launched.  kind: 0 = pass A, 1 = pass B (build and fused forward),*/
-/* 2 = apply with built weights, 3 = backward input-gradient sweep.          */
-/* If the environment variable DSNLM_TUNE_CACHE names a file, the table is   */
-/* read from it on first use and written back by dsnlm_tune.                 */
+/* Autotuning of the window sweeps (not in the paper: launch configuration).
+ * Two tables steer the launches.  (1) Every sweep kind has several compiled
+ * schedules ("variants"); a table keyed by (kind, S <= 12 or not, P) picks
+ * the one launched.  kind: 0 = pass A, 1 = pass B (build and fused forward),
+ * 2 = apply with built weights, 3 = backward input-gradient sweep; variant
+ * 0-2 = full-window schedules, 3 = half window (the default).  (2) A
+ * single-image half-window sweep splits each 32 x 64 tile's shifts into
+ * `groups` equal contiguous ranges, one block each, so that a small image
+ * fills the GPU; a table keyed by (S <= 12 or not, P, image size class by
+ * its number of 32 x 64 tiles: <= 16, 32, 64, 128, 256, 512, more) gives the
+ * count (0 = the default rule: enough blocks for two per CU, at most 4).
+ * Batched launches never split.  Changing an entry changes the order of the
+ * FP32 additions, not the result beyond rounding.
+ * If the environment variable DSNLM_TUNE_CACHE names a file, the tables are
+ * read from it on first use and written back by dsnlm_tune. */
 int dsnlm_tune_set(int kind, int S, int P, int variant);
 int dsnlm_tune_get(int kind, int S, int P, int* variant);
-/* Time every variant of every kind on an n1 x n2 image (guide: device, the
- * image used for timing), `reps` launches each, and keep the fastest.
- * Synchronous. */
+/* Set the shift groups (0..8; 0 = the rule) for images of the size class of
+ * n1 x n2 at S, P; get the count an n1 x n2 image at S, P is launched with. */
+int dsnlm_tune_set_groups(int n1, int n2, int S, int P, int groups);
+int dsnlm_tune_get_groups(int n1, int n2, int S, int P, int* groups);
+/* Time, on an n1 x n2 image (guide: device, the image used for timing),
+ * `reps` launches of every variant of every kind and keep the fastest; then,
+ * when the forward runs on the half window, time the single-image forward
+ * plus one frozen apply for each shift-group count in {1, 2, 3, 4, 5, 6, 8}
+ * and keep the fastest for this size class.  Synchronous; allocates a
+ * temporary handle. */
 int dsnlm_tune(const float* guide, int n1, int n2, int S, int P, float h, int reps, void* stream);
 
 /* Measured peak of one rate on the current device, used as a roofline

@@ -117,6 +117,8 @@ def _load():
         "dsnlm_tune_set": (i, [i, i, i, i]),
         "dsnlm_tune_get": (i, [i, i, i, C.POINTER(i)]),
         "dsnlm_tune": (i, [vp, i, i, i, i, f, i, vp]),
+        "dsnlm_tune_set_groups": (i, [i, i, i, i, i]),
+        "dsnlm_tune_get_groups": (i, [i, i, i, i, C.POINTER(i)]),
         "dsnlm_peak_probe": (i, [i, C.POINTER(C.c_double), vp]),
         "dsnlm_profile_enable": (i, [i]),
         "dsnlm_profile_query": (i, [i, C.POINTER(C.c_double), C.POINTER(i)]),
@@ -151,6 +153,7 @@ EXPORTED = [
     "ladmm_step_backward", "ladmm_solve_backward", "dsnlm_backward_batched", "dsnlm_nlm",
     "dsnlm_forward_brute", "admm_cg_solve", "dsnlm_batched_state",
     "dsnlm_forward_noalloc", "dsnlm_forward_noalloc_limit", "dsnlm_forward_noalloc_bytes",
+    "dsnlm_tune_set_groups", "dsnlm_tune_get_groups",
 ]
 
 K_PASS_A, K_PASS_B, K_APPLY, K_EPILOGUE, K_BWD_PREP, K_PASS_C, K_PASS_D, K_BWD_TAIL, K_LADMM, K_HALF_AUX = range(10)

@@ -64,7 +64,7 @@ ImgDesc base_desc(const dsnlm_weights* w) {
     d.part = w->part;
     d.zpad = w->part ? half_zpad(w->part, w->n1, w->n2, w->S, w->P) : nullptr;
     // a small image splits each tile's dx range over several blocks
-    const int groups = half_split_groups(w->n1, w->n2, w->S);
+    const int groups = half_split_groups(w->n1, w->n2, w->S, w->P);
     if (groups > 1 && w->gpart && w->gpart_cap >= half_group_floats(w->n1, w->n2, w->S, groups)) {
         d.gpart = w->gpart;
         d.groups = groups;
@@ -111,7 +111,7 @@ int prepare_handle(int n1, int n2, int S, int P, float h, dsnlm_weights** out) {
         if (rc) return rc;
         w->part_cap = need;
     }
-    const size_t gneed = half_group_floats(n1, n2, S, half_split_groups(n1, n2, S));
+    const size_t gneed = half_group_floats(n1, n2, S, half_split_groups(n1, n2, S, P));
     if (w->gpart_cap < gneed) {
         (void)hipFree(w->gpart);
         w->gpart = nullptr;

@@ -32,8 +32,6 @@ namespace dsnlm {
 
 namespace {
 
-// largest number of dx groups a single-image half-window sweep is split into
-constexpr int kHalfSplitCap = 4;
 
 template <int P, int S_CLASS, int GW_ = 11>
 struct HGeo {
@@ -69,6 +67,20 @@ __device__ __forceinline__ int reflect_h(int k, int n) {
     k = k < 0 ? 0 : k;
     k = k >= n ? n - 1 : k;
     return k;
+}
+
+// Shift number f (0 <= f < 2S(S+1)) of the half window H = {dy > 0} u {dy = 0,
+// dx > 0} in the order dx ascending, dy ascending: the S(S+1) shifts with
+// dx <= 0 (dy = 1..S), then those with dx > 0 (dy = 0..S).  Needs S >= 1.
+__device__ __forceinline__ void half_shift(int f, int S, int& dx, int& dy) {
+    if (f < S * (S + 1)) {
+        dx = -S + f / S;
+        dy = 1 + f % S;
+    } else {
+        const int g = f - S * (S + 1);
+        dx = 1 + g / (S + 1);
+        dy = g % (S + 1);
+    }
 }
 
 // the tile's index within its image
@@ -143,8 +155,21 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
     // dx group of this block (a single-image launch may split the half
     // window's dx range over blockIdx.z; each group has its own regions)
     const int grp = BATCH ? 0 : (int)blockIdx.z;
-    const int dxlo = BATCH ? -S : -S + grp * (2 * S + 1) / ngrp;
-    const int dxhi = BATCH ? S + 1 : -S + (grp + 1) * (2 * S + 1) / ngrp;  // exclusive
+    // this block's shifts: a contiguous range of the half window in the order
+    // dx ascending, dy ascending within a dx (a single-image launch may split
+    // the 2S(S+1) shifts into ngrp ranges of equal length, one per blockIdx.z;
+    // each group has its own regions).  (dxF, dyF) .. (dxL, dyL): the first
+    // and last shift (inclusive); empty when dxF > dxL.
+    int dxF = 1, dyF = 0, dxL = 0, dyL = 0;
+    {
+        const int H = 2 * S * (S + 1);
+        const int f0 = BATCH ? 0 : (int)((long long)grp * H / ngrp);
+        const int f1 = BATCH ? H : (int)((long long)(grp + 1) * H / ngrp);
+        if (f1 > f0) {
+            half_shift(f0, S, dxF, dyF);
+            half_shift(f1 - 1, S, dxL, dyL);
+        }
+    }
     const int n1 = d.n1, n2 = d.n2;
     const int AH = TH + S, AWr = TW + 2 * S;
     float* Vb = lds;
@@ -259,23 +284,23 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
     constexpr bool PF = MODE != kPassA && P <= 3;
     float nwin[PF ? NW : 1];
     if constexpr (PF) {
-        const int zw = zbase + (dxlo > 0 ? 0 : 1) * W2 + dxlo;
+        const int zw = zbase + dyF * W2 + dxF;
 #pragma unroll
         for (int q = 0; q < NW; ++q) nwin[q] = __builtin_bit_cast(float, zload(zw + q * W2));
     }
     int t = 0;
-    for (int dx = -S; dx <= S; ++dx) {
-        if (dx < dxlo || dx >= dxhi) continue;  // another group's (uniform)
-        const int dylo = dx > 0 ? 0 : 1;  // the half window
-        for (int dy0 = dylo; dy0 <= S; dy0 += GW) {
+    for (int dx = dxF; dx <= dxL; ++dx) {
+        const int dyA = dx == dxF ? dyF : (dx > 0 ? 0 : 1);  // the half window
+        const int dyB = dx == dxL ? dyL : S;
+        for (int dy0 = dyA; dy0 <= dyB; dy0 += GW) {
             float win[NW];
             if constexpr (PF) {
 #pragma unroll
                 for (int q = 0; q < NW; ++q) win[q] = nwin[q];
                 // the next group; past the last one this is an unused read,
                 // inside the range-checked buffer
-                const int ndx = dy0 + GW <= S ? dx : dx + 1;
-                const int ndy0 = dy0 + GW <= S ? dy0 + GW : (ndx > 0 ? 0 : 1);
+                const int ndx = dy0 + GW <= dyB ? dx : dx + 1;
+                const int ndy0 = dy0 + GW <= dyB ? dy0 + GW : (ndx > 0 ? 0 : 1);
                 const int zw = zbase + ndy0 * W2 + ndx;
 #pragma unroll
                 for (int q = 0; q < NW; ++q) nwin[q] = __builtin_bit_cast(float, zload(zw + q * W2));
@@ -287,7 +312,7 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
 #pragma unroll
             for (int g = 0; g < GW; ++g) {
                 const int dy = dy0 + g;
-                if (dy <= S) {
+                if (dy <= dyB) {
                     float* V = Vb + (t & 1) * (TH * VW);
                     // read here, so that the scalar load has returned by the
                     // barrier and no wait for it holds up the LDS reads after it
@@ -473,7 +498,7 @@ k_half_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __r
         ok[3] = above;
         ok[4] = above && left;
         ok[5] = above && right;
-        constexpr int GMAX = kHalfSplitCap;
+        constexpr int GMAX = kMaxShiftGroups;
         float2 val[6][GMAX];
 #pragma unroll
         for (int r = 0; r < 6; ++r) {
@@ -614,8 +639,9 @@ hipError_t launch_half_one(int S, const ImgDesc& one, const ImgDesc* batch, cons
     hipError_t ea = half_attr<P, S_CLASS, MODE, BATCH>();
     if (ea != hipSuccess) return ea;
     const dim3 grid = BATCH ? dim3(ntiles) : dim3((one.n2 + G::TW - 1) / G::TW, (one.n1 + G::TH - 1) / G::TH);
-    const int ngrp =
-        (BATCH || one.groups < 2 || !one.gpart) ? 1 : std::min(std::min(one.groups, 2 * S + 1), kHalfSplitCap);
+    const int ngrp = (BATCH || one.groups < 2 || !one.gpart)
+                         ? 1
+                         : std::min(std::min(one.groups, std::max(2 * S * (S + 1), 1)), kMaxShiftGroups);
     const dim3 sgrid(grid.x, grid.y, ngrp);
     HatTable hat = make_hat(S);
     if constexpr (MODE == kNLM)
@@ -689,13 +715,15 @@ static size_t part_regions(int n1, int n2, int S, int P) {
     return (regions + 63) & ~(size_t)63;
 }
 
-int half_split_groups(int n1, int n2, int S) {
-    // enough blocks for two tiles per CU on 256 CUs, at most kHalfSplitCap groups
-    constexpr int kSplitCap = kHalfSplitCap;
-    const int tiles = ((n1 + 31) / 32) * ((n2 + 63) / 64);
-    int g = (512 + tiles - 1) / tiles;
-    g = g > kSplitCap ? kSplitCap : g;
-    return g < 1 ? 1 : (g > 2 * S + 1 ? 2 * S + 1 : g);
+int half_split_groups(int n1, int n2, int S, int P) {
+    const int H = std::max(2 * S * (S + 1), 1);  // shifts of the half window
+    int g = tuned_shift_groups(n1, n2, S, P);
+    if (g < 1) {
+        // rule: enough blocks for two tiles per CU on 256 CUs, at most 4 groups
+        const int tiles = ((n1 + 31) / 32) * ((n2 + 63) / 64);
+        g = std::min((512 + tiles - 1) / tiles, 4);
+    }
+    return std::max(1, std::min(std::min(g, H), kMaxShiftGroups));
 }
 
 size_t half_group_floats(int n1, int n2, int S, int groups) {

@@ -124,11 +124,18 @@ hipError_t launch_epilogue(const ImgDesc& one, const ImgDesc* batch, const TileR
 // Lead pad (float2 entries) before the backward's (t, w) pair array.
 constexpr int kFacLead = 32;
 size_t half_part_floats(int n1, int n2, int S, int P);  // partial regions + mirrored guide
-// A single-image sweep splits the half window's dx range over `groups` blocks
-// per tile (ImgDesc::groups, ::gpart, set by base_desc from the handle), which
-// fills the GPU for a small image; batch launches never split, so a batched
-// result differs from the single-image one by summation order only.
-int half_split_groups(int n1, int n2, int S);
+// A single-image sweep splits the half window's shifts over `groups` blocks
+// per tile (equal contiguous ranges; ImgDesc::groups, ::gpart, set by
+// base_desc from the handle), which fills the GPU for a small image; batch
+// launches never split, so a batched result differs from the single-image one
+// by summation order only.
+// The count comes from the tuning table (dsnlm_tune) when it has an entry for
+// the image's size class, else from a rule (enough blocks for two per CU, at
+// most 4).
+constexpr int kMaxShiftGroups = 8;
+int half_split_groups(int n1, int n2, int S, int P);
+int tuned_shift_groups(int n1, int n2, int S, int P);  // 0: no table entry
+void set_shift_groups(int n1, int n2, int S, int P, int groups);
 size_t half_group_floats(int n1, int n2, int S, int groups);        // floats of ImgDesc::gpart
 float* half_zpad(float* part, int n1, int n2, int S, int P);  // the mirrored guide inside it
 bool half_lds_fits(int S, int P, int mode);

@@ -40,7 +40,7 @@ struct Layout {
 Layout layout(int n1, int n2, int S, int P) {
     Layout L{};
     const size_t n = (size_t)n1 * n2;
-    L.groups = half_split_groups(n1, n2, S);
+    L.groups = half_split_groups(n1, n2, S, P);
     L.key = 0;
     L.c = 64;
     L.delta = L.c + up64(n);
