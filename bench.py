@@ -442,6 +442,20 @@ def main():
     lad = ladmm_sr_timing(M, S, P) if not args.no_ladmm else None
     spi = unrolled_spi_timing(M) if not (args.no_ladmm or args.no_fb) else None
 
+    # ---- the launch configuration the library ran (autotuning tables)
+    tuning = {"variants_S10_P3": {}, "shift_groups_single_image_S10_P3": {}}
+    for kind, name in enumerate(["pass_a", "pass_b", "apply", "sweep_c"]):
+        v = C.c_int()
+        _lib.check(lib.dsnlm_tune_get(kind, S, P, C.byref(v)))
+        tuning["variants_S10_P3"][name] = {0: "full window", 1: "full window, pipelined",
+                                           2: "full window, register window",
+                                           3: "half window"}.get(v.value, v.value)
+    for sz in [(128, 128), (256, 256), (512, 512), (1024, 1024)]:
+        g = C.c_int()
+        _lib.check(lib.dsnlm_tune_get_groups(sz[0], sz[1], S, P, C.byref(g)))
+        tuning["shift_groups_single_image_S10_P3"]["%dx%d" % sz] = g.value
+    tuning["tile"] = "32 x 64 pixels, 512 threads, 4 outputs per thread; batched launches: one block per tile"
+
     out = {
         "metric": "DSG-NLM Mpixel/s @21x21 search, 7x7 patch (forward)",
         "value": total_px / (ms * 1e-3) / 1e6,
@@ -475,6 +489,7 @@ def main():
             "avg_launch_ms": pb_avg_ms,
         },
         "kernel_ms_per_step": {k: v[0] for k, v in km.items()},
+        "launch_config": tuning,
         "measured_peaks": probes,
         "per_image": per_image,
         "fwd_bwd_over_fwd": fb["ratio"] if fb else None,

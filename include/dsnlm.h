@@ -91,14 +91,18 @@ int dsnlm_forward(const float* guide, const float* x, float* y, int n1, int n2,
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * computation as dsnlm_forward with out = NULL -- y = W(guide) x, the same
- * kernels, bit-identical results -- but it allocates nothing (no hipMalloc,
+ * kernels, bit-identical results while the scratch below holds the partial
+ * regions of dsnlm_forward's shift split for the image (for larger images
+ * the split is reduced to fit, and the result differs only by the order of
+ * FP32 additions) -- but it allocates nothing (no hipMalloc,
  * no hipFree, no allocating library call) and does not synchronise.  Its
  * intermediates (c, delta, B', m, the partial regions, the mirrored guide)
  * live in a fixed scratch array of dsnlm_forward_noalloc_limit() bytes
  * (48 MiB) that each device holds from its first call until the process ends.
  * Arguments as for dsnlm_forward; P <= 5.  An image whose intermediates
  * (dsnlm_forward_noalloc_bytes) exceed the limit returns DSNLM_EUNSUPPORTED
- * before anything is launched (1024 x 1024 at S = 10, P = 3 needs 31 MiB).
+ * before anything is launched (1024 x 1024 at S = 10, P = 3 needs 31 MiB
+ * without a shift split, 44 MiB with the 2-way split it then uses).
  * Every call on a device shares that device's scratch, which keeps the last
  * call's contents: calls that overlap in time on one device (different
  * streams, or host threads) race and give wrong results; calls ordered on
@@ -364,7 +368,8 @@ int dsnlm_profile_reset(void);
  * `groups` equal contiguous ranges, one block each, so that a small image
  * fills the GPU; a table keyed by (S <= 12 or not, P, image size class by
  * its number of 32 x 64 tiles: <= 16, 32, 64, 128, 256, 512, more) gives the
- * count (0 = the default rule: enough blocks for two per CU, at most 4).
+ * count (0 = the default: 8 groups up to 64 tiles, 4 up to 256, 3 up to
+ * 512, then none).
  * Batched launches never split.  Changing an entry changes the order of the
  * FP32 additions, not the result beyond rounding.
  * If the environment variable DSNLM_TUNE_CACHE names a file, the tables are

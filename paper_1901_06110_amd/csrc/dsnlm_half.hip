@@ -498,7 +498,7 @@ k_half_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __r
         ok[3] = above;
         ok[4] = above && left;
         ok[5] = above && right;
-        constexpr int GMAX = kMaxShiftGroups;
+        constexpr int GMAX = BATCH ? 1 : kMaxShiftGroups;  // a batch never splits
         float2 val[6][GMAX];
 #pragma unroll
         for (int r = 0; r < 6; ++r) {
@@ -719,9 +719,12 @@ int half_split_groups(int n1, int n2, int S, int P) {
     const int H = std::max(2 * S * (S + 1), 1);  // shifts of the half window
     int g = tuned_shift_groups(n1, n2, S, P);
     if (g < 1) {
-        // rule: enough blocks for two tiles per CU on 256 CUs, at most 4 groups
+        // default by the number of 32 x 64 tiles, from timings of the forward
+        // and a frozen apply on MI355X (S = 7 and 10): 8 groups up to 64
+        // tiles (256 x 256), 4 up to 256 (512 x 512 is 128), 3 up to 512
+        // (1024 x 1024), then 1
         const int tiles = ((n1 + 31) / 32) * ((n2 + 63) / 64);
-        g = std::min((512 + tiles - 1) / tiles, 4);
+        g = tiles <= 64 ? 8 : tiles <= 256 ? 4 : tiles <= 512 ? 3 : 1;
     }
     return std::max(1, std::min(std::min(g, H), kMaxShiftGroups));
 }

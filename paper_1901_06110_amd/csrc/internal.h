@@ -130,8 +130,7 @@ size_t half_part_floats(int n1, int n2, int S, int P);  // partial regions + mir
 // launches never split, so a batched result differs from the single-image one
 // by summation order only.
 // The count comes from the tuning table (dsnlm_tune) when it has an entry for
-// the image's size class, else from a rule (enough blocks for two per CU, at
-// most 4).
+// the image's size class, else from a default by tile count.
 constexpr int kMaxShiftGroups = 8;
 int half_split_groups(int n1, int n2, int S, int P);
 int tuned_shift_groups(int n1, int n2, int S, int P);  // 0: no table entry

@@ -4,12 +4,14 @@
 //
 // The intermediates that dsnlm_forward keeps in a handle -- c, delta, B', the
 // packed (m, argmax) key, the half-window partial regions, the mirrored guide
-// and the extra dx groups' regions -- live instead in one file-scope device
+// and the extra shift groups' regions -- live instead in one file-scope device
 // array of fixed size.  Each device holds its own copy of the array until the
 // process ends; its device address is looked up once per device with
 // hipGetSymbolAddress and only that address is handed to kernels.  The kernels
 // are the same as dsnlm_forward's, launched with the same descriptor, so the
-// two entry points give identical results.
+// two entry points give identical results whenever the array holds the
+// partial regions of dsnlm_forward's shift split; for larger images the split
+// is reduced to fit (the sums then differ by the order of FP32 additions).
 #include <mutex>
 #include <string>
 
@@ -31,23 +33,27 @@ size_t up64(size_t f) { return (f + 63) & ~size_t(63); }
 
 // Layout inside the array (floats, each part 256-byte aligned): the key
 // (64 floats reserved), c, delta, B', the half-window partial buffer
-// (regions + mirrored guide), the extra dx groups' regions.
+// (regions + mirrored guide), the extra shift groups' regions.
 struct Layout {
     size_t key, c, delta, bp, part, gpart, total;
     int groups;
 };
 
+// The shift groups are those of dsnlm_forward for this size, reduced to the
+// largest count whose regions still fit in the array.
 Layout layout(int n1, int n2, int S, int P) {
     Layout L{};
     const size_t n = (size_t)n1 * n2;
-    L.groups = half_split_groups(n1, n2, S, P);
     L.key = 0;
     L.c = 64;
     L.delta = L.c + up64(n);
     L.bp = L.delta + up64(n);
     L.part = L.bp + up64(n);
     L.gpart = L.part + up64(half_part_floats(n1, n2, S, P));
-    L.total = L.gpart + up64(half_group_floats(n1, n2, S, L.groups));
+    for (L.groups = half_split_groups(n1, n2, S, P);; --L.groups) {
+        L.total = L.gpart + up64(half_group_floats(n1, n2, S, L.groups));
+        if (L.groups <= 1 || L.total <= kNoAllocFloats) break;
+    }
     return L;
 }
 
