@@ -164,6 +164,30 @@ def _kernel_ms(lib, kinds, fn, reps):
     return out
 
 
+def cpu_table1(n: int = 64, S: int = 10, Ps=(1, 3, 5, 8, 11, 14)):
+    """Table 1 on the host: the FP64 oracle's two patch-distance routes on an
+    n x n synthetic image, window (2S+1)^2, patch sides N_p = 2P+1 -- the
+    direct N_p^2 sums (the brute force) against the integral image of each
+    shift's squared-difference image (the fast scheme of Section 3).  Both
+    run the same shift loop, so the ratio isolates the patch distances."""
+    import torch
+    import synth
+    from oracle import dsnlm_ref
+    _, noisy = synth.piecewise_smooth(n, n, seed=1001, sigma_n=0.05)
+    rows = []
+    for P in Ps:
+        t0 = time.perf_counter()
+        a = dsnlm_ref.dsnlm_shifts(noisy, noisy, S, P, 0.1)["y"]
+        t1 = time.perf_counter()
+        b = dsnlm_ref.dsnlm_shifts(noisy, noisy, S, P, 0.1, distances="integral")["y"]
+        t2 = time.perf_counter()
+        rows.append(dict(Np=2 * P + 1, brute_s=t1 - t0, fast_s=t2 - t1, ratio=(t1 - t0) / (t2 - t1),
+                         max_abs_diff=float((a - b).abs().max())))
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    return dict(image=f"{n}x{n}", window=2 * S + 1, threads=torch.get_num_threads(),
+                cpu_model=_cpu_model(), kind="oracle", rows=rows)
+
+
 def fwd_bwd_ratio(M, lib, xs, hs, S, P, steps, half_pairs, exp_slots):
     """Time the batched forward alone and the batched forward + backward
     (input, guide and h gradients of every image); the ratio, and the
@@ -354,7 +378,12 @@ def main():
     ap.add_argument("--count", type=int, default=64)
     ap.add_argument("--no-ladmm", action="store_true", help="skip the LADMM solve timings")
     ap.add_argument("--no-fb", action="store_true", help="skip the forward+backward timings")
+    ap.add_argument("--table1-cpu", action="store_true",
+                    help="only time Table 1 on the host (the oracle's direct vs integral-image distances)")
     args = ap.parse_args()
+    if args.table1_cpu:
+        print(json.dumps(cpu_table1()))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path "
               "(a batch would shard image by image across GPUs, with no communication)", file=sys.stderr)

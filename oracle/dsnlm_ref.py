@@ -149,7 +149,25 @@ def _shift_ranges(n: int, d: int):
     return max(0, -d), min(n, n - d)
 
 
-def dsnlm_shifts(x, z, S: int, P: int, h, want: str = "y") -> dict:
+def integral_distances(zp: torch.Tensor, i0: int, i1: int, j0: int, j1: int, dy: int, dx: int,
+                       Np: int) -> torch.Tensor:
+    """Patch distances of the pixels s in [i0, i1) x [j0, j1) to s + d from
+    the integral image of the squared-difference image of the shift (Section
+    3, the fast scheme after Algorithm 2): e(p) = (z(p) - z(p + d))^2 over the
+    padded rows and columns the patches cover, I = its 2-D prefix sums with a
+    zero first row and column, and each distance a box of I read at its four
+    corners.  zp: the guide padded by P (padded index = image index + P)."""
+    a = zp[i0:i1 + Np - 1, j0:j1 + Np - 1]
+    b = zp[i0 + dy:i1 + dy + Np - 1, j0 + dx:j1 + dx + Np - 1]
+    e = (a - b) ** 2
+    integ = torch.zeros((e.shape[0] + 1, e.shape[1] + 1), dtype=torch.float64)
+    integ[1:, 1:] = torch.cumsum(torch.cumsum(e, dim=0), dim=1)
+    h1, w1 = i1 - i0, j1 - j0
+    return (integ[Np:Np + h1, Np:Np + w1] - integ[0:h1, Np:Np + w1]
+            - integ[Np:Np + h1, 0:w1] + integ[0:h1, 0:w1])
+
+
+def dsnlm_shifts(x, z, S: int, P: int, h, want: str = "y", distances: str = "direct") -> dict:
     """y = W(z) x from the matrices of steps S1-S3, one window shift at a time
     (torch FP64).
 
@@ -159,6 +177,8 @@ def dsnlm_shifts(x, z, S: int, P: int, h, want: str = "y") -> dict:
     step S3 are accumulated band by band.
     x, z: 2-D arrays or tensors (cast to float64; autograd flows through them
     and through h when they are tensors that require grad).
+    distances: "direct" sums every patch distance over its N_p^2 offsets (the
+    brute force); "integral" reads it from the shift's integral image.
     Returns a dict with y (= W x), omega (row sums after S1), delta (row sums
     after S2), m (their maximum), argmax (flat index of the first maximal delta,
     which is where the derivative of the max is routed; the paper does not
@@ -181,12 +201,15 @@ def dsnlm_shifts(x, z, S: int, P: int, h, want: str = "y") -> dict:
         j0, j1 = _shift_ranges(n2, dx)
         if i0 >= i1 or j0 >= j1:
             return None
-        D = torch.zeros((i1 - i0, j1 - j0), dtype=torch.float64)
-        for ty in range(Np):
-            for tx in range(Np):
-                a = zp[i0 + ty:i1 + ty, j0 + tx:j1 + tx]
-                b = zp[i0 + dy + ty:i1 + dy + ty, j0 + dx + tx:j1 + dx + tx]
-                D = D + (a - b) ** 2
+        if distances == "integral":
+            D = integral_distances(zp, i0, i1, j0, j1, dy, dx, Np)
+        else:
+            D = torch.zeros((i1 - i0, j1 - j0), dtype=torch.float64)
+            for ty in range(Np):
+                for tx in range(Np):
+                    a = zp[i0 + ty:i1 + ty, j0 + tx:j1 + tx]
+                    b = zp[i0 + dy + ty:i1 + dy + ty, j0 + dx + tx:j1 + dx + tx]
+                    D = D + (a - b) ** 2
         lam = hat(dy, S) * hat(dx, S)
         return (i0, i1, j0, j1), lam * torch.exp(-kappa * D)
 
