@@ -378,11 +378,17 @@ def main():
     ap.add_argument("--count", type=int, default=64)
     ap.add_argument("--no-ladmm", action="store_true", help="skip the LADMM solve timings")
     ap.add_argument("--no-fb", action="store_true", help="skip the forward+backward timings")
+    ap.add_argument("--only-ladmm", action="store_true",
+                    help="only time the 512x512 super-resolution solve (for profiling)")
     ap.add_argument("--table1-cpu", action="store_true",
                     help="only time Table 1 on the host (the oracle's direct vs integral-image distances)")
     args = ap.parse_args()
     if args.table1_cpu:
         print(json.dumps(cpu_table1()))
+        return
+    if args.only_ladmm:
+        import paper_1901_06110_amd as M
+        print(json.dumps(ladmm_sr_timing(M, 10, 3)))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path "
