@@ -32,8 +32,9 @@
  *      must be finite and > 0.
  *   Supported: 0 <= S <= 24, 0 <= P <= 5; dsnlm_build_weights, dsnlm_apply,
  *   dsnlm_forward and dsnlm_forward_brute also take 5 < P <= 15 (patch sides
- *   up to 31, Table 1's range) through slower full-window passes; the other
- *   entry points return DSNLM_EUNSUPPORTED for P > 5.  Images are limited
+ *   up to 31, Table 1's range: the half-window forward sweeps, or the
+ *   full-window wide-patch passes when the tuning table selects a full-window
+ *   schedule); the other entry points return DSNLM_EUNSUPPORTED for P > 5.  Images are limited
  *   to 2^28 pixels, and so is the image padded by S + P on every side
  *   (the kernels index elements with 32-bit offsets): larger ones return
  *   DSNLM_EUNSUPPORTED before anything is launched.

@@ -36,7 +36,9 @@ namespace {
 template <int P, int S_CLASS, int GW_ = 11>
 struct HGeo {
     static constexpr int TH = 32, TW = 64;   // s-tile (the forward tiling)
-    static constexpr int R = 8;              // phase-1 strip height
+    // phase-1 strip height: 8 rows; 16 for wide patches, whose strips would
+    // otherwise spend most of their work restarting the sliding sum
+    static constexpr int R = P > kMaxP ? 16 : 8;
     static constexpr int L = 4;              // outputs per thread
     static constexpr int NT = TH * (TW / L);  // 512 threads
     static constexpr int TWE = TW + 2 * P;
@@ -672,6 +674,16 @@ hipError_t launch_half_one(int S, const ImgDesc& one, const ImgDesc* batch, cons
 template <int P, int S_CLASS, bool BATCH>
 hipError_t half_mode(int mode, int S, const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
                      int ntiles, hipStream_t st) {
+    if constexpr (P > kMaxP) {
+        // wide patches: the single-image forward sweeps only
+        switch (mode) {
+            case kPassA: return launch_half_one<P, S_CLASS, kPassA, false>(S, one, batch, tiles, ntiles, st);
+            case kPassBApply: return launch_half_one<P, S_CLASS, kPassBApply, false>(S, one, batch, tiles, ntiles, st);
+            case kPassBBuild: return launch_half_one<P, S_CLASS, kPassBBuild, false>(S, one, batch, tiles, ntiles, st);
+            case kApply: return launch_half_one<P, S_CLASS, kApply, false>(S, one, batch, tiles, ntiles, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (mode) {
         case kPassA: return launch_half_one<P, S_CLASS, kPassA, BATCH>(S, one, batch, tiles, ntiles, st);
         case kPassBApply: return launch_half_one<P, S_CLASS, kPassBApply, BATCH>(S, one, batch, tiles, ntiles, st);
@@ -700,8 +712,24 @@ hipError_t half_p(int mode, int S, int P, const ImgDesc& one, const ImgDesc* bat
         case 3: return half_s<3, BATCH>(mode, S, one, batch, tiles, ntiles, st);
         case 4: return half_s<4, BATCH>(mode, S, one, batch, tiles, ntiles, st);
         case 5: return half_s<5, BATCH>(mode, S, one, batch, tiles, ntiles, st);
-        default: return hipErrorInvalidValue;
+        default: break;
     }
+    if constexpr (!BATCH) {  // wide patches (single image, forward sweeps)
+        switch (P) {
+            case 6: return half_s<6, false>(mode, S, one, batch, tiles, ntiles, st);
+            case 7: return half_s<7, false>(mode, S, one, batch, tiles, ntiles, st);
+            case 8: return half_s<8, false>(mode, S, one, batch, tiles, ntiles, st);
+            case 9: return half_s<9, false>(mode, S, one, batch, tiles, ntiles, st);
+            case 10: return half_s<10, false>(mode, S, one, batch, tiles, ntiles, st);
+            case 11: return half_s<11, false>(mode, S, one, batch, tiles, ntiles, st);
+            case 12: return half_s<12, false>(mode, S, one, batch, tiles, ntiles, st);
+            case 13: return half_s<13, false>(mode, S, one, batch, tiles, ntiles, st);
+            case 14: return half_s<14, false>(mode, S, one, batch, tiles, ntiles, st);
+            case 15: return half_s<15, false>(mode, S, one, batch, tiles, ntiles, st);
+            default: break;
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -750,7 +778,11 @@ bool half_lds_fits(int S, int P, int mode) {
         case 3: f = S <= 12 ? half_lds_floats<3, 12>(S, mode) : half_lds_floats<3, kMaxS>(S, mode); break;
         case 4: f = S <= 12 ? half_lds_floats<4, 12>(S, mode) : half_lds_floats<4, kMaxS>(S, mode); break;
         case 5: f = S <= 12 ? half_lds_floats<5, 12>(S, mode) : half_lds_floats<5, kMaxS>(S, mode); break;
-        default: return false;
+        default:
+            // wide patches (forward sweeps): the V buffers grow with P
+            if (P > kMaxPWide || mode == kPassC || mode == kNLM) return false;
+            f = S <= 12 ? half_lds_floats<kMaxPWide, 12>(S, mode) : half_lds_floats<kMaxPWide, kMaxS>(S, mode);
+            break;
     }
     return f * sizeof(float) <= 160 * 1024;
 }

@@ -579,17 +579,19 @@ hipError_t launch_sweep(int mode, int S, int P, const ImgDesc& one, const ImgDes
                      : (mode == kPassBApply || mode == kPassBBuild) ? DSNLM_K_PASS_B
                      : mode == kApply ? DSNLM_K_APPLY
                                       : DSNLM_K_PASS_C;
-    if (P > kMaxP) return batch ? hipErrorInvalidValue : launch_wide(mode, S, P, one, st);
-    if (sweep_takes_half(mode, S, P, one))
+    if (sweep_takes_half(mode, S, P, one) && !(batch && P > kMaxP))
         return launch_half(mode, S, P, one, batch, tiles, ntiles, st);  // times its kernels itself
+    if (P > kMaxP) return batch ? hipErrorInvalidValue : launch_wide(mode, S, P, one, st);
     ProfScope prof(kind, st);
     if (batch) return dispatch_p<true>(mode, S, P, one, batch, tiles, ntiles, st);
     return dispatch_p<false>(mode, S, P, one, batch, tiles, ntiles, st);
 }
 
 bool sweep_takes_half(int mode, int S, int P, const ImgDesc& one) {
-    return P <= kMaxP && one.part && half_mode_ok(mode) && sweep_variant(mode, S, P) == kHalfVariant &&
-           half_lds_fits(S, P, mode);
+    // wide patches (5 < P <= 15) have the half-window forward sweeps only
+    const bool wide_ok = mode == kPassA || mode == kPassBApply || mode == kPassBBuild || mode == kApply;
+    return (P <= kMaxP || (P <= kMaxPWide && wide_ok)) && one.part && half_mode_ok(mode) &&
+           sweep_variant(mode, S, P) == kHalfVariant && half_lds_fits(S, P, mode);
 }
 
 hipError_t launch_epilogue(const ImgDesc& one, const ImgDesc* batch, const TileRef* tiles,
