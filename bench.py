@@ -447,7 +447,7 @@ def main():
     # ---- measured peak rates of this device (context for the roofline)
     import ctypes as C
     probes = {}
-    for kind, name in [(0, "fp32_fma_flop_s"), (1, "exp_per_s"), (2, "hbm_copy_bytes_s")]:
+    for kind, name in [(0, "fp32_fma_flop_s"), (1, "exp_per_s"), (2, "hbm_copy_bytes_s"), (3, "lds_read_bytes_s")]:
         r = C.c_double()
         if lib.dsnlm_peak_probe(kind, C.byref(r), C.c_void_p(torch.cuda.current_stream().cuda_stream)) == 0:
             probes[name] = r.value

@@ -1,5 +1,6 @@
 // Peak-rate probes used as roofline denominators: FP32 FMA issue rate,
-// v_exp_f32 rate and HBM copy bandwidth, each timed with HIP events.
+// v_exp_f32 rate, HBM copy bandwidth and LDS read bandwidth, each timed with
+// HIP events.
 #include "internal.h"
 
 namespace dsnlm {
@@ -42,15 +43,41 @@ __global__ void __launch_bounds__(256) k_probe_copy(const float4* __restrict__ s
     for (size_t i = blockIdx.x * 256 + threadIdx.x; i < n4; i += (size_t)gridDim.x * 256) dst[i] = src[i];
 }
 
+// LDS reads: 16 bytes per lane per read at fixed, conflict-free addresses
+// (consecutive lanes at consecutive 16-byte slots), 8 reads per step, each
+// folded into its own accumulator with one 3-input and one 2-input XOR; a
+// compiler-only memory fence per step keeps the reads inside the loop.
+__global__ void __launch_bounds__(256) k_probe_lds(unsigned* out, int iters) {
+    __shared__ uint4 buf[2048];  // 32 KiB
+    for (int i = threadIdx.x; i < 2048; i += 256) buf[i] = make_uint4(i, 3 * i, 5 * i, 7 * i);
+    __syncthreads();
+    unsigned acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = threadIdx.x + k;
+    const uint4* p = buf + threadIdx.x;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint4 v = p[k * 256];
+            acc[k] = (acc[k] ^ v.x ^ v.y) ^ (v.z ^ v.w);
+        }
+        __asm__ __volatile__("" ::: "memory");
+    }
+    unsigned r = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r ^= acc[k];
+    if (r == 0x12345678u) out[threadIdx.x] = r;  // keeps the reads alive
+}
+
 }  // namespace
 }  // namespace dsnlm
 
 using namespace dsnlm;
 
 // kind 0: FP32 FMA (FLOP/s, 2 per FMA); 1: v_exp_f32 (exp/s); 2: HBM copy
-// (bytes/s, read + write).
+// (bytes/s, read + write); 3: LDS reads (bytes/s over the chip).
 extern "C" int dsnlm_peak_probe(int kind, double* rate, void* stream) {
-    if (!rate || kind < 0 || kind > 2) return fail(DSNLM_EINVAL, "dsnlm_peak_probe: bad argument");
+    if (!rate || kind < 0 || kind > 3) return fail(DSNLM_EINVAL, "dsnlm_peak_probe: bad argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
     int dev = 0, ncu = 0;
     (void)hipGetDevice(&dev);
@@ -79,9 +106,12 @@ extern "C" int dsnlm_peak_probe(int kind, double* rate, void* stream) {
         } else if (kind == 1) {
             hipLaunchKernelGGL(k_probe_exp, dim3(blocks), dim3(256), 0, st, out, iters);
             if (r) work += 16.0 * iters * (double)blocks * 256;
-        } else {
+        } else if (kind == 2) {
             hipLaunchKernelGGL(k_probe_copy, dim3(ncu * 16), dim3(256), 0, st, a, b, bytes / 16);
             if (r) work += 2.0 * bytes;
+        } else {
+            hipLaunchKernelGGL(k_probe_lds, dim3(blocks), dim3(256), 0, st, reinterpret_cast<unsigned*>(out), iters);
+            if (r) work += 16.0 * 8 * iters * (double)blocks * 256;
         }
         if (!rc) rc = check_hip(hipGetLastError(), "probe launch");
     }
