@@ -76,3 +76,36 @@ def test_unrolled_sr_reverse_step_runs_and_is_deterministic():
         outs.append((float(lt.grad), float(rt.grad)))
     assert outs[0] == outs[1]
     assert all(np.isfinite(v) for v in outs[0])
+
+
+def test_unrolled_spi_thirty_iterations_against_stored_oracle():
+    """The configuration's unrolled solve (30 iterations, weights frozen after
+    5, S = 7, P = 2, K = 16, eta = 4, coupled bandwidth) on a 48 x 48 image:
+    dL/dlambda, dL/drho and the initial image's adjoint against the FP64
+    oracle's values stored by tests/golden/make_unrolled_spi.py (the oracle
+    takes about a minute here, so it is not rerun in the test)."""
+    import json
+    import os
+    M = _M()
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "unrolled_spi_48.json")))
+    n, K, eta = ref["n"], ref["K"], ref["eta"]
+    clean, uni = synth.config4_batch(count=1, n=n, K=K)[0]
+    ones = L.spi_counts(clean, uni, eta)
+    x0 = np.clip(L.spi_ml(ones, K, eta), 0, 1).astype(np.float32)
+    op = M.SPIOperator(n1=n, n2=n, ones=_t(ones, np.uint8), K=K, eta=eta)
+    prm = M.LadmmParams(lam=ref["lam"], rho=ref["rho"], gamma=1.0 / (eta * eta), S=ref["S"], P=ref["P"], h=0.0,
+                        iters=ref["iters"], freeze_after=ref["freeze_after"])
+    x0t = _t(x0).requires_grad_(True)
+    lt = torch.tensor(ref["lam"], device="cuda", requires_grad=True)
+    rt = torch.tensor(ref["rho"], device="cuda", requires_grad=True)
+    print(f"unrolled SPI {n}x{n} iters={ref['iters']} against the stored oracle", flush=True)
+    x = M.unrolled_ladmm(x0t, lt, rt, op, prm)
+    ((x.double() - _t(clean).double()) ** 2).sum().backward()
+    torch.cuda.synchronize()
+    idx = np.asarray(ref["pixels"])
+    assert np.abs(x.detach().cpu().numpy().ravel()[idx] - np.asarray(ref["x_final"])).max() <= 1e-4
+    assert abs(float(lt.grad) - ref["dlambda"]) <= 1e-3 * abs(ref["dlambda"])
+    assert abs(float(rt.grad) - ref["drho"]) <= 1e-3 * abs(ref["drho"])
+    g = x0t.grad.cpu().numpy().ravel()
+    assert np.abs(g[idx] - np.asarray(ref["dx0"])).max() <= 1e-3 * ref["dx0_maxabs"]
+    assert abs(float(np.sqrt((g.astype(np.float64) ** 2).sum())) - ref["dx0_norm2"]) <= 1e-3 * ref["dx0_norm2"]
