@@ -21,7 +21,7 @@ What is computed (Section 3 of the paper):
   makes every row sum exactly one);
 * output W x.  Algorithm 2 computes the same product without storing W.
 
-Two independent routes are provided:
+Three routes are provided:
 
 dense_weights / dsnlm_dense -- build the n x n matrices of eqs. S1-S3 literally
                                (tiny images only; patches cut from numpy's
@@ -35,6 +35,11 @@ dsnlm_shifts                -- the same matrices evaluated one window shift at
                                box-sum trick) and the mirror indexing of
                                sym_index.  This is the route used for GPU
                                parity and for the CPU baseline.
+dsnlm_pixels                -- the rows of the same matrices at chosen
+                               pixels only (numpy float64), for images the
+                               band route cannot afford: omega at a pixel and
+                               at each of its partners from their own rows,
+                               delta and y at the pixel given the image's m.
 """
 from __future__ import annotations
 
@@ -50,6 +55,7 @@ __all__ = [
     "dense_weights",
     "dsnlm_dense",
     "dsnlm_shifts",
+    "dsnlm_pixels",
     "check_args",
 ]
 
@@ -255,6 +261,64 @@ def dsnlm_shifts(x, z, S: int, P: int, h, want: str = "y", distances: str = "dir
         hs[i0:i1, j0:j1] += w
     out["y"] = acc + (1.0 - hs) * xt
     return out
+
+
+# ---------------------------------------------------------------------------
+# Route 3: the rows of S1-S3 one pixel at a time (images of any size).
+# ---------------------------------------------------------------------------
+def _row_weights(zp: np.ndarray, n1: int, n2: int, ci, cj, S: int, P: int, kappa: float):
+    """Step S1 rows of the pixels (ci[k], cj[k]): for each, the partners
+    r = (ci + dy, cj + dx) of its window, a mask of those inside the image, and
+    their weights Lambda_d k_{s,r} (zero outside), the patch distances summed
+    directly over the N_p^2 offsets of the guide padded by P (zp).  Arrays of
+    shape (len(ci), (2S + 1)^2)."""
+    Np = 2 * P + 1
+    dy, dx = np.meshgrid(np.arange(-S, S + 1), np.arange(-S, S + 1), indexing="ij")
+    ci = np.asarray(ci)[:, None]
+    cj = np.asarray(cj)[:, None]
+    ri, rj = ci + dy.ravel()[None, :], cj + dx.ravel()[None, :]
+    keep = (ri >= 0) & (ri < n1) & (rj >= 0) & (rj < n2)
+    qi, qj = np.where(keep, ri, ci), np.where(keep, rj, cj)  # in range; masked below
+    dist = np.zeros(ri.shape)
+    for ty in range(Np):
+        for tx in range(Np):
+            dist += (zp[ci + ty, cj + tx] - zp[qi + ty, qj + tx]) ** 2
+    lam = (1.0 - np.abs(dy.ravel()) / (S + 1.0)) * (1.0 - np.abs(dx.ravel()) / (S + 1.0))
+    return ri, rj, keep, np.where(keep, lam[None, :] * np.exp(-kappa * dist), 0.0)
+
+
+def dsnlm_pixels(x, z, S: int, P: int, h: float, pixels, m: float) -> dict:
+    """omega, delta and y = (W x) at the listed pixels, each from its own rows
+    of the matrices of steps S1-S3, for images too large for the band route.
+
+    omega_s is the row sum of step S1 at s; delta_s = sum_r (omega_s
+    omega_r)^-1/2 w1_{s,r} (step S2, which needs omega at every partner r of
+    s, each from that partner's own row); y_s = sum_r w_{s,r} x_r + (1 -
+    sum_r w_{s,r}) x_s with w = (omega_s omega_r)^-1/2 w1 / m (step S3).  The
+    normalisation m, the maximum of delta over the whole image, is an input:
+    the caller checks it separately (delta at the maximising pixel is one of
+    the pixels this function can evaluate).
+    pixels: iterable of (i, j).  Returns arrays omega, delta, y over them.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    n1, n2 = z.shape
+    check_args(n1, n2, S, P, h)
+    Np = 2 * P + 1
+    zp = z[sym_index(n1, P)][:, sym_index(n2, P)]
+    kappa = 1.0 / (2.0 * Np * Np * h * h)
+    om, de, ys = [], [], []
+    for i, j in pixels:
+        ri, rj, keep, w1 = _row_weights(zp, n1, n2, [i], [j], S, P, kappa)
+        ri, rj, w1 = ri[0][keep[0]], rj[0][keep[0]], w1[0][keep[0]]
+        om_s = w1.sum()
+        om_r = _row_weights(zp, n1, n2, ri, rj, S, P, kappa)[3].sum(axis=1)
+        w2 = (om_s * om_r) ** -0.5 * w1
+        w = w2 / m
+        om.append(om_s)
+        de.append(w2.sum())
+        ys.append((w * x[ri, rj]).sum() + (1.0 - w.sum()) * x[i, j])
+    return dict(omega=np.array(om), delta=np.array(de), y=np.array(ys))
 
 
 # ---------------------------------------------------------------------------

@@ -214,3 +214,33 @@ def test_batched_bench_instance_matches_oracle():
             assert am == amo, (k, am, amo)
         assert np.abs(delta.cpu().numpy() - dl).max() <= 2e-5
         assert np.abs(c.cpu().numpy() / om ** -0.5 - 1).max() <= 2e-5
+
+
+def test_batched_full_config_sampled_pixels_match_oracle():
+    """The 64-image batch the bench times (20.5 Mpx, images up to 1024 x 1024,
+    S = 10, P = 3, h = 1.2 sigma_n, one launch per sweep), against the FP64
+    oracle at full size on sampled pixels, each evaluated from its own rows of
+    the matrices of steps S1-S3: at the pixel where the GPU puts the maximum
+    the oracle's delta equals the GPU's m; at that pixel, two corners and two
+    random pixels of every image the oracle's omega (through c), delta and
+    y = W x (given m) equal the GPU's, and no sampled delta exceeds m."""
+    M = _gpu()
+    batch = synth.config2_batch()
+    xs = [_t(it.noisy) for it in batch]
+    print("batched config sampled pixels: %d images" % len(xs), flush=True)
+    ys = M.dsnlm_forward_batched([(x, x, it.h) for x, it in zip(xs, batch)], 10, 3)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(77)
+    for k, (it, y) in enumerate(zip(batch, ys)):
+        m, am, c, delta = M.dsnlm_batched_state(k)
+        n1, n2 = it.noisy.shape
+        pix = [(am // n2, am % n2), (0, 0), (n1 - 1, n2 - 1),
+               (int(rng.integers(n1)), int(rng.integers(n2))), (int(rng.integers(n1)), int(rng.integers(n2)))]
+        q = R.dsnlm_pixels(it.noisy, it.noisy, 10, 3, it.h, pix, m)
+        assert abs(q["delta"][0] - m) <= 2e-5 * m, (k, q["delta"][0], m)
+        yc, cc, dc = y.cpu().numpy(), c.cpu().numpy(), delta.cpu().numpy()
+        for t, (i, j) in enumerate(pix):
+            assert abs(yc[i, j] - q["y"][t]) <= TOL, (k, i, j)
+            assert abs(cc[i, j] * q["omega"][t] ** 0.5 - 1) <= 2e-5, (k, i, j)
+            assert abs(dc[i, j] - q["delta"][t]) <= 2e-5, (k, i, j)
+            assert q["delta"][t] <= m * (1 + 2e-5), (k, i, j)

@@ -225,3 +225,36 @@ def test_integral_image_distances_equal_direct_sums(n1, n2, S, P):
     a = R.dsnlm_shifts(x, z, S, P, h)["y"]
     b = R.dsnlm_shifts(x, z, S, P, h, distances="integral")["y"]
     assert float((a - b).abs().max()) <= 1e-12
+
+
+@pytest.mark.parametrize("n1,n2,S,P", [(7, 9, 3, 1), (6, 5, 6, 2), (1, 8, 2, 0)])
+def test_pixel_rows_equal_dense_matrices(n1, n2, S, P):
+    """The one-pixel-at-a-time route against the n x n matrices of steps
+    S1-S3 built literally, at every pixel of a tiny image (windows cut by
+    every border, S beyond the image)."""
+    z, x = _img(n1, n2, 31), _img(n1, n2, 32)
+    h = 0.15
+    dw = R.dense_weights(z, S, P, h)
+    pix = [(i, j) for i in range(n1) for j in range(n2)]
+    q = R.dsnlm_pixels(x, z, S, P, h, pix, dw["m"])
+    y = (dw["W"] @ x.astype(np.float64).ravel())
+    assert np.abs(q["omega"] - dw["omega"]).max() <= 1e-13
+    assert np.abs(q["delta"] - dw["delta"]).max() <= 1e-13
+    assert np.abs(q["y"] - y).max() <= 1e-13
+
+
+def test_pixel_rows_equal_shift_bands():
+    """The same against the band-by-band route on a larger image, at the
+    corners, edges, an interior pixel and the maximising pixel."""
+    n1, n2, S, P, h = 40, 57, 10, 3, 0.08
+    z, x = _img(n1, n2, 33), _img(n1, n2, 34)
+    o = R.dsnlm_shifts(x, z, S, P, h)
+    am = o["argmax"]
+    pix = [(0, 0), (0, n2 - 1), (n1 - 1, 0), (n1 - 1, n2 - 1), (3, 20), (20, 2), (17, 31),
+           (am // n2, am % n2)]
+    q = R.dsnlm_pixels(x, z, S, P, h, pix, float(o["m"]))
+    for k, (i, j) in enumerate(pix):
+        assert abs(q["omega"][k] - float(o["omega"][i, j])) <= 1e-12
+        assert abs(q["delta"][k] - float(o["delta"][i, j])) <= 1e-12
+        assert abs(q["y"][k] - float(o["y"][i, j])) <= 1e-12
+    assert q["delta"][-1] == pytest.approx(float(o["m"]), abs=1e-12)
