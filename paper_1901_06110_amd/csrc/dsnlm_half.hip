@@ -319,7 +319,13 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
                     // read here, so that the scalar load has returned by the
                     // barrier and no wait for it holds up the LDS reads after it
                     const float lg = hat.lg[dy + S] + hat.lg[dx + S];
-                    // phase 1: vertical sliding box of (z(p) - z(p+d))^2
+                    // phase 1: vertical sliding box of (z(p) - z(p+d))^2.
+                    // Its waves run at raised issue priority: the block's
+                    // barrier waits for them, while the other block on the
+                    // CU is in phase 2 and can yield the SIMDs (measured on
+                    // the 64-image batch: pass A -5%, pass B and sweep C
+                    // -4%; priority 3 no better than 1).
+                    __builtin_amdgcn_s_setprio(1);
                     if (has1) {
                         float tq[NE];
 #pragma unroll
@@ -336,6 +342,7 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
                             vo[q * VW] = v;
                         }
                     }
+                    __builtin_amdgcn_s_setprio(0);
                     __syncthreads();
                     // phase 2: horizontal sliding box, weights, both-sided sums
                     float vv[NV];
