@@ -320,12 +320,12 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
                     // barrier and no wait for it holds up the LDS reads after it
                     const float lg = hat.lg[dy + S] + hat.lg[dx + S];
                     // phase 1: vertical sliding box of (z(p) - z(p+d))^2.
-                    // Its waves run at raised issue priority: the block's
-                    // barrier waits for them, while the other block on the
-                    // CU is in phase 2 and can yield the SIMDs (measured on
-                    // the 64-image batch: pass A -5%, pass B and sweep C
-                    // -4%; priority 3 no better than 1).
-                    __builtin_amdgcn_s_setprio(1);
+                    // Issue priorities: phase 1 highest (the block's barrier
+                    // waits for it while the other block on the CU is in
+                    // phase 2), then the LDS reads that open phase 2, then
+                    // the rest.  Measured on the 64-image batch against no
+                    // priorities: pass A -5%, pass B and sweep C -5%.
+                    __builtin_amdgcn_s_setprio(2);
                     if (has1) {
                         float tq[NE];
 #pragma unroll
@@ -342,7 +342,7 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
                             vo[q * VW] = v;
                         }
                     }
-                    __builtin_amdgcn_s_setprio(0);
+                    __builtin_amdgcn_s_setprio(1);
                     __syncthreads();
                     // phase 2: horizontal sliding box, weights, both-sided sums
                     float vv[NV];
@@ -366,6 +366,7 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
 #pragma unroll
                         for (int k = 0; k < L; ++k) pv[k] = reinterpret_cast<const float4*>(Acc)[pr + k];
                     }
+                    __builtin_amdgcn_s_setprio(0);
                     float hs = vv[0];
 #pragma unroll
                     for (int q = 1; q <= 2 * P; ++q) hs += vv[q];

@@ -357,7 +357,13 @@ k_d2(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__
                         }
                     }
                     loadr(dy, dx);  // in flight over phase 3, the barrier and phase 4
+                    // phase 3 is a chain of LDS round trips on the block's
+                    // path to the barrier: raised issue priority lets each
+                    // step go as soon as its rows arrive (-1% on the batch;
+                    // the same for phase 1, or for phases 4 and 2, gains less)
+                    __builtin_amdgcn_s_setprio(1);
                     if (t > 0) phase3();
+                    __builtin_amdgcn_s_setprio(0);
                     __syncthreads();
                     if (t > 0) phase4(pdy, pdx);
                     math2(dy, dx);
