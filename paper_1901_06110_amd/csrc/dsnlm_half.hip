@@ -102,7 +102,7 @@ k_half_pad(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __rest
     ImgDesc d;
     int ti0, tj0;
     if constexpr (BATCH) {
-        const TileRef t = tiles[blockIdx.x];
+        const TileRef t = tiles[xcd_tile((int)blockIdx.x, (int)gridDim.x)];
         d = batch[t.img];
         ti0 = t.ti0;
         tj0 = t.tj0;
@@ -143,7 +143,7 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
     int ti0, tj0;
     bool first;
     if constexpr (BATCH) {
-        const TileRef t = tiles[blockIdx.x];
+        const TileRef t = tiles[xcd_tile((int)blockIdx.x, (int)gridDim.x)];
         d = batch[t.img];
         ti0 = t.ti0;
         tj0 = t.tj0;
@@ -461,7 +461,7 @@ k_half_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __r
     ImgDesc d;
     int ti0, tj0;
     if constexpr (BATCH) {
-        const TileRef t = tiles[blockIdx.x];
+        const TileRef t = tiles[xcd_tile((int)blockIdx.x, (int)gridDim.x)];
         d = batch[t.img];
         ti0 = t.ti0;
         tj0 = t.tj0;

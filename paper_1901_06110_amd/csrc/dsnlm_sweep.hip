@@ -109,7 +109,7 @@ k_sweep(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restric
     int ti0, tj0;
     bool first;
     if constexpr (BATCH) {
-        const TileRef t = tiles[blockIdx.x];
+        const TileRef t = tiles[xcd_tile((int)blockIdx.x, (int)gridDim.x)];
         d = batch[t.img];
         ti0 = t.ti0;
         tj0 = t.tj0;
@@ -409,7 +409,7 @@ k_epilogue(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __rest
     ImgDesc d;
     int ti0, tj0;
     if constexpr (BATCH) {
-        const TileRef t = tiles[blockIdx.x];
+        const TileRef t = tiles[xcd_tile((int)blockIdx.x, (int)gridDim.x)];
         d = batch[t.img];
         ti0 = t.ti0;
         tj0 = t.tj0;

@@ -90,7 +90,7 @@ k_d2(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__
     ImgDesc d;
     int ti0, tj0;
     if constexpr (BATCH) {
-        const TileRef t = tiles[blockIdx.x];
+        const TileRef t = tiles[xcd_tile((int)blockIdx.x, (int)gridDim.x)];
         d = batch[t.img];
         ti0 = t.ti0;
         tj0 = t.tj0;

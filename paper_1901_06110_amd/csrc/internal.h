@@ -83,6 +83,16 @@ struct TileRef {
     int flags;             // bit 0: first tile of its image
 };
 
+// Tile of block b in a batched launch of n blocks (one per tile).  The
+// hardware deals consecutive blocks to the 8 XCDs in turn, so block b runs on
+// XCD b mod 8; this gives each XCD a contiguous run of the tile list (the
+// tiles of one image in row-major order), so that neighbouring tiles, which
+// read the same guide and factor halos, share that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+    const int x = b & 7, q = n >> 3, r = n & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 enum SweepMode : int {
     kPassA = 0,        // row sums of step S1 -> c
     kPassBApply = 1,   // delta, B' and the running max key (x known)
