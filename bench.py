@@ -164,12 +164,14 @@ def _kernel_ms(lib, kinds, fn, reps):
     return out
 
 
-def cpu_table1(n: int = 64, S: int = 10, Ps=(1, 3, 5, 8, 11, 14)):
-    """Table 1 on the host: the FP64 oracle's two patch-distance routes on an
-    n x n synthetic image, window (2S+1)^2, patch sides N_p = 2P+1 -- the
-    direct N_p^2 sums (the brute force) against the integral image of each
-    shift's squared-difference image (the fast scheme of Section 3).  Both
-    run the same shift loop, so the ratio isolates the patch distances."""
+def cpu_baseline_table1(n: int = 64, S: int = 10, Ps=(1, 3, 5, 8, 11, 14)):
+    """The CPU-baseline leg of Table 1 (`--table1-cpu`, not part of the
+    default run): the FP64 oracle's two patch-distance routes timed on the
+    host, on an n x n synthetic image, window (2S+1)^2, patch sides
+    N_p = 2P+1 -- the direct N_p^2 sums (the brute force) against the
+    integral image of each shift's squared-difference image (the fast scheme
+    of Section 3).  Both run the same shift loop, so the ratio isolates the
+    patch distances."""
     import torch
     import synth
     from oracle import dsnlm_ref
@@ -384,7 +386,7 @@ def main():
                     help="only time Table 1 on the host (the oracle's direct vs integral-image distances)")
     args = ap.parse_args()
     if args.table1_cpu:
-        print(json.dumps(cpu_table1()))
+        print(json.dumps(cpu_baseline_table1()))
         return
     if args.only_ladmm:
         import paper_1901_06110_amd as M
