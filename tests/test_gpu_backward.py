@@ -221,3 +221,32 @@ def test_batched_backward_full_size_directional_derivatives():
         print(f"  guide {an:.6g} vs fd {fd:.6g}; x {lhs:.8g} vs {rhs:.8g}; h {float(dh.cpu()):.6g} vs fd {dhf:.6g}",
               flush=True)
         assert abs(float(dh.cpu()) - dhf) <= 2e-3 * abs(dhf), (float(dh.cpu()), dhf)
+
+
+def test_batched_backward_full_config_sampled_pixels():
+    """The backward the bench times: the 64-image batch (20.5 Mpx, S = 10,
+    P = 3, h = 1.2 sigma_n) with every gradient requested.  W is symmetric,
+    so x-bar = W y-bar; at two corners and three random pixels of every image
+    it must equal the FP64 oracle's rows of steps S1-S3 applied to y-bar
+    (given the image's m), and over each whole image sum(x-bar) = sum(y-bar)
+    (the columns of W sum to one); h-bar is finite."""
+    M = _M()
+    batch = synth.config2_batch()
+    xs = [_t(it.noisy) for it in batch]
+    print("batched backward full config: %d images" % len(xs), flush=True)
+    M.dsnlm_forward_batched([(x, x, it.h) for x, it in zip(xs, batch)], 10, 3)
+    rng = np.random.default_rng(91)
+    ybars = [rng.standard_normal(it.noisy.shape).astype(np.float32) for it in batch]
+    out = M.dsnlm_backward_batched([_t(yb) for yb in ybars])
+    torch.cuda.synchronize()
+    for k, (it, yb, (dx, dg, dh)) in enumerate(zip(batch, ybars, out)):
+        m, _, _, _ = M.dsnlm_batched_state(k)
+        n1, n2 = it.noisy.shape
+        dxc = dx.cpu().numpy()
+        assert abs(float(dxc.astype(np.float64).sum()) - float(yb.astype(np.float64).sum())) <= 1e-5 * yb.size, k
+        assert np.isfinite(float(dh.cpu())) and bool(torch.isfinite(dg).all()), k
+        pix = [(0, 0), (n1 - 1, n2 - 1)] + [(int(rng.integers(n1)), int(rng.integers(n2))) for _ in range(3)]
+        q = R.dsnlm_pixels(yb, it.noisy, 10, 3, it.h, pix, m)
+        scale = float(np.abs(yb).max())
+        for t, (i, j) in enumerate(pix):
+            assert abs(dxc[i, j] - q["y"][t]) <= 1e-4 * scale, (k, i, j, dxc[i, j], q["y"][t])
