@@ -185,6 +185,11 @@ k_d2(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__
     const int q4 = has4 ? tid - (NT - G::NQ) : 0;
     const int qr = q4 / G::NSEG - P;
     const int qc = (q4 - (qr + P) * G::NSEG) * L4 - P;
+    // loop-invariant parts of the phase-4 addresses (each shift adds a
+    // wave-uniform offset: one addition per pointer instead of a multiply)
+    const int vq0 = (qr + P) * VBW + qc + P;
+    const int zq0 = (qc + P) * ZC + qr + P;
+    const int rq0 = (qr + P) * RWc + qc + P + S;
     float zown[L4], accz[L4];
     float hsum = 0.f;  // sum of D-bar D over the tile's pairs
 #pragma unroll
@@ -288,9 +293,9 @@ k_d2(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__
         if (has4) {
             // every read before the first write: the writes could alias the
             // reads as far as the compiler knows, and would force reloads
-            const float* vr = VDb + (qr + P) * VBW + qc + P;
-            const float* zq = Zs + (qc + P + S + dx) * ZC + qr + P + dy;
-            float* rq = Rg + (qr + P + dy) * RWc + qc + P + S + dx;
+            const float* vr = VDb + vq0;
+            const float* zq = Zs + zq0 + ((S + dx) * ZC + dy);
+            float* rq = Rg + rq0 + (dy * RWc + dx);
             float vq[L4 + 2 * P], zs[L4], rg[L4];
 #pragma unroll
             for (int q = 0; q < L4 + 2 * P; ++q) vq[q] = vr[q];
