@@ -284,11 +284,18 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
     // one tile per CU) have none to spare and load each group's rows at its
     // start.
     constexpr bool PF = MODE != kPassA && P <= 3;
+    // With the look-ahead, only the threads with a phase-1 item load windows
+    // (the others, the last three waves of the block and part of the fifth,
+    // would only repeat item 0's loads).
     float nwin[PF ? NW : 1];
     if constexpr (PF) {
-        const int zw = zbase + dyF * W2 + dxF;
 #pragma unroll
-        for (int q = 0; q < NW; ++q) nwin[q] = __builtin_bit_cast(float, zload(zw + q * W2));
+        for (int q = 0; q < NW; ++q) nwin[q] = 0.f;
+        if (has1) {
+            const int zw = zbase + dyF * W2 + dxF;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) nwin[q] = __builtin_bit_cast(float, zload(zw + q * W2));
+        }
     }
     int t = 0;
     for (int dx = dxF; dx <= dxL; ++dx) {
@@ -303,10 +310,14 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
                 // inside the range-checked buffer
                 const int ndx = dy0 + GW <= dyB ? dx : dx + 1;
                 const int ndy0 = dy0 + GW <= dyB ? dy0 + GW : (ndx > 0 ? 0 : 1);
-                const int zw = zbase + ndy0 * W2 + ndx;
+                if (has1) {
+                    const int zw = zbase + ndy0 * W2 + ndx;
 #pragma unroll
-                for (int q = 0; q < NW; ++q) nwin[q] = __builtin_bit_cast(float, zload(zw + q * W2));
+                    for (int q = 0; q < NW; ++q) nwin[q] = __builtin_bit_cast(float, zload(zw + q * W2));
+                }
             } else {
+                // (unguarded: under pass A's register cap the guarded form
+                // spills)
                 const int zw = zbase + dy0 * W2 + dx;
 #pragma unroll
                 for (int q = 0; q < NW; ++q) win[q] = __builtin_bit_cast(float, zload(zw + q * W2));
