@@ -84,10 +84,12 @@ struct TileRef {
 };
 
 // Tile of block b in a batched launch of n blocks (one per tile).  The
-// hardware deals consecutive blocks to the 8 XCDs in turn, so block b runs on
-// XCD b mod 8; this gives each XCD a contiguous run of the tile list (the
+// dispatcher deals consecutive blocks to the 8 XCDs in turn, so block b runs
+// on XCD b mod 8; this gives each XCD a contiguous run of the tile list (the
 // tiles of one image in row-major order), so that neighbouring tiles, which
-// read the same guide and factor halos, share that XCD's L2.
+// read the same guide and factor halos, share that XCD's L2.  The mapping is
+// a permutation of 0..n-1: any other placement of blocks changes only which
+// tiles share an L2, not the results.
 __device__ __forceinline__ int xcd_tile(int b, int n) {
     const int x = b & 7, q = n >> 3, r = n & 7;
     return x * q + (x < r ? x : r) + (b >> 3);
