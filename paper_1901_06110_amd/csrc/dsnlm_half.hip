@@ -301,6 +301,11 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
     for (int dx = dxF; dx <= dxL; ++dx) {
         const int dyA = dx == dxF ? dyF : (dx > 0 ? 0 : 1);  // the half window
         const int dyB = dx == dxL ? dyL : S;
+        // log2 of the hat's dx factor in a vector register (a VALU
+        // instruction reads one scalar operand, so log2 Lambda_d is then one
+        // addition per shift instead of a move and an addition)
+        float lgx;
+        asm("v_mov_b32 %0, %1" : "=v"(lgx) : "s"(hat.lg[dx + S]));
         for (int dy0 = dyA; dy0 <= dyB; dy0 += GW) {
             float win[NW];
             if constexpr (PF) {
@@ -329,7 +334,7 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
                     float* V = Vb + (t & 1) * (TH * VW);
                     // read here, so that the scalar load has returned by the
                     // barrier and no wait for it holds up the LDS reads after it
-                    const float lg = hat.lg[dy + S] + hat.lg[dx + S];
+                    const float lg = hat.lg[dy + S] + lgx;
                     // phase 1: vertical sliding box of (z(p) - z(p+d))^2.
                     // Issue priorities: phase 1 highest (the block's barrier
                     // waits for it while the other block on the CU is in
