@@ -216,6 +216,7 @@ k_d2(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__
     //   -kappa (omegabar_s + omegabar_r)
     //   - kappa c_s c_r ((B'bar_s - B'bar_r)(x_r - x_s) + f_s + f_r)
     constexpr int NV = ((L + 2 * P + 3) / 4) * 4;
+    float lgx = 0.f;  // log2 of the hat's dx factor, set per dx below
     auto math2 = [&](int dy, int dx) {
         float vv[NV];
         const float* vr = V + pi * VW + pj;
@@ -227,7 +228,7 @@ k_d2(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__
             vv[4 * q + 2] = t4.z;
             vv[4 * q + 3] = t4.w;
         }
-        const float lg = hat.lg[dy + S] + hat.lg[dx + S];
+        const float lg = hat.lg[dy + S] + lgx;
         float hs = vv[0];
 #pragma unroll
         for (int q = 1; q <= 2 * P; ++q) hs += vv[q];
@@ -334,6 +335,9 @@ k_d2(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__
     const int dxhi = BATCH ? S + 1 : -S + (grp + 1) * (2 * S + 1) / ngrp;
     for (int dx = -S; dx <= S; ++dx) {
         if (dx < dxlo || dx >= dxhi) continue;  // another group's (uniform)
+        // the hat's dx term in a vector register: one addition per shift for
+        // log2 Lambda_d (a VALU instruction reads one scalar operand)
+        asm("v_mov_b32 %0, %1" : "=v"(lgx) : "s"(hat.lg[dx + S]));
         for (int dy0 = dx > 0 ? 0 : 1; dy0 <= S; dy0 += GW) {
             float win[NW];
             {
