@@ -127,9 +127,21 @@ __device__ __forceinline__ void footprint(int p, int f, int R, int bs, int m, in
 // a preimage of (i, j).  BS > 0: blur size BS and factor F fixed at compile
 // time, with at most ceil(BS / F) samples per axis and preimage (loops
 // unrolled, same order of additions as the general form).
-template <int BOUNDARY, int BS, int F>
-__device__ __forceinline__ float sr_adjoint_at(const float* __restrict__ r, int i, int j,
-                                               const SRGeom& g, const Taps& taps) {
+// Readers of the low-resolution residual r(I, J): the whole grid in global
+// memory, or a block's window of it in LDS.
+struct RGlobal {
+    const float* __restrict__ r;
+    int m2;
+    __device__ float operator()(int I, int J) const { return r[(size_t)I * m2 + J]; }
+};
+struct RLds {
+    const float* r;
+    int stride, I0, J0;
+    __device__ float operator()(int I, int J) const { return r[(I - I0) * stride + (J - J0)]; }
+};
+
+template <int BOUNDARY, int BS, int F, class RD>
+__device__ __forceinline__ float sr_adjoint_at(const RD& rd, int i, int j, const SRGeom& g, const Taps& taps) {
     constexpr int NS = BS > 0 ? (BS + F - 1) / F : 1;
     const int f = BS > 0 ? F : g.f, bs = BS > 0 ? BS : g.bs, R = (bs - 1) / 2;
     int pi[3], pj[3];
@@ -146,7 +158,6 @@ __device__ __forceinline__ float sr_adjoint_at(const float* __restrict__ r, int 
                 const int I = Ilo + t;
                 if (I <= Ihi) {
                     const float ta = taps.t[ip - F * I + R];
-                    const float* rr = r + (size_t)I * g.m2;
                     float rowacc = 0.f;
                     for (int b = 0; b < cj; ++b) {
                         const int jp = pj[b];
@@ -155,7 +166,7 @@ __device__ __forceinline__ float sr_adjoint_at(const float* __restrict__ r, int 
 #pragma unroll
                         for (int q = 0; q < NS; ++q) {
                             const int J = Jlo + q;
-                            if (J <= Jhi) rowacc = fmaf(taps.t[jp - F * J + R], rr[J], rowacc);
+                            if (J <= Jhi) rowacc = fmaf(taps.t[jp - F * J + R], rd(I, J), rowacc);
                         }
                     }
                     acc = fmaf(ta, rowacc, acc);
@@ -164,13 +175,12 @@ __device__ __forceinline__ float sr_adjoint_at(const float* __restrict__ r, int 
         } else {
             for (int I = Ilo; I <= Ihi; ++I) {
                 const float ta = taps.t[ip - f * I + R];
-                const float* rr = r + (size_t)I * g.m2;
                 float rowacc = 0.f;
                 for (int b = 0; b < cj; ++b) {
                     const int jp = pj[b];
                     int Jlo, Jhi;
                     footprint(jp, f, R, bs, g.m2, &Jlo, &Jhi);
-                    for (int J = Jlo; J <= Jhi; ++J) rowacc = fmaf(taps.t[jp - f * J + R], rr[J], rowacc);
+                    for (int J = Jlo; J <= Jhi; ++J) rowacc = fmaf(taps.t[jp - f * J + R], rd(I, J), rowacc);
                 }
                 acc = fmaf(ta, rowacc, acc);
             }
@@ -182,6 +192,21 @@ __device__ __forceinline__ float sr_adjoint_at(const float* __restrict__ r, int 
 struct StepScalars {
     float alpha, rho, mu, lo, hi;
 };
+
+// clip(mu (alpha x + rho (v - u) - grad)): the x-step at one pixel.
+__device__ __forceinline__ float xstep_value(float grad, float x, float v, float u, const StepScalars& s) {
+    const float xn = s.mu * (s.alpha * x + s.rho * (v - u) - grad);
+    return fminf(fmaxf(xn, s.lo), s.hi);
+}
+
+// xo = the x-step and z = xo + u at idx.
+__device__ __forceinline__ void xstep_store(float grad, const float* x, const float* v, const float* u, float* xo,
+                                            float* z, size_t idx, const StepScalars& s) {
+    const float uu = u[idx];
+    const float xn = xstep_value(grad, x[idx], v[idx], uu, s);
+    xo[idx] = xn;
+    z[idx] = xn + uu;
+}
 
 // x <- clip(mu (alpha x + rho (v - u) - A^T r)); z = x + u.
 // With step == 0 it only writes g = A^T r into xo (gradient / adjoint).
@@ -200,9 +225,8 @@ __device__ __forceinline__ float phase_tap(const Taps& taps, int t, int ph) {
 // footprint (R <= i < n1 - R, R <= j < n2 - R): the samples of an axis are
 // I = (i + R) / F - t, t = 0 .. ceil(BS / F) - 1, with tap b[(i + R) % F + F t]
 // (zero where that passes the kernel); they all lie inside the grid.
-template <int BS, int F>
-__device__ __forceinline__ float sr_adjoint_interior(const float* __restrict__ r, int i, int j, const SRGeom& g,
-                                                     const Taps& taps) {
+template <int BS, int F, class RD>
+__device__ __forceinline__ float sr_adjoint_interior(const RD& rd, int i, int j, const Taps& taps) {
     constexpr int R = (BS - 1) / 2, NS = (BS + F - 1) / F;
     const int qi = i + R, qj = j + R;
     const int phi = qi % F, phj = qj % F;
@@ -217,7 +241,7 @@ __device__ __forceinline__ float sr_adjoint_interior(const float* __restrict__ r
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
             const int J = J0 - q > 0 ? J0 - q : 0;
-            rv[t][q] = r[(size_t)I * g.m2 + J];
+            rv[t][q] = rd(I, J);
         }
     }
     float acc = 0.f;
@@ -239,24 +263,137 @@ k_sr_adjoint_step(const float* __restrict__ r, float* __restrict__ x, const floa
     const int idx = blockIdx.x * 256 + threadIdx.x;
     if (idx >= g.n1 * g.n2) return;
     const int i = idx / g.n2, j = idx - i * g.n2;
+    const RGlobal rd{r, g.m2};
     float grad;
     if constexpr (BS > 0) {
         constexpr int R = (BS - 1) / 2;
         if (i >= R && i < g.n1 - R && j >= R && j < g.n2 - R)
-            grad = sr_adjoint_interior<BS, F>(r, i, j, g, taps);
+            grad = sr_adjoint_interior<BS, F>(rd, i, j, taps);
         else
-            grad = sr_adjoint_at<BOUNDARY, BS, F>(r, i, j, g, taps);
+            grad = sr_adjoint_at<BOUNDARY, BS, F>(rd, i, j, g, taps);
     } else {
-        grad = sr_adjoint_at<BOUNDARY, BS, F>(r, i, j, g, taps);
+        grad = sr_adjoint_at<BOUNDARY, BS, F>(rd, i, j, g, taps);
     }
     if (!step) {
         x[idx] = grad;
         return;
     }
-    float xn = s.mu * (s.alpha * x[idx] + s.rho * (v[idx] - u[idx]) - grad);
-    xn = fminf(fmaxf(xn, s.lo), s.hi);
-    x[idx] = xn;
-    z[idx] = xn + u[idx];
+    xstep_store(grad, x, v, u, x, z, idx, s);
+}
+
+// The x-step of the 9-tap, factor-2 operator with mirrored boundary (the
+// super-resolution setting of Section 4.1) in one launch.  A block owns a
+// TH x TW tile of the high-resolution grid.  The low-resolution samples that
+// the adjoint at the tile's pixels reads, mirrored copies included, form a
+// window [Ilo, Ihi] x [Jlo, Jhi] of the grid: a pixel i reads samples
+// (i + R) / F - t (t < NS) or, within R of an edge, samples next to that same
+// edge, which lie in the tile's own window for a mirrored boundary (a periodic
+// one would reach the opposite edge).  The block stages the rows of x those
+// samples cover, forms r = A x - y on the window in LDS with the additions of
+// k_sr_forward (each row's taps first, then across rows), and finishes as
+// k_sr_adjoint_step, reading r from LDS; the results equal the two-kernel
+// form's bit for bit.  x is read and xo written: they must not alias, since
+// every block reads x beyond its own tile.
+template <int TH, int TW>
+struct XsGeo {
+    static constexpr int BS = 9, F = 2, R = 4, NS = 5;
+    // samples per window side: the tile's pixels reach ceil((n - 1) / F) + 1
+    // distinct values of (i + R) / F, each with NS - 1 more below it
+    static constexpr int NI = (TH - 1 + F - 1) / F + NS;
+    static constexpr int NJ = (TW - 1 + F - 1) / F + NS;
+    static constexpr int XR = F * (NI - 1) + BS;  // staged rows and columns of x
+    static constexpr int XC = F * (NJ - 1) + BS;
+};
+constexpr int kXsTH = 8, kXsTW = 64, kXsThreads = 512;
+
+template <int TH, int TW>
+__global__ void __launch_bounds__(kXsThreads)
+k_sr_step_tile(const float* __restrict__ x, const float* __restrict__ y, float* __restrict__ xo,
+               const float* __restrict__ v, const float* __restrict__ u, float* __restrict__ z, SRGeom g,
+               Taps taps, StepScalars s) {
+    using G = XsGeo<TH, TW>;
+    constexpr int BS = G::BS, F = G::F, R = G::R, NS = G::NS, NT = kXsThreads;
+    constexpr int XN = G::XR * G::XC, HN = G::XR * G::NJ, RN = G::NI * G::NJ, PN = TH * TW;
+    constexpr int KX = (XN + NT - 1) / NT, KH = (HN + NT - 1) / NT, KR = (RN + NT - 1) / NT, KP = PN / NT;
+    static_assert(PN % NT == 0, "whole pixels per thread");
+    __shared__ float X[XN];
+    __shared__ float H[HN];
+    __shared__ float Rw[RN];
+    const int tid = threadIdx.x;
+    const int i0 = blockIdx.y * TH, j0 = blockIdx.x * TW;
+    const int imax = min(i0 + TH, g.n1) - 1, jmax = min(j0 + TW, g.n2) - 1;
+    const int Ilo = max(0, (i0 + R) / F - (NS - 1)), Ihi = min(g.m1 - 1, (imax + R) / F);
+    const int Jlo = max(0, (j0 + R) / F - (NS - 1)), Jhi = min(g.m2 - 1, (jmax + R) / F);
+    const int ni = Ihi - Ilo + 1, nj = Jhi - Jlo + 1;
+    const int xr = F * (ni - 1) + BS, xc = F * (nj - 1) + BS;
+    const int pr0 = F * Ilo - R, pc0 = F * Jlo - R;  // padded position of the first staged row and column
+    // every global load is issued before the first wait: the pixels' x, v, u,
+    // the sample's y and the staged rows of x (their latency overlaps)
+    float xv[KP], vv[KP], uv[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        const int e = tid + k * NT, i = i0 + e / TW, j = j0 + e % TW;
+        const bool in = i <= imax && j <= jmax;
+        const size_t idx = in ? (size_t)i * g.n2 + j : 0;
+        xv[k] = x[idx];
+        vv[k] = v[idx];
+        uv[k] = u[idx];
+    }
+    float yv[KR];
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+        const int e = tid + k * NT, t = e / G::NJ, q = e % G::NJ;
+        yv[k] = e < RN && t < ni && q < nj ? y[(size_t)(Ilo + t) * g.m2 + Jlo + q] : 0.f;
+    }
+    float xs[KX];
+#pragma unroll
+    for (int k = 0; k < KX; ++k) {
+        const int e = tid + k * NT, a = e / G::XC, b = e % G::XC;
+        xs[k] = e < XN && a < xr && b < xc
+                    ? x[(size_t)src_index<0>(pr0 + a, g.n1) * g.n2 + src_index<0>(pc0 + b, g.n2)]
+                    : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < KX; ++k)
+        if (tid + k * NT < XN) X[tid + k * NT] = xs[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KH; ++k) {
+        const int e = tid + k * NT, a = e / G::NJ, q = e % G::NJ;
+        if (e < HN && a < xr && q < nj) {
+            const float* row = X + a * G::XC + F * q;
+            float ra = 0.f;
+#pragma unroll
+            for (int b = 0; b < BS; ++b) ra = fmaf(taps.t[b], row[b], ra);
+            H[e] = ra;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+        const int e = tid + k * NT, t = e / G::NJ, q = e % G::NJ;
+        if (e < RN && t < ni && q < nj) {
+            const float* col = H + F * t * G::NJ + q;
+            float acc = 0.f;
+#pragma unroll
+            for (int a = 0; a < BS; ++a) acc = fmaf(taps.t[a], col[a * G::NJ], acc);
+            Rw[e] = acc - yv[k];
+        }
+    }
+    __syncthreads();
+    const RLds rd{Rw, G::NJ, Ilo, Jlo};
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        const int e = tid + k * NT, i = i0 + e / TW, j = j0 + e % TW;
+        if (i > imax || j > jmax) continue;
+        const float grad = i >= R && i < g.n1 - R && j >= R && j < g.n2 - R
+                               ? sr_adjoint_interior<BS, F>(rd, i, j, taps)
+                               : sr_adjoint_at<0, BS, F>(rd, i, j, g, taps);
+        const size_t idx = (size_t)i * g.n2 + j;
+        const float xn = xstep_value(grad, xv[k], vv[k], uv[k], s);
+        xo[idx] = xn;
+        z[idx] = xn + uv[k];
+    }
 }
 
 // Launch the forward blur/decimation (r = A x - y) and the adjoint step on
@@ -286,6 +423,17 @@ void launch_sr_adjoint(const SRGeom& g, const Taps& taps, int boundary, const fl
         if (fixed) hipLaunchKernelGGL((k_sr_adjoint_step<1, 9, 2>), grid, dim3(256), 0, st, r, x, v, u, z, g, taps, s, step);
         else hipLaunchKernelGGL((k_sr_adjoint_step<1, 0, 0>), grid, dim3(256), 0, st, r, x, v, u, z, g, taps, s, step);
     }
+}
+
+// The operator takes the one-launch x-step (k_sr_step_tile).
+bool sr_step_fusable(const ladmm_operator* op, const SRGeom& g) {
+    return op->kind == LADMM_OP_SR && op->boundary == 0 && g.bs == 9 && g.f == 2;
+}
+
+void launch_sr_step_tile(const SRGeom& g, const Taps& taps, const float* x, const float* y, float* xo,
+                         const float* v, const float* u, float* z, const StepScalars& s, hipStream_t st) {
+    const dim3 grid((g.n2 + kXsTW - 1) / kXsTW, (g.n1 + kXsTH - 1) / kXsTH);
+    hipLaunchKernelGGL((k_sr_step_tile<kXsTH, kXsTW>), grid, dim3(kXsThreads), 0, st, x, y, xo, v, u, z, g, taps, s);
 }
 
 struct SPIScalars {
@@ -627,29 +775,35 @@ int enqueue_residuals(const float* partials, int n1, int n2, int iters, float rh
     return check_hip(hipGetLastError(), "residual reduction");
 }
 
-// Enqueue iteration k of Algorithm 1.  lr: scratch for the low-resolution
-// residual (SR); partials: this iteration's slot of residual partials (written
-// when want_res); ckpt: device [4][n] or null.
+// Enqueue iteration k of Algorithm 1.  The x-step reads x and writes xo: the
+// same buffer (in place, two launches for the super-resolution operator) or,
+// for an operator with sr_step_fusable, another one (one launch).  The rest of
+// the iteration works on xo.  lr: scratch for the low-resolution residual
+// (SR); partials: this iteration's slot of residual partials (written when
+// want_res); ckpt: device [4][n] or null.
 int enqueue_step(const ladmm_operator* op, const OpView& ov, const ladmm_params* p, float h, int k,
-                 dsnlm_weights* w, float* x, float* v, float* u, float* lr, float* partials,
+                 dsnlm_weights* w, const float* x, float* xo, float* v, float* u, float* lr, float* partials,
                  bool want_res, float* ckpt, hipStream_t st) {
     (void)h;
     const int n = op->n1 * op->n2;
     const float alpha = 1.0f / p->gamma;
     StepScalars s{alpha, p->rho, 1.0f / (alpha + p->rho), p->lo, p->hi};
     float* z = w->zbuf;
+    if (xo != x && !sr_step_fusable(op, ov.g)) return fail(DSNLM_EINVAL, "x-step: out of place for this operator");
     {
         ProfScope prof(DSNLM_K_LADMM, st);
-        if (op->kind == LADMM_OP_SR) {
+        if (xo != x) {
+            launch_sr_step_tile(ov.g, ov.taps, x, op->y, xo, v, u, z, s, st);
+        } else if (op->kind == LADMM_OP_SR) {
             launch_sr_forward(ov.g, ov.taps, op->boundary, x, op->y, lr, st);
-            launch_sr_adjoint(ov.g, ov.taps, op->boundary, lr, x, v, u, z, s, 1, st);
+            launch_sr_adjoint(ov.g, ov.taps, op->boundary, lr, xo, v, u, z, s, 1, st);
         } else {
-            hipLaunchKernelGGL(k_spi_step, dim3(blocks(n)), dim3(256), 0, st, x, v, u, z, op->ones, n, ov.q, s, 1);
+            hipLaunchKernelGGL(k_spi_step, dim3(blocks(n)), dim3(256), 0, st, xo, v, u, z, op->ones, n, ov.q, s, 1);
         }
         int rc = check_hip(hipGetLastError(), "x-step");
         if (rc) return rc;
     }
-    return enqueue_denoise_dual(p, k, w, x, v, u, partials, want_res, ckpt, st);
+    return enqueue_denoise_dual(p, k, w, xo, v, u, partials, want_res, ckpt, st);
 }
 
 // ---- standard plug-and-play ADMM with a conjugate-gradient inversion (the
@@ -764,13 +918,16 @@ void enqueue_AtA(const ladmm_operator* op, const OpView& ov, const float* x, flo
     launch_sr_adjoint(ov.g, ov.taps, op->boundary, lr, out, nullptr, nullptr, nullptr, s, 0, st);
 }
 
-// Solver scratch layout inside the handle: [z: n][lr: m][partials: slots x
-// partial_stride] (one slot of residual partials per iteration of a solve).
+// Solver scratch layout inside the handle: [z: n][lr: m][xt: n][partials:
+// slots x partial_stride] (one slot of residual partials per iteration of a
+// solve; lr and xt for the super-resolution operator only, xt being the
+// second x buffer of the one-launch x-step).
 int ensure_solver_scratch(dsnlm_weights* w, const OpView& ov, const ladmm_operator* op, int slots, float** lr,
-                          float** partials) {
+                          float** partials, float** xt = nullptr) {
     const size_t n = (size_t)op->n1 * op->n2;
-    const size_t mlr = op->kind == LADMM_OP_SR ? (size_t)ov.g.m1 * ov.g.m2 : 0;
-    const size_t lead = (n + mlr + 63) & ~(size_t)63;
+    const bool sr = op->kind == LADMM_OP_SR;
+    const size_t mlr = sr ? (size_t)ov.g.m1 * ov.g.m2 : 0;
+    const size_t lead = (n + mlr + (sr ? n : 0) + 63) & ~(size_t)63;
     const size_t need = lead + (size_t)(slots < 1 ? 1 : slots) * partial_stride(op->n1, op->n2) + 64;
     int rc;
     float* base = scratch_floats(w, need, &rc);
@@ -778,6 +935,7 @@ int ensure_solver_scratch(dsnlm_weights* w, const OpView& ov, const ladmm_operat
     w->zbuf = base;
     *lr = base + n;
     *partials = base + lead;
+    if (xt) *xt = sr ? base + n + mlr : nullptr;
     return DSNLM_OK;
 }
 
@@ -791,13 +949,21 @@ int ensure_solver_scratch(dsnlm_weights* w, const OpView& ov, const ladmm_operat
 // Every iteration of a solve on stream st (ckpt/res: per-iteration slices).
 int enqueue_solve(const ladmm_operator* op, const OpView& ov, const ladmm_params* p, float h, dsnlm_weights* w,
                   float* x, float* v, float* u, float* residuals, float* checkpoints, hipStream_t st) {
-    float *lr, *partials;
-    int rc = ensure_solver_scratch(w, ov, op, residuals ? p->iters : 1, &lr, &partials);
+    float *lr, *partials, *xt;
+    int rc = ensure_solver_scratch(w, ov, op, residuals ? p->iters : 1, &lr, &partials, &xt);
     const size_t n = (size_t)op->n1 * op->n2;
     const size_t stride = partial_stride(op->n1, op->n2);
-    for (int k = 1; k <= p->iters && !rc; ++k)
-        rc = enqueue_step(op, ov, p, h, k, w, x, v, u, lr, partials + (residuals ? (k - 1) * stride : 0),
+    // With the one-launch x-step, x alternates between the state buffer and
+    // xt; an odd count takes its first step in place, so the last lands in x.
+    const bool alt = sr_step_fusable(op, ov.g);
+    float* cur = x;
+    for (int k = 1; k <= p->iters && !rc; ++k) {
+        float* next = cur;
+        if (alt && (k > 1 || p->iters % 2 == 0)) next = cur == x ? xt : x;
+        rc = enqueue_step(op, ov, p, h, k, w, cur, next, v, u, lr, partials + (residuals ? (k - 1) * stride : 0),
                           residuals != nullptr, checkpoints ? checkpoints + 4 * n * (size_t)(k - 1) : nullptr, st);
+        cur = next;
+    }
     // every iteration's residual norms in one fixed-order reduction at the end
     if (!rc && residuals) rc = enqueue_residuals(partials, op->n1, op->n2, p->iters, p->rho, residuals, st);
     return rc;
@@ -973,7 +1139,7 @@ int ladmm_step(const ladmm_operator* op, const ladmm_params* p, int k, dsnlm_wei
     float *lr, *partials;
     rc = ensure_solver_scratch(*w, ov, op, 1, &lr, &partials);
     if (rc) return rc;
-    return enqueue_step(op, ov, p, h, k, *w, x, v, u, lr, partials, false, nullptr,
+    return enqueue_step(op, ov, p, h, k, *w, x, x, v, u, lr, partials, false, nullptr,
                         static_cast<hipStream_t>(stream));
 }
 

@@ -177,6 +177,31 @@ def test_solve_equals_steps_and_checkpoints():
         M.ladmm_step(op, prm2, iters + 1, w, x2, v2, u2)
 
 
+@pytest.mark.parametrize("n1,n2,iters", [(33, 29, 4), (37, 130, 3), (70, 64, 2), (9, 11, 2), (16, 65, 5), (512, 512, 2)])
+def test_solve_one_launch_xstep_equals_two_launch_steps(n1, n2, iters):
+    """The solve's one-launch x-step for the 9-tap, factor-2 mirrored operator
+    (tiles of 8 x 64 with their own residual window in LDS, x alternating
+    between two buffers) gives the same bits as the in-place two-launch step
+    of ladmm_step, on shapes with ragged tiles, odd sizes, a single tile and
+    odd and even iteration counts."""
+    M = _M()
+    print(f"one-launch x-step {n1}x{n2} iters={iters}", flush=True)
+    rng = np.random.default_rng(n1 * 131 + n2)
+    y = rng.uniform(0, 1, ((n1 + 1) // 2, (n2 + 1) // 2)).astype(np.float32)
+    x0 = rng.uniform(0, 1, (n1, n2)).astype(np.float32)
+    op = _sr_op(M, n1, n2, y=_t(y))
+    prm = M.LadmmParams(lam=1e-2, rho=1.0, gamma=1.0 / 0.3321609, S=3, P=1, h=0.2,
+                        freeze_after=1, iters=iters)
+    x1, v1, u1 = _t(x0), _t(x0), torch.zeros((n1, n2), device="cuda")
+    M.ladmm_solve(op, prm, x1, v1, u1)
+    x2, v2, u2 = _t(x0), _t(x0), torch.zeros((n1, n2), device="cuda")
+    w = None
+    for k in range(1, iters + 1):
+        w = M.ladmm_step(op, prm, k, w, x2, v2, u2)
+    torch.cuda.synchronize()
+    assert torch.equal(x1, x2) and torch.equal(v1, v2) and torch.equal(u1, u2)
+
+
 def test_frozen_weights_converge_to_fixed_point():
     """16x16 super-resolution with weights frozen after the first iteration
     and an inactive box: the iterates reach the solution of
