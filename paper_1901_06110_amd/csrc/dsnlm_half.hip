@@ -465,14 +465,20 @@ __device__ __forceinline__ unsigned long long wave_max_u64_h(unsigned long long 
     return v;
 }
 
+// Threads of a gather block: 256 for a batch tile (32 x 64 pixels), 512 for a
+// quarter tile of a single image (8 x 64 pixels, one per thread, so that no
+// thread waits on a second pixel's loads).
+constexpr int gather_threads(bool batch) { return batch ? 256 : 512; }
+
 // One block per s-tile: every pixel of the tile sums the partial regions of
 // the tiles covering it (own, left, right, above, above-left, above-right),
 // adds the d = 0 term and finishes the pass.
 template <int MODE, bool BATCH>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 k_half_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict__ tiles, int S,
               int ngrp) {
     constexpr int TH = 32, TW = 64;
+    constexpr int NT = gather_threads(BATCH), NW = NT / 64;
     constexpr int NP = half_np(MODE);
     ImgDesc d;
     int ti0, tj0;
@@ -499,7 +505,7 @@ k_half_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __r
     float m = 1.f;
     if constexpr (MODE == kApply) m = __uint_as_float((unsigned)(*d.key >> 32));  // the built weights' m
     float rp = 0.f, rd = 0.f;  // fused dual half: residual sums of this thread
-    for (int e = threadIdx.x; e < rows * TW; e += 256) {
+    for (int e = threadIdx.x; e < rows * TW; e += NT) {
         const int li = li0 + e / TW, lj = e % TW;
         const int gi = ti0 + li, gj = tj0 + lj;
         if (gi >= n1 || gj >= n2) continue;
@@ -595,7 +601,7 @@ k_half_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __r
     if constexpr (MODE == kApply) {
         if (d.lres) {
             // fixed-order block sums of the residual terms (wave, then block)
-            __shared__ float wsum[2][4];
+            __shared__ float wsum[2][NW];
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) {
                 rp += __shfl_xor(rp, off, 64);
@@ -608,21 +614,28 @@ k_half_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __r
             __syncthreads();
             if (threadIdx.x == 0) {
                 const int b = ((int)blockIdx.z * (int)gridDim.y + (int)blockIdx.y) * (int)gridDim.x + (int)blockIdx.x;
-                d.lres[2 * b] = (wsum[0][0] + wsum[0][1]) + (wsum[0][2] + wsum[0][3]);
-                d.lres[2 * b + 1] = (wsum[1][0] + wsum[1][1]) + (wsum[1][2] + wsum[1][3]);
+                float r2[2];
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    r2[c] = (wsum[c][0] + wsum[c][1]) + (wsum[c][2] + wsum[c][3]);
+                    if constexpr (NW == 8)
+                        r2[c] = r2[c] + ((wsum[c][4] + wsum[c][5]) + (wsum[c][6] + wsum[c][7]));
+                }
+                d.lres[2 * b] = r2[0];
+                d.lres[2 * b + 1] = r2[1];
             }
         }
     }
     if constexpr (MODE == kPassBApply || MODE == kPassBBuild) {
         // one atomic per block: wave maxima, then the block's in LDS
-        __shared__ unsigned long long wmax[4];
+        __shared__ unsigned long long wmax[NW];
         best = wave_max_u64_h(best);
         if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = best;
         __syncthreads();
         if (threadIdx.x == 0) {
             unsigned long long b = wmax[0];
 #pragma unroll
-            for (int w = 1; w < 4; ++w) b = wmax[w] > b ? wmax[w] : b;
+            for (int w = 1; w < NW; ++w) b = wmax[w] > b ? wmax[w] : b;
             if (b != 0ull) atomicMax(d.key, b);
         }
     }
@@ -691,7 +704,8 @@ hipError_t launch_half_one(int S, const ImgDesc& one, const ImgDesc* batch, cons
     }
     ProfScope prof(DSNLM_K_HALF_AUX, st);
     const dim3 ggrid(grid.x, grid.y, BATCH ? 1 : kGatherSplit);
-    hipLaunchKernelGGL((k_half_gather<MODE, BATCH>), ggrid, dim3(256), 0, st, one, batch, tiles, S, ngrp);
+    hipLaunchKernelGGL((k_half_gather<MODE, BATCH>), ggrid, dim3(gather_threads(BATCH)), 0, st, one, batch, tiles,
+                       S, ngrp);
     return hipGetLastError();
 }
 

@@ -470,11 +470,14 @@ k_spi_step(float* __restrict__ x, const float* __restrict__ v, const float* __re
     z[idx] = xn + u[idx];
 }
 
+// Threads of an epilogue block: one per pixel of its 8 x 64 rows.
+constexpr int kEpilogueThreads = 512;
+
 // v_new = z + B'/m (denoiser output); u <- u + x - v_new; v <- v_new; per-block
 // partial sums of (x - v_new)^2 and (v_new - v_old)^2.  The blocks follow the
 // single-image gather's geometry (a 32 x 64 tile's rows split over gridDim.z
 // blocks), so both leave the same number of partials per iteration.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kEpilogueThreads)
 k_ladmm_epilogue(const float* __restrict__ z, const float* __restrict__ bp,
                  const unsigned long long* __restrict__ key, const float* __restrict__ x,
                  float* __restrict__ v, float* __restrict__ u, int n1, int n2, float* __restrict__ partials) {
@@ -483,7 +486,7 @@ k_ladmm_epilogue(const float* __restrict__ z, const float* __restrict__ bp,
     const int rows = TH / (int)gridDim.z;
     const int i0 = (int)blockIdx.y * TH + (int)blockIdx.z * rows, j0 = (int)blockIdx.x * TW;
     float p = 0.f, d = 0.f;
-    for (int e = threadIdx.x; e < rows * TW; e += 256) {
+    for (int e = threadIdx.x; e < rows * TW; e += kEpilogueThreads) {
         const int gi = i0 + e / TW, gj = j0 + e % TW;
         if (gi >= n1 || gj >= n2) continue;
         const size_t idx = (size_t)gi * n2 + gj;
@@ -496,7 +499,9 @@ k_ladmm_epilogue(const float* __restrict__ z, const float* __restrict__ bp,
         d = fmaf(vn - vo, vn - vo, d);
     }
     if (!partials) return;
-    __shared__ float wsum[2][4];
+    constexpr int NW = kEpilogueThreads / 64;
+    static_assert(NW == 8, "the fixed-order block sum below adds eight wave sums");
+    __shared__ float wsum[2][NW];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         p += __shfl_xor(p, off, 64);
@@ -509,8 +514,10 @@ k_ladmm_epilogue(const float* __restrict__ z, const float* __restrict__ bp,
     __syncthreads();
     if (threadIdx.x == 0) {
         const int b = ((int)blockIdx.z * (int)gridDim.y + (int)blockIdx.y) * (int)gridDim.x + (int)blockIdx.x;
-        partials[2 * b] = (wsum[0][0] + wsum[0][1]) + (wsum[0][2] + wsum[0][3]);
-        partials[2 * b + 1] = (wsum[1][0] + wsum[1][1]) + (wsum[1][2] + wsum[1][3]);
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+            partials[2 * b + c] = ((wsum[c][0] + wsum[c][1]) + (wsum[c][2] + wsum[c][3])) +
+                                  ((wsum[c][4] + wsum[c][5]) + (wsum[c][6] + wsum[c][7]));
     }
 }
 
@@ -750,7 +757,7 @@ int enqueue_denoise_dual(const ladmm_params* p, int k, dsnlm_weights* w, float* 
     if (!fused) {
         ProfScope prof(DSNLM_K_LADMM, st);
         const dim3 grid((w->n2 + 63) / 64, (w->n1 + 31) / 32, kGatherSplit);
-        hipLaunchKernelGGL(k_ladmm_epilogue, grid, dim3(256), 0, st, z, w->bp, w->key, x, v, u, w->n1, w->n2,
+        hipLaunchKernelGGL(k_ladmm_epilogue, grid, dim3(kEpilogueThreads), 0, st, z, w->bp, w->key, x, v, u, w->n1, w->n2,
                            want_res ? partials : nullptr);
         rc = check_hip(hipGetLastError(), "dual update");
         if (rc) return rc;
