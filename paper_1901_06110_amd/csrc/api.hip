@@ -71,6 +71,10 @@ ImgDesc base_desc(const dsnlm_weights* w) {
     }
     d.n1 = w->n1;
     d.n2 = w->n2;
+    // builds that run on the half-window path store pass B's sum of a c for
+    // the apply, which then need not form it again (it is fixed with the
+    // weights); both build modes must take that path for the apply to rely on it
+    if (sweep_takes_half(kPassBApply, w->S, w->P, d) && sweep_takes_half(kPassBBuild, w->S, w->P, d)) d.s0 = w->s0;
     const double np = 2.0 * w->P + 1.0;
     const double kappa = 1.0 / (2.0 * np * np * (double)w->h * (double)w->h);
     d.kappa = (float)kappa;
@@ -94,6 +98,7 @@ int prepare_handle(int n1, int n2, int S, int P, float h, dsnlm_weights** out) {
         hipError_t e = hipMalloc(&w->guide, n * sizeof(float));
         if (e == hipSuccess) e = hipMalloc(&w->c, n * sizeof(float));
         if (e == hipSuccess) e = hipMalloc(&w->delta, n * sizeof(float));
+        if (e == hipSuccess) e = hipMalloc(&w->s0, n * sizeof(float));
         if (e == hipSuccess) e = hipMalloc(&w->bp, n * sizeof(float));
         if (e == hipSuccess) e = hipMalloc(&w->key, sizeof(unsigned long long));
         if (e != hipSuccess) {
@@ -142,6 +147,7 @@ void dsnlm_weights_destroy(dsnlm_weights* w) {
     (void)hipFree(w->guide);
     (void)hipFree(w->c);
     (void)hipFree(w->delta);
+    (void)hipFree(w->s0);
     (void)hipFree(w->bp);
     (void)hipFree(w->key);
     (void)hipFree(w->scratch);

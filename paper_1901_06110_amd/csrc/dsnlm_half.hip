@@ -51,11 +51,13 @@ struct HGeo {
     static_assert(NITEM1 <= NT, "one phase-1 item per thread");
 };
 
-// floats per partner-region entry in LDS: the sum of a (pass A), or the
+// floats per partner-region entry in LDS: the sum of a (pass A); the partner
+// factor c x and the sum of a c x (the apply of built weights, whose sum of
+// a c is fixed with the weights: the gather takes it as delta / c); or the
 // partner factors and the two factor-weighted sums (the others)
-constexpr int half_nc(int mode) { return mode == kPassA ? 1 : 4; }
+constexpr int half_nc(int mode) { return mode == kPassA ? 1 : mode == kApply ? 2 : 4; }
 // channels of the partial buffer
-constexpr int half_np(int mode) { return mode == kPassA ? 1 : 2; }
+constexpr int half_np(int mode) { return mode == kPassA || mode == kApply ? 1 : 2; }
 
 template <int P, int S_CLASS>
 size_t half_lds_floats(int S, int mode) {
@@ -217,7 +219,10 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
             if (slot[it] >= 0) {
                 float2 f = fv[it];
                 if constexpr (MODE == kPassBApply || MODE == kApply) f.y = f.x * f.y;
-                reinterpret_cast<float4*>(Acc)[slot[it]] = make_float4(f.x, f.y, 0.f, 0.f);
+                if constexpr (NC == 2)
+                    reinterpret_cast<float2*>(Acc)[slot[it]] = make_float2(f.y, 0.f);
+                else
+                    reinterpret_cast<float4*>(Acc)[slot[it]] = make_float4(f.x, f.y, 0.f, 0.f);
             }
         }
     }
@@ -266,6 +271,9 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
             const float4 v = reinterpret_cast<const float4*>(Acc)[own + k];
             f0[k] = v.x;
             f1[k] = v.y;
+        } else if constexpr (NC == 2) {
+            f0[k] = 0.f;
+            f1[k] = reinterpret_cast<const float2*>(Acc)[own + k].x;
         } else {
             f0[k] = 0.f;
             f1[k] = 0.f;
@@ -378,9 +386,13 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
                     // of one shift are distinct across the block)
                     const int pr = own + dy * AW + dx;  // partner entry of output 0
                     float4 pv[NC == 4 ? L : 1];
+                    float2 pv2[NC == 2 ? L : 1];
                     if constexpr (NC == 4) {
 #pragma unroll
                         for (int k = 0; k < L; ++k) pv[k] = reinterpret_cast<const float4*>(Acc)[pr + k];
+                    } else if constexpr (NC == 2) {
+#pragma unroll
+                        for (int k = 0; k < L; ++k) pv2[k] = reinterpret_cast<const float2*>(Acc)[pr + k];
                     }
                     __builtin_amdgcn_s_setprio(0);
                     float hs = vv[0];
@@ -410,6 +422,12 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
                             acc0[k] += a[k];
                             Acc[pr + k] += a[k];
                         }
+                    } else if constexpr (NC == 2) {
+#pragma unroll
+                        for (int k = 0; k < L; ++k) {
+                            acc1[k] = fmaf(a[k], pv2[k].x, acc1[k]);
+                            Acc[2 * (pr + k) + 1] = fmaf(a[k], f1[k], pv2[k].y);
+                        }
                     } else {
 #pragma unroll
                         for (int k = 0; k < L; ++k) {
@@ -433,6 +451,8 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
     for (int k = 0; k < L; ++k) {
         if constexpr (NC == 1) {
             Acc[own + k] += acc0[k];
+        } else if constexpr (NC == 2) {
+            Acc[2 * (own + k) + 1] += acc1[k];
         } else {
             float2* e = reinterpret_cast<float2*>(reinterpret_cast<float4*>(Acc) + own + k) + 1;
             const float2 v = *e;
@@ -449,6 +469,8 @@ k_half(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __restrict
         const int r = idx / AWr, q = idx - r * AWr;
         if constexpr (NC == 1) {
             part[idx] = Acc[r * AW + q];
+        } else if constexpr (NC == 2) {
+            part[idx] = Acc[2 * (r * AW + q) + 1];
         } else {
             const float4 v = reinterpret_cast<const float4*>(Acc)[r * AW + q];
             reinterpret_cast<float2*>(part)[idx] = make_float2(v.z, v.w);
@@ -570,7 +592,17 @@ k_half_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __r
             if (d.y) d.y[p] = xs + inc;
         } else {
             const float cs = d.c[p];
-            s0 += cs;  // d = 0: a = 1, partner factor c_s
+            if constexpr (MODE == kApply) {
+                // the one channel is sum_r a c_r x_r; sum_r a c_r (d = 0
+                // included) is fixed with the weights: pass B's own sum, or
+                // delta / c where the build kept none
+                s1 = s0;
+                s0 = d.s0 ? d.s0[p] : d.delta[p] / cs;
+            } else {
+                s0 += cs;  // d = 0: a = 1, partner factor c_s
+                if constexpr (!BATCH && (MODE == kPassBApply || MODE == kPassBBuild))
+                    if (d.s0) d.s0[p] = s0;
+            }
             if constexpr (MODE == kPassBApply || MODE == kApply) {
                 const float xs = d.x[p];
                 s1 += cs * xs;

@@ -32,6 +32,8 @@ struct ImgDesc {
     float* y;              // output of the epilogue
     float* c;              // c_s = omega_s^(-1/2)
     float* delta;          // delta_s = c_s sum_r a c_r
+    float* s0;             // sum_r a c_r (d = 0 included) of the last build, kept for the
+                           // half-window apply (single image; null: it takes delta / c)
     float* bp;             // B'_s = c_s sum_r a c_r (x_r - x_s)
     unsigned long long* key;  // packed (bits(m) << 32) | (~argmax)
     // backward
@@ -234,6 +236,7 @@ struct dsnlm_weights {
     float* guide;      // copy of the guide
     float* c;
     float* delta;
+    float* s0;         // pass B's sum_r a c_r (half-window builds of a single image)
     float* bp;
     unsigned long long* key;
     float* scratch;    // solver scratch (grow-only), freed with the handle

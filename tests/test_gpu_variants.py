@@ -68,3 +68,27 @@ def test_every_schedule_matches_oracle(pin, variant, n1, n2, S, P, h):
         ref = (Wd @ ybar.ravel()).reshape(n1, n2)
         torch.cuda.synchronize()
         assert np.abs(dx.cpu().numpy() - ref).max() <= 1e-4 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("pass_b_variant", [0, 2])
+def test_half_apply_after_full_window_build(pin, pass_b_variant):
+    """The half-window apply keeps one channel (the sum of a c x) and takes
+    the sum of a c, fixed with the weights, from the build: pass B's own sum
+    when pass B ran on the half window, else delta / c.  With pass B pinned to
+    a full-window schedule and the apply left on the half window, the apply
+    must still give the oracle's result."""
+    from paper_1901_06110_amd import _lib
+    M, _ = pin
+    lib = _lib.get()
+    n1, n2, S, P, h = 70, 131, 10, 3, 0.05
+    set_all = pin[1]
+    set_all(S, P, 3)  # records and restores every kind's entry
+    _lib.check(lib.dsnlm_tune_set(1, S, P, pass_b_variant))
+    print(f"pass B variant {pass_b_variant}, half apply, {n1}x{n2} S={S} P={P}", flush=True)
+    _, z = synth.piecewise_smooth(n1, n2, 710, 0.05)
+    _, x = synth.piecewise_smooth(n1, n2, 810, 0.05)
+    wb = M.dsnlm_build_weights(_t(z), S, P, h)
+    y = M.dsnlm_apply(wb, _t(x))
+    yo = R.dsnlm_shifts(x, z, S, P, h)["y"].numpy()
+    torch.cuda.synchronize()
+    assert np.abs(y.cpu().numpy() - yo).max() <= TOL
