@@ -27,6 +27,7 @@
 #include <cmath>
 
 #include "internal.h"
+#include "sr_step.h"
 
 namespace dsnlm {
 
@@ -527,6 +528,14 @@ k_half_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __r
     float m = 1.f;
     if constexpr (MODE == kApply) m = __uint_as_float((unsigned)(*d.key >> 32));  // the built weights' m
     float rp = 0.f, rd = 0.f;  // fused dual half: residual sums of this thread
+    // the next iteration's x-step (single image, lstep set): its window loads
+    // go out with the partial loads; the thread's one pixel keeps x, v and u
+    using XW = SRWindow<kNextStepRows, TW, NT>;
+    XW xwin;
+    float kx = 0.f, kv = 0.f, ku = 0.f;
+    bool kin = false;
+    if constexpr (MODE == kApply && !BATCH)
+        if (d.lstep) xwin.load(d.lx, d.lstep->y, d.lstep->g, ti0 + li0, tj0, threadIdx.x);
     for (int e = threadIdx.x; e < rows * TW; e += NT) {
         const int li = li0 + e / TW, lj = e % TW;
         const int gi = ti0 + li, gj = tj0 + lj;
@@ -614,8 +623,13 @@ k_half_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __r
                     if (d.lu) {
                         // Algorithm 1, dual half: u <- u + x - v, v <- W z
                         const float xv = d.lx[p], vo = d.lv[p];
-                        d.lu[p] = d.lu[p] + xv - vn;
+                        const float un = d.lu[p] + xv - vn;
+                        d.lu[p] = un;
                         d.lv[p] = vn;
+                        kx = xv;
+                        kv = vn;
+                        ku = un;
+                        kin = true;
                         rp = fmaf(xv - vn, xv - vn, rp);
                         rd = fmaf(vn - vo, vn - vo, rd);
                     }
@@ -655,6 +669,13 @@ k_half_gather(ImgDesc one, const ImgDesc* __restrict__ batch, const TileRef* __r
                 }
                 d.lres[2 * b] = r2[0];
                 d.lres[2 * b + 1] = r2[1];
+            }
+        }
+        if constexpr (!BATCH) {
+            if (d.lstep) {
+                static_assert(BATCH || NT == kNextStepRows * TW, "one pixel per thread");
+                const int e = threadIdx.x;
+                next_xstep(xwin, d.lstep, ti0 + li0 + e / TW, tj0 + e % TW, kin, kx, kv, ku);
             }
         }
     }

@@ -63,11 +63,16 @@ struct ImgDesc {
     float* lv;
     float* lu;
     float* lres;
+    // with lstep also set (the 9-tap, factor-2 mirrored super-resolution
+    // operator), the gather then takes the next iteration's x-step from lx,
+    // lv and lu (sr_step.h)
+    const struct SRStepArgs* lstep;
 };
 
 // A single-image gather (and epilogue) splits each 32 x 64 tile's rows over
 // this many blocks, so that a small image still spreads over the CUs.
 constexpr int kGatherSplit = 4;
+static_assert(32 / kGatherSplit == 8, "the folded next x-step covers 8 rows per gather block");
 inline int gather_blocks(int n1, int n2) { return ((n1 + 31) / 32) * ((n2 + 63) / 64) * kGatherSplit; }
 
 // Per-pixel float4 factors of sweep D are stored with this many zero-cost pad

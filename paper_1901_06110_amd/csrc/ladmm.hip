@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "sr_step.h"
 
 namespace dsnlm {
 
@@ -30,32 +31,7 @@ ImgDesc base_desc(const dsnlm_weights* w);
 
 namespace {
 
-constexpr int kMaxTaps = 31;
 
-struct Taps {
-    float t[kMaxTaps];
-};
-
-struct SRGeom {
-    int n1, n2;   // high-resolution size
-    int m1, m2;   // low-resolution size, ceil(n / factor)
-    int f;        // decimation factor
-    int bs;       // blur size (odd)
-    int R;        // (bs - 1) / 2
-};
-
-// Source index in [0, n) of padded position k (|k| < 2n).
-template <int BOUNDARY>
-__device__ __forceinline__ int src_index(int k, int n) {
-    if (BOUNDARY == 0) {
-        if (k < 0) return -k - 1;
-        if (k >= n) return 2 * n - 1 - k;
-        return k;
-    }
-    if (k < 0) return k + n;
-    if (k >= n) return k - n;
-    return k;
-}
 
 // r = A x - y on the low-resolution grid (y may be null: r = A x).
 // BS > 0 fixes the blur size and F the factor at compile time (the loops
@@ -97,163 +73,6 @@ k_sr_forward(const float* __restrict__ x, const float* __restrict__ y, float* __
     r[idx] = y ? acc - y[idx] : acc;
 }
 
-// The padded positions that map onto pixel i (itself and up to two copies).
-template <int BOUNDARY>
-__device__ __forceinline__ int preimages(int i, int n, int R, int* out) {
-    int c = 0;
-    out[c++] = i;
-    if (BOUNDARY == 0) {
-        if (i <= R - 1) out[c++] = -1 - i;
-        if (i >= n - R) out[c++] = 2 * n - 1 - i;
-    } else {
-        if (i <= R - 1) out[c++] = i + n;
-        if (i >= n - R) out[c++] = i - n;
-    }
-    return c;
-}
-
-// The low-resolution samples I = lo..hi whose blur footprint covers padded
-// position p: 0 <= p - f I + R <= bs - 1, clamped to the grid [0, m).
-__device__ __forceinline__ void footprint(int p, int f, int R, int bs, int m, int* lo, int* hi) {
-    int l = p + R - (bs - 1);
-    l = l <= 0 ? 0 : (l + f - 1) / f;
-    int h = p + R;
-    h = h < 0 ? -1 : h / f;
-    *lo = l;
-    *hi = h > m - 1 ? m - 1 : h;
-}
-
-// (A^T r)(i, j): gather over the low-resolution samples whose footprint covers
-// a preimage of (i, j).  BS > 0: blur size BS and factor F fixed at compile
-// time, with at most ceil(BS / F) samples per axis and preimage (loops
-// unrolled, same order of additions as the general form).
-// Readers of the low-resolution residual r(I, J): the whole grid in global
-// memory, or a block's window of it in LDS.
-struct RGlobal {
-    const float* __restrict__ r;
-    int m2;
-    __device__ float operator()(int I, int J) const { return r[(size_t)I * m2 + J]; }
-};
-struct RLds {
-    const float* r;
-    int stride, I0, J0;
-    __device__ float operator()(int I, int J) const { return r[(I - I0) * stride + (J - J0)]; }
-};
-
-template <int BOUNDARY, int BS, int F, class RD>
-__device__ __forceinline__ float sr_adjoint_at(const RD& rd, int i, int j, const SRGeom& g, const Taps& taps) {
-    constexpr int NS = BS > 0 ? (BS + F - 1) / F : 1;
-    const int f = BS > 0 ? F : g.f, bs = BS > 0 ? BS : g.bs, R = (bs - 1) / 2;
-    int pi[3], pj[3];
-    const int ci = preimages<BOUNDARY>(i, g.n1, R, pi);
-    const int cj = preimages<BOUNDARY>(j, g.n2, R, pj);
-    float acc = 0.f;
-    for (int a = 0; a < ci; ++a) {
-        const int ip = pi[a];
-        int Ilo, Ihi;
-        footprint(ip, f, R, bs, g.m1, &Ilo, &Ihi);
-        if constexpr (BS > 0) {
-#pragma unroll
-            for (int t = 0; t < NS; ++t) {
-                const int I = Ilo + t;
-                if (I <= Ihi) {
-                    const float ta = taps.t[ip - F * I + R];
-                    float rowacc = 0.f;
-                    for (int b = 0; b < cj; ++b) {
-                        const int jp = pj[b];
-                        int Jlo, Jhi;
-                        footprint(jp, F, R, BS, g.m2, &Jlo, &Jhi);
-#pragma unroll
-                        for (int q = 0; q < NS; ++q) {
-                            const int J = Jlo + q;
-                            if (J <= Jhi) rowacc = fmaf(taps.t[jp - F * J + R], rd(I, J), rowacc);
-                        }
-                    }
-                    acc = fmaf(ta, rowacc, acc);
-                }
-            }
-        } else {
-            for (int I = Ilo; I <= Ihi; ++I) {
-                const float ta = taps.t[ip - f * I + R];
-                float rowacc = 0.f;
-                for (int b = 0; b < cj; ++b) {
-                    const int jp = pj[b];
-                    int Jlo, Jhi;
-                    footprint(jp, f, R, bs, g.m2, &Jlo, &Jhi);
-                    for (int J = Jlo; J <= Jhi; ++J) rowacc = fmaf(taps.t[jp - f * J + R], rd(I, J), rowacc);
-                }
-                acc = fmaf(ta, rowacc, acc);
-            }
-        }
-    }
-    return acc;
-}
-
-struct StepScalars {
-    float alpha, rho, mu, lo, hi;
-};
-
-// clip(mu (alpha x + rho (v - u) - grad)): the x-step at one pixel.
-__device__ __forceinline__ float xstep_value(float grad, float x, float v, float u, const StepScalars& s) {
-    const float xn = s.mu * (s.alpha * x + s.rho * (v - u) - grad);
-    return fminf(fmaxf(xn, s.lo), s.hi);
-}
-
-// xo = the x-step and z = xo + u at idx.
-__device__ __forceinline__ void xstep_store(float grad, const float* x, const float* v, const float* u, float* xo,
-                                            float* z, size_t idx, const StepScalars& s) {
-    const float uu = u[idx];
-    const float xn = xstep_value(grad, x[idx], v[idx], uu, s);
-    xo[idx] = xn;
-    z[idx] = xn + uu;
-}
-
-// x <- clip(mu (alpha x + rho (v - u) - A^T r)); z = x + u.
-// With step == 0 it only writes g = A^T r into xo (gradient / adjoint).
-// Tap b[F t + ph] for a per-lane phase ph in [0, F) (0 past the kernel's end):
-// every index is a compile-time constant, so the taps stay in scalar registers.
-template <int BS, int F>
-__device__ __forceinline__ float phase_tap(const Taps& taps, int t, int ph) {
-    float v = taps.t[F * t];
-#pragma unroll
-    for (int e = 1; e < F; ++e)
-        if (ph == e) v = F * t + e < BS ? taps.t[F * t + e] : 0.f;
-    return v;
-}
-
-// (A^T r)(i, j) for a pixel with no mirrored or wrapped copy inside any
-// footprint (R <= i < n1 - R, R <= j < n2 - R): the samples of an axis are
-// I = (i + R) / F - t, t = 0 .. ceil(BS / F) - 1, with tap b[(i + R) % F + F t]
-// (zero where that passes the kernel); they all lie inside the grid.
-template <int BS, int F, class RD>
-__device__ __forceinline__ float sr_adjoint_interior(const RD& rd, int i, int j, const Taps& taps) {
-    constexpr int R = (BS - 1) / 2, NS = (BS + F - 1) / F;
-    const int qi = i + R, qj = j + R;
-    const int phi = qi % F, phj = qj % F;
-    const int I0 = qi / F, J0 = qj / F;
-    float tb[NS];
-#pragma unroll
-    for (int q = 0; q < NS; ++q) tb[q] = phase_tap<BS, F>(taps, q, phj);
-    float rv[NS][NS];
-#pragma unroll
-    for (int t = 0; t < NS; ++t) {
-        const int I = I0 - t > 0 ? I0 - t : 0;  // a zero tap's sample is clamped into the grid
-#pragma unroll
-        for (int q = 0; q < NS; ++q) {
-            const int J = J0 - q > 0 ? J0 - q : 0;
-            rv[t][q] = rd(I, J);
-        }
-    }
-    float acc = 0.f;
-#pragma unroll
-    for (int t = 0; t < NS; ++t) {
-        float rowacc = 0.f;
-#pragma unroll
-        for (int q = 0; q < NS; ++q) rowacc = fmaf(tb[q], rv[t][q], rowacc);
-        acc = fmaf(phase_tap<BS, F>(taps, t, phi), rowacc, acc);
-    }
-    return acc;
-}
 
 template <int BOUNDARY, int BS, int F>
 __global__ void __launch_bounds__(256)
@@ -282,28 +101,10 @@ k_sr_adjoint_step(const float* __restrict__ r, float* __restrict__ x, const floa
 }
 
 // The x-step of the 9-tap, factor-2 operator with mirrored boundary (the
-// super-resolution setting of Section 4.1) in one launch.  A block owns a
-// TH x TW tile of the high-resolution grid.  The low-resolution samples that
-// the adjoint at the tile's pixels reads, mirrored copies included, form a
-// window [Ilo, Ihi] x [Jlo, Jhi] of the grid: a pixel i reads samples
-// (i + R) / F - t (t < NS) or, within R of an edge, samples next to that same
-// edge, which lie in the tile's own window for a mirrored boundary (a periodic
-// one would reach the opposite edge).  The block stages the rows of x those
-// samples cover, forms r = A x - y on the window in LDS with the additions of
-// k_sr_forward (each row's taps first, then across rows), and finishes as
-// k_sr_adjoint_step, reading r from LDS; the results equal the two-kernel
-// form's bit for bit.  x is read and xo written: they must not alias, since
-// every block reads x beyond its own tile.
-template <int TH, int TW>
-struct XsGeo {
-    static constexpr int BS = 9, F = 2, R = 4, NS = 5;
-    // samples per window side: the tile's pixels reach ceil((n - 1) / F) + 1
-    // distinct values of (i + R) / F, each with NS - 1 more below it
-    static constexpr int NI = (TH - 1 + F - 1) / F + NS;
-    static constexpr int NJ = (TW - 1 + F - 1) / F + NS;
-    static constexpr int XR = F * (NI - 1) + BS;  // staged rows and columns of x
-    static constexpr int XC = F * (NJ - 1) + BS;
-};
+// super-resolution setting of Section 4.1) in one launch: one block per
+// kXsTH x kXsTW tile forms r = A x - y on the tile's window in LDS and takes
+// the adjoint, clip and z = x + u from it (SRWindow).  x is read and xo
+// written: they must not alias, since every block reads x beyond its own tile.
 constexpr int kXsTH = 8, kXsTW = 64, kXsThreads = 512;
 
 template <int TH, int TW>
@@ -311,86 +112,34 @@ __global__ void __launch_bounds__(kXsThreads)
 k_sr_step_tile(const float* __restrict__ x, const float* __restrict__ y, float* __restrict__ xo,
                const float* __restrict__ v, const float* __restrict__ u, float* __restrict__ z, SRGeom g,
                Taps taps, StepScalars s) {
-    using G = XsGeo<TH, TW>;
-    constexpr int BS = G::BS, F = G::F, R = G::R, NS = G::NS, NT = kXsThreads;
-    constexpr int XN = G::XR * G::XC, HN = G::XR * G::NJ, RN = G::NI * G::NJ, PN = TH * TW;
-    constexpr int KX = (XN + NT - 1) / NT, KH = (HN + NT - 1) / NT, KR = (RN + NT - 1) / NT, KP = PN / NT;
-    static_assert(PN % NT == 0, "whole pixels per thread");
-    __shared__ float X[XN];
-    __shared__ float H[HN];
-    __shared__ float Rw[RN];
+    using W = SRWindow<TH, TW, kXsThreads>;
+    constexpr int NT = kXsThreads, KP = TH * TW / NT;
+    static_assert(TH * TW % NT == 0, "whole pixels per thread");
+    __shared__ float X[W::XN];
+    __shared__ float H[W::HN];
+    __shared__ float Rw[W::RN];
     const int tid = threadIdx.x;
     const int i0 = blockIdx.y * TH, j0 = blockIdx.x * TW;
-    const int imax = min(i0 + TH, g.n1) - 1, jmax = min(j0 + TW, g.n2) - 1;
-    const int Ilo = max(0, (i0 + R) / F - (NS - 1)), Ihi = min(g.m1 - 1, (imax + R) / F);
-    const int Jlo = max(0, (j0 + R) / F - (NS - 1)), Jhi = min(g.m2 - 1, (jmax + R) / F);
-    const int ni = Ihi - Ilo + 1, nj = Jhi - Jlo + 1;
-    const int xr = F * (ni - 1) + BS, xc = F * (nj - 1) + BS;
-    const int pr0 = F * Ilo - R, pc0 = F * Jlo - R;  // padded position of the first staged row and column
-    // every global load is issued before the first wait: the pixels' x, v, u,
-    // the sample's y and the staged rows of x (their latency overlaps)
+    // every global load is issued before the first wait: the pixels' x, v, u
+    // and the window's x and y (their latency overlaps)
     float xv[KP], vv[KP], uv[KP];
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
         const int e = tid + k * NT, i = i0 + e / TW, j = j0 + e % TW;
-        const bool in = i <= imax && j <= jmax;
-        const size_t idx = in ? (size_t)i * g.n2 + j : 0;
+        const size_t idx = i < g.n1 && j < g.n2 ? (size_t)i * g.n2 + j : 0;
         xv[k] = x[idx];
         vv[k] = v[idx];
         uv[k] = u[idx];
     }
-    float yv[KR];
-#pragma unroll
-    for (int k = 0; k < KR; ++k) {
-        const int e = tid + k * NT, t = e / G::NJ, q = e % G::NJ;
-        yv[k] = e < RN && t < ni && q < nj ? y[(size_t)(Ilo + t) * g.m2 + Jlo + q] : 0.f;
-    }
-    float xs[KX];
-#pragma unroll
-    for (int k = 0; k < KX; ++k) {
-        const int e = tid + k * NT, a = e / G::XC, b = e % G::XC;
-        xs[k] = e < XN && a < xr && b < xc
-                    ? x[(size_t)src_index<0>(pr0 + a, g.n1) * g.n2 + src_index<0>(pc0 + b, g.n2)]
-                    : 0.f;
-    }
-#pragma unroll
-    for (int k = 0; k < KX; ++k)
-        if (tid + k * NT < XN) X[tid + k * NT] = xs[k];
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < KH; ++k) {
-        const int e = tid + k * NT, a = e / G::NJ, q = e % G::NJ;
-        if (e < HN && a < xr && q < nj) {
-            const float* row = X + a * G::XC + F * q;
-            float ra = 0.f;
-#pragma unroll
-            for (int b = 0; b < BS; ++b) ra = fmaf(taps.t[b], row[b], ra);
-            H[e] = ra;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < KR; ++k) {
-        const int e = tid + k * NT, t = e / G::NJ, q = e % G::NJ;
-        if (e < RN && t < ni && q < nj) {
-            const float* col = H + F * t * G::NJ + q;
-            float acc = 0.f;
-#pragma unroll
-            for (int a = 0; a < BS; ++a) acc = fmaf(taps.t[a], col[a * G::NJ], acc);
-            Rw[e] = acc - yv[k];
-        }
-    }
-    __syncthreads();
-    const RLds rd{Rw, G::NJ, Ilo, Jlo};
+    W win;
+    win.load(x, y, g, i0, j0, tid);
+    win.build(X, H, Rw, taps, tid);
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
         const int e = tid + k * NT, i = i0 + e / TW, j = j0 + e % TW;
-        if (i > imax || j > jmax) continue;
-        const float grad = i >= R && i < g.n1 - R && j >= R && j < g.n2 - R
-                               ? sr_adjoint_interior<BS, F>(rd, i, j, taps)
-                               : sr_adjoint_at<0, BS, F>(rd, i, j, g, taps);
+        if (i >= g.n1 || j >= g.n2) continue;
         const size_t idx = (size_t)i * g.n2 + j;
-        const float xn = xstep_value(grad, xv[k], vv[k], uv[k], s);
+        const float xn = xstep_value(win.grad(Rw, i, j, g, taps), xv[k], vv[k], uv[k], s);
         xo[idx] = xn;
         z[idx] = xn + uv[k];
     }
@@ -478,14 +227,21 @@ constexpr int kEpilogueThreads = 512;
 // single-image gather's geometry (a 32 x 64 tile's rows split over gridDim.z
 // blocks), so both leave the same number of partials per iteration.
 __global__ void __launch_bounds__(kEpilogueThreads)
-k_ladmm_epilogue(const float* __restrict__ z, const float* __restrict__ bp,
-                 const unsigned long long* __restrict__ key, const float* __restrict__ x,
-                 float* __restrict__ v, float* __restrict__ u, int n1, int n2, float* __restrict__ partials) {
+k_ladmm_epilogue(const float* z, const float* __restrict__ bp, const unsigned long long* __restrict__ key,
+                 const float* __restrict__ x, float* __restrict__ v, float* __restrict__ u, int n1, int n2,
+                 float* __restrict__ partials, const SRStepArgs* __restrict__ ns) {
     constexpr int TH = 32, TW = 64;
     const float m = __uint_as_float((unsigned)(*key >> 32));
     const int rows = TH / (int)gridDim.z;
     const int i0 = (int)blockIdx.y * TH + (int)blockIdx.z * rows, j0 = (int)blockIdx.x * TW;
+    // with ns set, the block ends with the next iteration's x-step for its
+    // rows (kNextStepRows, one pixel per thread): its window loads go out first
+    using W = SRWindow<kNextStepRows, TW, kEpilogueThreads>;
+    W win;
+    if (ns) win.load(x, ns->y, ns->g, i0, j0, threadIdx.x);
     float p = 0.f, d = 0.f;
+    float kx = 0.f, kv = 0.f, ku = 0.f;  // this thread's pixel (the loop runs once when ns is set)
+    bool kin = false;
     for (int e = threadIdx.x; e < rows * TW; e += kEpilogueThreads) {
         const int gi = i0 + e / TW, gj = j0 + e % TW;
         if (gi >= n1 || gj >= n2) continue;
@@ -493,10 +249,19 @@ k_ladmm_epilogue(const float* __restrict__ z, const float* __restrict__ bp,
         const float vn = z[idx] + bp[idx] / m;
         const float xv = x[idx];
         const float vo = v[idx];
-        u[idx] = u[idx] + xv - vn;
+        const float un = u[idx] + xv - vn;
+        u[idx] = un;
         v[idx] = vn;
         p = fmaf(xv - vn, xv - vn, p);
         d = fmaf(vn - vo, vn - vo, d);
+        kx = xv;
+        kv = vn;
+        ku = un;
+        kin = true;
+    }
+    if (ns) {
+        const int e = threadIdx.x;
+        next_xstep(win, ns, i0 + e / TW, j0 + e % TW, kin, kx, kv, ku);
     }
     if (!partials) return;
     constexpr int NW = kEpilogueThreads / 64;
@@ -722,7 +487,8 @@ size_t partial_stride(int n1, int n2) {
 // A frozen iteration on the half-window path does the dual half inside the
 // apply's gather (m is known), so no separate update kernel runs.
 int enqueue_denoise_dual(const ladmm_params* p, int k, dsnlm_weights* w, float* x, float* v, float* u,
-                         float* partials, bool want_res, float* ckpt, hipStream_t st) {
+                         float* partials, bool want_res, float* ckpt, hipStream_t st,
+                         const SRStepArgs* ns = nullptr) {
     const int n = w->n1 * w->n2;
     float* z = w->zbuf;
     ImgDesc d = base_desc(w);
@@ -750,6 +516,7 @@ int enqueue_denoise_dual(const ladmm_params* p, int k, dsnlm_weights* w, float* 
             d.lv = v;
             d.lu = u;
             d.lres = want_res ? partials : nullptr;
+            d.lstep = ns;
         }
         rc = check_hip(launch_sweep(kApply, p->S, p->P, d, nullptr, nullptr, 0, st), "apply sweep");
     }
@@ -758,7 +525,7 @@ int enqueue_denoise_dual(const ladmm_params* p, int k, dsnlm_weights* w, float* 
         ProfScope prof(DSNLM_K_LADMM, st);
         const dim3 grid((w->n2 + 63) / 64, (w->n1 + 31) / 32, kGatherSplit);
         hipLaunchKernelGGL(k_ladmm_epilogue, grid, dim3(kEpilogueThreads), 0, st, z, w->bp, w->key, x, v, u, w->n1, w->n2,
-                           want_res ? partials : nullptr);
+                           want_res ? partials : nullptr, ns);
         rc = check_hip(hipGetLastError(), "dual update");
         if (rc) return rc;
     }
@@ -785,19 +552,21 @@ int enqueue_residuals(const float* partials, int n1, int n2, int iters, float rh
 // Enqueue iteration k of Algorithm 1.  The x-step reads x and writes xo: the
 // same buffer (in place, two launches for the super-resolution operator) or,
 // for an operator with sr_step_fusable, another one (one launch).  The rest of
-// the iteration works on xo.  lr: scratch for the low-resolution residual
-// (SR); partials: this iteration's slot of residual partials (written when
-// want_res); ckpt: device [4][n] or null.
+// the iteration works on xo.  With stepped set the previous iteration's last
+// kernel has already taken this x-step; with ns set this iteration's last
+// kernel takes the next one (ns: device arguments, reading xo).  lr: scratch
+// for the low-resolution residual (SR); partials: this iteration's slot of
+// residual partials (written when want_res); ckpt: device [4][n] or null.
 int enqueue_step(const ladmm_operator* op, const OpView& ov, const ladmm_params* p, float h, int k,
                  dsnlm_weights* w, const float* x, float* xo, float* v, float* u, float* lr, float* partials,
-                 bool want_res, float* ckpt, hipStream_t st) {
+                 bool want_res, float* ckpt, hipStream_t st, bool stepped = false, const SRStepArgs* ns = nullptr) {
     (void)h;
     const int n = op->n1 * op->n2;
     const float alpha = 1.0f / p->gamma;
     StepScalars s{alpha, p->rho, 1.0f / (alpha + p->rho), p->lo, p->hi};
     float* z = w->zbuf;
     if (xo != x && !sr_step_fusable(op, ov.g)) return fail(DSNLM_EINVAL, "x-step: out of place for this operator");
-    {
+    if (!stepped) {
         ProfScope prof(DSNLM_K_LADMM, st);
         if (xo != x) {
             launch_sr_step_tile(ov.g, ov.taps, x, op->y, xo, v, u, z, s, st);
@@ -810,7 +579,7 @@ int enqueue_step(const ladmm_operator* op, const OpView& ov, const ladmm_params*
         int rc = check_hip(hipGetLastError(), "x-step");
         if (rc) return rc;
     }
-    return enqueue_denoise_dual(p, k, w, xo, v, u, partials, want_res, ckpt, st);
+    return enqueue_denoise_dual(p, k, w, xo, v, u, partials, want_res, ckpt, st, ns);
 }
 
 // ---- standard plug-and-play ADMM with a conjugate-gradient inversion (the
@@ -955,20 +724,29 @@ int ensure_solver_scratch(dsnlm_weights* w, const OpView& ov, const ladmm_operat
 
 // Every iteration of a solve on stream st (ckpt/res: per-iteration slices).
 int enqueue_solve(const ladmm_operator* op, const OpView& ov, const ladmm_params* p, float h, dsnlm_weights* w,
-                  float* x, float* v, float* u, float* residuals, float* checkpoints, hipStream_t st) {
+                  float* x, float* v, float* u, float* residuals, float* checkpoints, hipStream_t st,
+                  const SRStepArgs* chain = nullptr) {
     float *lr, *partials, *xt;
     int rc = ensure_solver_scratch(w, ov, op, residuals ? p->iters : 1, &lr, &partials, &xt);
     const size_t n = (size_t)op->n1 * op->n2;
     const size_t stride = partial_stride(op->n1, op->n2);
     // With the one-launch x-step, x alternates between the state buffer and
     // xt; an odd count takes its first step in place, so the last lands in x.
+    // With chain (device arguments: [0] writes xt, [1] writes x) and no
+    // checkpoints (which keep each iteration's z), every iteration but the
+    // last ends with the next one's x-step.
     const bool alt = sr_step_fusable(op, ov.g);
+    const bool fold = alt && chain && !checkpoints;
     float* cur = x;
+    bool stepped = false;
     for (int k = 1; k <= p->iters && !rc; ++k) {
         float* next = cur;
         if (alt && (k > 1 || p->iters % 2 == 0)) next = cur == x ? xt : x;
+        const SRStepArgs* ns = fold && k < p->iters ? chain + (next == x ? 0 : 1) : nullptr;
         rc = enqueue_step(op, ov, p, h, k, w, cur, next, v, u, lr, partials + (residuals ? (k - 1) * stride : 0),
-                          residuals != nullptr, checkpoints ? checkpoints + 4 * n * (size_t)(k - 1) : nullptr, st);
+                          residuals != nullptr, checkpoints ? checkpoints + 4 * n * (size_t)(k - 1) : nullptr, st,
+                          stepped, ns);
+        stepped = ns != nullptr;
         cur = next;
     }
     // every iteration's residual norms in one fixed-order reduction at the end
@@ -994,6 +772,7 @@ struct SolveEntry {
     float* buf = nullptr;          // x, v, u | observation y or counts | residuals | checkpoints
     float *x, *v, *u, *res, *ckpt;
     const float* y;
+    const SRStepArgs* chain = nullptr;  // device [2]: the folded x-steps' arguments (or null)
     const unsigned char* ones;
     hipGraphExec_t exec = nullptr;  // null: the solve is enqueued step by step
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -1052,9 +831,10 @@ int solve_entry(const SolveKey& key, const ladmm_operator* op, const OpView& ov,
     const size_t nobs = op->kind == LADMM_OP_SR ? (size_t)ov.g.m1 * ov.g.m2 : (n + 3) / 4;  // floats
     const size_t nres = key.want_res ? 2 * (size_t)p->iters : 0;
     const size_t nck = key.want_ckpt ? 4 * n * (size_t)p->iters : 0;
+    const size_t nargs = (2 * sizeof(SRStepArgs) + sizeof(float) - 1) / sizeof(float);
     const size_t r64 = 64;
     auto up = [&](size_t f) { return (f + r64 - 1) / r64 * r64; };
-    rc = check_hip(hipMalloc(&e->buf, (3 * up(n) + up(nobs) + up(nres) + up(nck)) * sizeof(float)),
+    rc = check_hip(hipMalloc(&e->buf, (3 * up(n) + up(nobs) + up(nres) + up(nck) + up(nargs)) * sizeof(float)),
                    "ladmm_solve: state buffers");
     if (rc) {
         delete e;
@@ -1072,8 +852,25 @@ int solve_entry(const SolveKey& key, const ladmm_operator* op, const OpView& ov,
     iop.y = e->y;
     iop.ones = e->ones;
     rc = prepare_handle(op->n1, op->n2, p->S, p->P, h, &e->w);
-    float *lr, *partials;
-    if (!rc) rc = ensure_solver_scratch(e->w, ov, op, key.want_res ? p->iters : 1, &lr, &partials);
+    float *lr, *partials, *xt;
+    if (!rc) rc = ensure_solver_scratch(e->w, ov, op, key.want_res ? p->iters : 1, &lr, &partials, &xt);
+    if (!rc && sr_step_fusable(op, ov.g)) {
+        // the arguments of the x-steps folded into the iterations' last kernels
+        const float alpha = 1.0f / p->gamma;
+        SRStepArgs a[2];
+        std::memset(a, 0, sizeof(a));
+        for (int t = 0; t < 2; ++t) {
+            a[t].g = ov.g;
+            a[t].taps = ov.taps;
+            a[t].s = StepScalars{alpha, p->rho, 1.0f / (alpha + p->rho), p->lo, p->hi};
+            a[t].y = e->y;
+            a[t].xo = t == 0 ? xt : e->x;
+            a[t].z = e->w->zbuf;
+        }
+        SRStepArgs* dev = reinterpret_cast<SRStepArgs*>(obs + up(nobs) + up(nres) + up(nck));
+        rc = check_hip(hipMemcpy(dev, a, sizeof(a), hipMemcpyHostToDevice), "ladmm_solve: step arguments");
+        if (!rc) e->chain = dev;
+    }
     if (!rc) rc = check_hip(prepare_sweeps(p->S, p->P), "sweep attributes");
     if (!rc) rc = check_hip(hipEventCreateWithFlags(&e->ev_in, hipEventDisableTiming), "ladmm_solve: event");
     if (!rc) rc = check_hip(hipEventCreateWithFlags(&e->ev_out, hipEventDisableTiming), "ladmm_solve: event");
@@ -1083,7 +880,7 @@ int solve_entry(const SolveKey& key, const ladmm_operator* op, const OpView& ov,
     }
     hipStream_t is = g_solves.stream[dev];
     if (hipStreamBeginCapture(is, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-        rc = enqueue_solve(&iop, ov, p, h, e->w, e->x, e->v, e->u, e->res, e->ckpt, is);
+        rc = enqueue_solve(&iop, ov, p, h, e->w, e->x, e->v, e->u, e->res, e->ckpt, is, e->chain);
         hipGraph_t graph = nullptr;
         const hipError_t ec = hipStreamEndCapture(is, &graph);
         if (!rc && ec == hipSuccess && graph &&
@@ -1215,7 +1012,7 @@ int ladmm_solve(const ladmm_operator* op, const ladmm_params* p, float* x, float
             ladmm_operator iop = *op;
             iop.y = e->y;
             iop.ones = e->ones;
-            rc = enqueue_solve(&iop, ov, p, h, e->w, e->x, e->v, e->u, e->res, e->ckpt, is);
+            rc = enqueue_solve(&iop, ov, p, h, e->w, e->x, e->v, e->u, e->res, e->ckpt, is, e->chain);
         }
     }
     copy(x, e->x, nb);

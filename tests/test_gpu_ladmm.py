@@ -179,11 +179,12 @@ def test_solve_equals_steps_and_checkpoints():
 
 @pytest.mark.parametrize("n1,n2,iters", [(33, 29, 4), (37, 130, 3), (70, 64, 2), (9, 11, 2), (16, 65, 5), (512, 512, 2)])
 def test_solve_one_launch_xstep_equals_two_launch_steps(n1, n2, iters):
-    """The solve's one-launch x-step for the 9-tap, factor-2 mirrored operator
-    (tiles of 8 x 64 with their own residual window in LDS, x alternating
-    between two buffers) gives the same bits as the in-place two-launch step
-    of ladmm_step, on shapes with ragged tiles, odd sizes, a single tile and
-    odd and even iteration counts."""
+    """The solve's x-steps for the 9-tap, factor-2 mirrored operator (tiles
+    of 8 x 64 with their own residual window in LDS, x alternating between
+    two buffers; after the first iteration each x-step is taken by the
+    previous iteration's last kernel, the gather or the epilogue) give the
+    same bits as the in-place two-launch step of ladmm_step, on shapes with
+    ragged tiles, odd sizes, a single tile and odd and even iteration counts."""
     M = _M()
     print(f"one-launch x-step {n1}x{n2} iters={iters}", flush=True)
     rng = np.random.default_rng(n1 * 131 + n2)
