@@ -262,7 +262,7 @@ int ladmm_step(const ladmm_operator* op, const ladmm_params* p, int k, dsnlm_wei
  * library keeps for that combination -- x, v, u, the observation (y or
  * ones), residuals, checkpoints -- which are copied from the caller's buffers
  * before each replay and back after it (device-to-device copies).  Up to 4
- * combinations are kept, each with its own weights and buffers (about 25 MiB
+ * combinations are kept, each with its own weights and buffers (about 27 MiB
  * at 512 x 512, S = 10, without checkpoints), least recently used dropped
  * first.  The work runs on a library stream of the device that waits for the
  * work already on `stream`, and `stream` waits for it, so ordering is as if it
