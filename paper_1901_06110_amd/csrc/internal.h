@@ -254,4 +254,6 @@ struct dsnlm_weights {
     float* gpart;      // partial regions of the extra dx groups (grow-only)
     size_t gpart_cap;
     bool applied;      // bp holds B' of the last apply
+    bool solver_owned; // owned by a ladmm_solve cache entry: nothing outside the solve
+                       // reads its guide copy
 };

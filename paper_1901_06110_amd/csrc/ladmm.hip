@@ -503,10 +503,20 @@ int enqueue_denoise_dual(const ladmm_params* p, int k, dsnlm_weights* w, float* 
         d.y = nullptr;
         if (!rc) rc = check_hip(launch_half(kNLM, p->S, p->P, d, nullptr, nullptr, 0, st), "plain NLM");
     } else if (k <= p->freeze_after) {
-        // adaptive weights: guide = the denoiser's own input z
-        rc = check_hip(hipMemcpyAsync(w->guide, z, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st),
-                       "copy guide");
-        d.z = w->guide;
+        // adaptive weights: guide = the denoiser's own input z.  On the half
+        // window only pass A's pad reads it (into the mirrored copy that the
+        // later sweeps and frozen applies use), so a solve's own handle takes z
+        // as it is; otherwise the handle keeps a copy (the full-window sweeps
+        // read the guide itself, and a caller's handle may be differentiated)
+        d.z = z;
+        const bool direct = w->solver_owned && sweep_takes_half(kPassA, p->S, p->P, d) &&
+                            sweep_takes_half(kPassBApply, p->S, p->P, d) && sweep_takes_half(kApply, p->S, p->P, d);
+        rc = DSNLM_OK;
+        if (!direct) {
+            rc = check_hip(hipMemcpyAsync(w->guide, z, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st),
+                           "copy guide");
+            d.z = w->guide;
+        }
         if (!rc) rc = check_hip(launch_sweep(kPassA, p->S, p->P, d, nullptr, nullptr, 0, st), "pass A");
         if (!rc) rc = check_hip(launch_sweep(kPassBApply, p->S, p->P, d, nullptr, nullptr, 0, st), "pass B");
     } else {
@@ -852,6 +862,7 @@ int solve_entry(const SolveKey& key, const ladmm_operator* op, const OpView& ov,
     iop.y = e->y;
     iop.ones = e->ones;
     rc = prepare_handle(op->n1, op->n2, p->S, p->P, h, &e->w);
+    if (!rc) e->w->solver_owned = true;
     float *lr, *partials, *xt;
     if (!rc) rc = ensure_solver_scratch(e->w, ov, op, key.want_res ? p->iters : 1, &lr, &partials, &xt);
     if (!rc && sr_step_fusable(op, ov.g)) {
