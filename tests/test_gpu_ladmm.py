@@ -201,6 +201,13 @@ def test_solve_one_launch_xstep_equals_two_launch_steps(n1, n2, iters):
         w = M.ladmm_step(op, prm, k, w, x2, v2, u2)
     torch.cuda.synchronize()
     assert torch.equal(x1, x2) and torch.equal(v1, v2) and torch.equal(u1, u2)
+    # the same solve with residuals (another cached graph): the same iterates
+    x3, v3, u3 = _t(x0), _t(x0), torch.zeros((n1, n2), device="cuda")
+    res = torch.zeros((iters, 2), device="cuda")
+    M.ladmm_solve(op, prm, x3, v3, u3, residuals=res)
+    torch.cuda.synchronize()
+    assert torch.equal(x1, x3) and torch.equal(v1, v3) and torch.equal(u1, u3)
+    assert bool(torch.isfinite(res).all())
 
 
 def test_frozen_weights_converge_to_fixed_point():
